@@ -1,0 +1,254 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP path.
+
+Two independent realisations of the same definitions:
+
+* ``liboracle.so`` (oracle.c): plain FP64 direct sums over a CSR adjacency or
+  hypergraph, libm, OpenMP over rows; classical RK4 / explicit Euler.
+* the ``dense_*`` functions below: NumPy brute force over a dense adjacency
+  matrix, for tiny N only.
+
+Definitions followed: eq. (2.1)/(2.2) (general network model), the phase
+model of Sec. 3 with the real difference Fourier series of App. A.2, the
+higher-order Kuramoto model of App. A.7 (on a hypergraph), and the
+Cucker-Smale model of App. A.6.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i64p = ctypes.c_void_p
+_vp = ctypes.c_void_p
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle: gcc -O2, no fast-math (libm sin/cos, IEEE FP64)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+                               "-shared", "-fPIC", "-std=c11", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        d, i32, i64, u64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        lib.oracle_phase_rhs.restype = None
+        lib.oracle_phase_rhs.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp, _vp,
+                                         _vp, _vp, i64, _vp]
+        lib.oracle_order_parameter.restype = d
+        lib.oracle_order_parameter.argtypes = [i64, _vp]
+        lib.oracle_phase_integrate.restype = ctypes.c_int
+        lib.oracle_phase_integrate.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp,
+                                               _vp, _vp, d, i64, ctypes.c_int, _vp]
+        lib.oracle_splitmix64.restype = u64
+        lib.oracle_splitmix64.argtypes = [u64]
+        lib.oracle_triple_present.restype = ctypes.c_int
+        lib.oracle_triple_present.argtypes = [u64, u64, i32, i32, i32]
+        lib.oracle_triple_threshold.restype = u64
+        lib.oracle_triple_threshold.argtypes = [d]
+        lib.oracle_triadic_rhs.restype = None
+        lib.oracle_triadic_rhs.argtypes = [i64, _vp, _vp, _vp, u64, d, i64, _vp, _vp, d, d, _vp, _vp,
+                                           i64, _vp]
+        lib.oracle_triadic_integrate.restype = ctypes.c_int
+        lib.oracle_triadic_integrate.argtypes = [i64, _vp, _vp, _vp, u64, d, i64, _vp, _vp, d, d, _vp,
+                                                 d, i64, ctypes.c_int, _vp]
+        lib.oracle_cs_rhs.restype = None
+        lib.oracle_cs_rhs.argtypes = [i64, ctypes.c_int, _vp, _vp, ctypes.c_int, d, d, d, _vp, _vp,
+                                      _vp, i64, _vp, _vp]
+        lib.oracle_cs_integrate.restype = ctypes.c_int
+        lib.oracle_cs_integrate.argtypes = [i64, ctypes.c_int, _vp, _vp, ctypes.c_int, d, d, d, _vp,
+                                            _vp, d, i64, ctypes.c_int]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _csr(row_ptr, col):
+    if row_ptr is None:
+        return None, None
+    return np.ascontiguousarray(row_ptr, dtype=np.int64), np.ascontiguousarray(col, dtype=np.int32)
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    _load().oracle_set_num_threads(int(t))
+
+
+# ---------------------------------------------------------------------------
+# phase model
+# ---------------------------------------------------------------------------
+
+def phase_rhs(n, row_ptr, col, omega, K, d_sin, d_cos, theta, rows=None, complete=False):
+    """H_m = omega_m + (K/N) sum_l a_ml h(theta_l - theta_m)  (eq. 2.2 with
+    f_m = omega_m; h as in App. A.2).  rows: optional int64 subset."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    d_sin, d_cos = _f64(d_sin), _f64(d_cos)
+    p = len(d_sin) - 1
+    assert len(d_cos) == p + 1
+    theta, omega = _f64(theta), _f64(omega)
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    out = np.empty(cnt, dtype=np.float64)
+    lib.oracle_phase_rhs(n, _p(rp), _p(cl), int(bool(complete)), _p(omega), float(K), p, _p(d_sin),
+                         _p(d_cos), _p(theta), _p(rws), 0 if rws is None else len(rws), _p(out))
+    return out
+
+
+def order_parameter(theta) -> float:
+    theta = _f64(theta)
+    return float(_load().oracle_order_parameter(len(theta), _p(theta)))
+
+
+def phase_integrate(n, row_ptr, col, omega, K, d_sin, d_cos, theta0, dt, steps,
+                    stepper="rk4", complete=False, trace=True):
+    """Returns (theta_final, r_trace or None).  No phase wrapping."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    d_sin, d_cos = _f64(d_sin), _f64(d_cos)
+    th = np.array(theta0, dtype=np.float64, copy=True)
+    r = np.empty(steps + 1, dtype=np.float64) if trace else None
+    rc = lib.oracle_phase_integrate(n, _p(rp), _p(cl), int(bool(complete)), _p(_f64(omega)), float(K),
+                                    len(d_sin) - 1, _p(d_sin), _p(d_cos), _p(th), float(dt), int(steps),
+                                    1 if stepper == "euler" else 0, _p(r))
+    if rc != 0:
+        raise MemoryError("oracle_phase_integrate")
+    return th, r
+
+
+# ---------------------------------------------------------------------------
+# triadic model
+# ---------------------------------------------------------------------------
+
+def splitmix64(x: int) -> int:
+    return int(_load().oracle_splitmix64(int(x) & 0xFFFFFFFFFFFFFFFF))
+
+
+def triple_threshold(p: float) -> int:
+    return int(_load().oracle_triple_threshold(float(p)))
+
+
+def triple_present(seed: int, p: float, a: int, b: int, c: int) -> bool:
+    lib = _load()
+    return bool(lib.oracle_triple_present(int(seed), lib.oracle_triple_threshold(float(p)), a, b, c))
+
+
+def triadic_rhs(n, row_ptr, col, labels, tri_seed, p_tri, tri, omega, K1, K2, theta, rows=None):
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    out = np.empty(cnt, dtype=np.float64)
+    lib.oracle_triadic_rhs(n, _p(rp), _p(cl), _p(labels), int(tri_seed), float(p_tri), len(tri),
+                           _p(tri), _p(_f64(omega)), float(K1), float(K2), _p(_f64(theta)), _p(rws),
+                           0 if rws is None else len(rws), _p(out))
+    return out
+
+
+def triadic_integrate(n, row_ptr, col, labels, tri_seed, p_tri, tri, omega, K1, K2, theta0, dt,
+                      steps, stepper="rk4", trace=True):
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    th = np.array(theta0, dtype=np.float64, copy=True)
+    r = np.empty(steps + 1, dtype=np.float64) if trace else None
+    rc = lib.oracle_triadic_integrate(n, _p(rp), _p(cl), _p(labels), int(tri_seed), float(p_tri),
+                                      len(tri), _p(tri), _p(_f64(omega)), float(K1), float(K2), _p(th),
+                                      float(dt), int(steps), 1 if stepper == "euler" else 0, _p(r))
+    if rc != 0:
+        raise MemoryError("oracle_triadic_integrate")
+    return th, r
+
+
+# ---------------------------------------------------------------------------
+# Cucker-Smale
+# ---------------------------------------------------------------------------
+
+def cs_rhs(n, row_ptr, col, K, sigma, beta, s, v, rows=None, complete=False):
+    """s, v: [dim, n].  Returns (sdot, vdot), each [dim, len(rows) or n]."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    dim = s.shape[0]
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    sd = np.empty((dim, cnt), dtype=np.float64)
+    vd = np.empty((dim, cnt), dtype=np.float64)
+    lib.oracle_cs_rhs(n, dim, _p(rp), _p(cl), int(bool(complete)), float(K), float(sigma), float(beta),
+                      _p(s), _p(v), _p(rws), 0 if rws is None else len(rws), _p(sd), _p(vd))
+    return sd, vd
+
+
+def cs_integrate(n, row_ptr, col, K, sigma, beta, s0, v0, dt, steps, stepper="rk4", complete=False):
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    s = np.array(s0, dtype=np.float64, copy=True)
+    v = np.array(v0, dtype=np.float64, copy=True)
+    rc = lib.oracle_cs_integrate(n, s.shape[0], _p(rp), _p(cl), int(bool(complete)), float(K),
+                                 float(sigma), float(beta), _p(s), _p(v), float(dt), int(steps),
+                                 1 if stepper == "euler" else 0)
+    if rc != 0:
+        raise MemoryError("oracle_cs_integrate")
+    return s, v
+
+
+# ---------------------------------------------------------------------------
+# NumPy brute force over a dense adjacency (tiny N)
+# ---------------------------------------------------------------------------
+
+def dense_from_csr(n, row_ptr, col) -> np.ndarray:
+    A = np.zeros((n, n), dtype=np.float64)
+    for m in range(n):
+        A[m, col[row_ptr[m]:row_ptr[m + 1]]] = 1.0
+    return A
+
+
+def dense_phase_rhs(A, omega, K, d_sin, d_cos, theta):
+    """Dense O(N^2) evaluation of eq. (2.2) for the phase model."""
+    n = A.shape[0]
+    diff = theta[None, :] - theta[:, None]          # diff[m, l] = theta_l - theta_m
+    h = np.full_like(diff, d_cos[0])
+    for k in range(1, len(d_sin)):
+        h += d_sin[k] * np.sin(k * diff) + d_cos[k] * np.cos(k * diff)
+    return omega + (K / n) * (A * h).sum(axis=1)
+
+
+def dense_cs_rhs(A, K, sigma, beta, s, v):
+    n = A.shape[0]
+    ds = s[:, None, :] - s[:, :, None]               # ds[d, m, l] = s_l - s_m
+    w = K / (sigma ** 2 + (ds ** 2).sum(axis=0)) ** beta
+    dv = v[:, None, :] - v[:, :, None]
+    return v.copy(), (A[None] * w[None] * dv).sum(axis=2) / n
