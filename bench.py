@@ -1,0 +1,175 @@
+"""Benchmark of the CIA right-hand side inside RK4 on one MI355X.
+
+Workload: Kuramoto on the N = 1e6 planted power-law community graph
+(sizes ~ s^-2 on [100, 5000], p_in 0.95, mean inter degree 5, Cauchy(0, 0.5)
+frequencies, K = 3, RK4 dt 0.01), synthetic and seeded.
+
+One bench step = one RK4 step = four RHS evaluations (E1 + E2 + combine),
+fused with the stage updates, plus the FP64 order parameter r(t).
+value = N * 4 * steps / seconds (RHS node-updates per second).  The direct
+O(|E|) method is timed the same way on the same data; the FP64 CPU oracle
+is timed on a bounded sample.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True):
+    import numpy as np
+    th = torch.as_tensor(theta0, dtype=torch.float32, device="cuda")
+    if warmup:
+        plan.integrate(th, dt, warmup, np.zeros(warmup + 1) if with_r else None)
+    torch.cuda.synchronize()
+    th = torch.as_tensor(theta0, dtype=torch.float32, device="cuda")
+    r = np.zeros(steps + 1) if with_r else None
+    stream = torch.cuda.current_stream()
+    plan.timing(reset=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    plan.integrate(th, dt, steps, r, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    t = plan.timing(reset=True)
+    return ms, t, r
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="large", choices=["large", "small"])
+    ap.add_argument("--direct-steps", type=int, default=100,
+                    help="RK4 steps timed for the direct method")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
+    ap.add_argument("--unit-work", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(communities would shard across GPUs with one halo exchange of z per RK stage)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2203_16657_amd as cia
+    import workloads as W
+
+    if not os.path.exists(cia.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    cia.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    t0 = time.time()
+    P = W.kuramoto_large() if args.workload == "large" else W.kuramoto_small()
+    g = P.graph
+    log("workload %s: n=%d nnz=%d communities=%d (%.1fs)" % (P.name, g.n, g.nnz, g.ncomm, time.time() - t0))
+
+    flags = 0 if args.no_timing else cia.CIA_FLAG_TIMING
+    t0 = time.time()
+    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, flags=flags,
+                          unit_work=args.unit_work, block=args.block)
+    info = plan.info()
+    log("cia plan: units=%d ncomm=%d nnz_neg=%d nnz_pos=%d unassigned=%d bytes/stage=%.3e (%.1fs)" % (
+        info.nunits, info.ncomm, info.nnz_neg, info.nnz_pos, info.n_unassigned, info.bytes_per_stage,
+        time.time() - t0))
+    ms, tim, r = time_integrate(plan, torch, P.theta0, P.dt, args.steps, args.warmup)
+    n = g.n
+    rhs_per_step = 4
+    value = n * rhs_per_step * args.steps / (ms / 1e3)
+    log("cia: %.3f ms/step, %.3e RHS node-updates/s" % (ms / args.steps, value))
+    stage_avg_ms = tim.stage_ms / max(tim.stage_launches, 1) if tim.stage_launches else None
+    roof = None
+    if stage_avg_ms:
+        achieved = info.bytes_per_stage / (stage_avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "phase_stage_kernel", "avg_launch_us": round(stage_avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": info.bytes_per_stage}
+        log("stage kernel avg %.2f us, %.1f GB/s algorithmic (%.1f%% of 8 TB/s)" % (
+            stage_avg_ms * 1e3, achieved, 100 * achieved / HBM_PEAK_GBS))
+    plan.close()
+
+    # direct method, same data layout and stepper
+    t0 = time.time()
+    dplan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, flags=flags,
+                           method=cia.CIA_METHOD_DIRECT)
+    dinfo = dplan.info()
+    log("direct plan: units=%d nnz=%d (%.1fs)" % (dinfo.nunits, dinfo.nnz_pos, time.time() - t0))
+    dsteps = min(args.direct_steps, args.steps)
+    dms, dtim, _ = time_integrate(dplan, torch, P.theta0, P.dt, dsteps, min(args.warmup, 5))
+    dvalue = n * rhs_per_step * dsteps / (dms / 1e3)
+    d_stage_ms = dtim.stage_ms / max(dtim.stage_launches, 1) if dtim.stage_launches else None
+    log("direct: %.3f ms/step, %.3e RHS node-updates/s" % (dms / dsteps, dvalue))
+    direct = {"value": dvalue, "ms_per_step": dms / dsteps, "steps": dsteps}
+    if d_stage_ms:
+        dach = dinfo.bytes_per_stage / (d_stage_ms / 1e3) / 1e9
+        direct.update(avg_launch_us=round(d_stage_ms * 1e3, 2), achieved_gbs=round(dach, 1),
+                      frac=round(dach / HBM_PEAK_GBS, 4))
+    dplan.close()
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        th = P.theta0.astype(np.float64)
+        csteps = 1 if args.workload == "large" else 20
+        t0 = time.time()
+        oracle.phase_integrate(g.n, g.row_ptr, g.col, P.omega, P.K, [0, 1], [0, 0], th, P.dt, csteps,
+                               trace=False)
+        ct = time.time() - t0
+        cpu = {"value": n * rhs_per_step * csteps / ct, "unit": "RHS node-updates/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "%d FP64 RK4 step(s) (%d RHS evaluations) of the full workload, %.1f s" % (
+                   csteps, rhs_per_step * csteps, ct)}
+        log("cpu oracle: %.3e RHS node-updates/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    res = {
+        "metric": "RHS node-updates/s, CIA vs direct, 1 MI355X, N=1e6, <=1e-5 rel err vs FP64",
+        "value": value,
+        "unit": "RHS node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": P.name, "n": n, "communities": info.ncomm, "nnz_graph": info.nnz_graph,
+                   "nnz_neg": info.nnz_neg, "nnz_pos": info.nnz_pos, "stepper": "rk4", "dt": P.dt,
+                   "rhs_per_step": rhs_per_step, "parallelism": "single-gpu"},
+        "direct": direct,
+        "speedup_vs_direct": value / dvalue,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "r_final": float(r[-1]) if r is not None else None,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,283 @@
+/*
+ * cia.h -- C ABI of the community integration algorithm (CIA) library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the right-hand side of network ODEs
+ *     x_m' = f_m(x_m) + (1/N) sum_l a_ml g(x_l, x_m)            (eq. 2.1/2.2)
+ * in O(N + nnz S) instead of O(|E|), following the four steps of Sec. 3:
+ * (P1) permute nodes so communities are contiguous and split the permuted
+ * adjacency B = D + S into exact blocks D and a sparse remainder S with
+ * entries in {-1,+1}; (P2) expand the coupling in a separable basis;
+ * (E1) per-community observables (sums of basis functions) broadcast to every
+ * member; (E2) direct summation over S.  A direct O(|E|) method over the
+ * same data layout is kept as the baseline.
+ *
+ * Conventions for every call:
+ *  - The return value is a cia_status: CIA_OK (0) or a negative error code.
+ *    No C++ exception crosses this boundary.  cia_last_error() returns a
+ *    thread-local message describing the last failure of the calling thread.
+ *  - Host input pointers are borrowed for the duration of the call only; the
+ *    plan copies what it needs.
+ *  - Device pointers (state, dstate) are caller-owned HIP device memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work and return; a kernel fault surfaces as CIA_EHIP from a later call
+ *    or from the caller's own synchronisation.  cia_integrate with a
+ *    non-NULL r_trace synchronises the stream before returning.
+ *  - A plan is not thread-safe; distinct plans are independent.
+ *  - State layout is SoA in the caller's (user) node order: phase models use
+ *    one plane of N values; the flock model uses six planes
+ *    (s_x, s_y, s_z, v_x, v_y, v_z), each of N values.  Element type is float
+ *    for CIA_F32 plans and double for CIA_F64 plans.
+ */
+#ifndef CIA_H
+#define CIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cia_plan cia_plan;
+
+typedef enum cia_status {
+    CIA_OK = 0,
+    CIA_EINVAL = -1,        /* invalid argument or malformed graph */
+    CIA_ENOMEM = -2,        /* host or device allocation failed */
+    CIA_EHIP = -3,          /* a HIP runtime call failed */
+    CIA_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+    CIA_ENONFINITE = -5     /* the integrated state contains NaN or Inf */
+} cia_status;
+
+/* graph kinds */
+#define CIA_GRAPH_CSR 0       /* explicit symmetric adjacency in CSR form */
+#define CIA_GRAPH_COMPLETE 1  /* all-to-all: a_ml = 1 for l != m; nothing stored */
+
+/* models */
+#define CIA_MODEL_PHASE 0    /* theta_m' = omega_m + (K/N) sum_l a_ml h(theta_l - theta_m),
+                                h(x) = d_cos[0] + sum_{k=1..p} d_sin[k] sin(kx) + d_cos[k] cos(kx)
+                                (Sec. 3; real difference series of App. A.2; Kuramoto App. A.4) */
+#define CIA_MODEL_TRIADIC 1  /* phase model with h = sin plus the higher-order term
+                                (K2/N^2) sum_{(j,k) ordered} B_mjk sin(theta_j + theta_k - 2 theta_m)
+                                (App. A.7 with lambda = (1,1,-2), on a hypergraph) */
+#define CIA_MODEL_FLOCK 2    /* Cucker-Smale in 3-D (App. A.6): s_m' = v_m,
+                                v_m' = (1/N) sum_l a_ml w(|s_l - s_m|) (v_l - v_m),
+                                w(r) = cs_K / (cs_sigma^2 + r^2)^cs_beta */
+
+/* methods */
+#define CIA_METHOD_CIA 0     /* E1 + E2 (community observables + sparse remainder) */
+#define CIA_METHOD_DIRECT 1  /* direct O(|E|) summation (all-to-all: O(N^2)) */
+
+/* arithmetic of state and kernels */
+#define CIA_F32 0
+#define CIA_F64 1
+
+/* time steppers (Sec. 3: any explicit scheme needs >= 1 RHS per step) */
+#define CIA_RK4 0            /* classical four-stage Runge-Kutta */
+#define CIA_EULER 1          /* explicit Euler (the setting of Sec. 4's timing runs) */
+
+/* separable basis of the flock weight on intra-community pairs */
+#define CIA_BASIS_EXACT 0    /* no expansion: intra blocks summed directly */
+#define CIA_BASIS_FOURIER 1  /* truncated 3-D Fourier series on [-L, L]^3 (App. A.6) */
+#define CIA_BASIS_LEARNED 2  /* learned rank-R separable basis, checked per community
+                                against the exact weight (judge) with exact fallback */
+
+/* option flags */
+#define CIA_FLAG_KEEP_LABELS 0x1u  /* skip the P1 cost rule (App. A.1): every labelled
+                                      community is treated as a dense block */
+#define CIA_FLAG_TIMING 0x2u       /* record HIP events around every kernel launch;
+                                      read them with cia_plan_get_timing */
+#define CIA_FLAG_NO_VALIDATE 0x4u  /* skip the symmetry / sortedness checks of cia_build */
+#define CIA_FLAG_HIPGRAPH 0x8u     /* replay the RK step loop from a captured HIP graph */
+/* kernel-path overrides, for testing and tuning (results stay within tolerance) */
+#define CIA_FLAG_FORCE_WIDE 0x100u  /* FP64 observables/combine for every community */
+#define CIA_FLAG_FORCE_NEG32 0x200u /* S-neg as int32 positions for every community */
+#define CIA_FLAG_NO_LDS 0x400u      /* no LDS staging of community z values */
+
+typedef struct cia_graph {
+    int64_t n;                 /* number of nodes N >= 1 */
+    int32_t kind;              /* CIA_GRAPH_CSR or CIA_GRAPH_COMPLETE */
+    int32_t reserved;
+    const int64_t *row_ptr;    /* host [n+1]; CSR only */
+    const int32_t *col;        /* host [row_ptr[n]]; symmetric, rows strictly increasing,
+                                  no self-loops; CSR only */
+} cia_graph;
+
+/* Hypergraph of the triadic model.  A triple of distinct nodes inside one
+   community is a hyperedge iff splitmix64(seed ^ key) < floor(p_intra * 2^64),
+   key = a | b << 21 | c << 42 for the sorted user ids a < b < c (N < 2^21);
+   every other hyperedge is listed explicitly in `tri`. */
+typedef struct cia_hypergraph {
+    uint64_t seed;
+    double p_intra;            /* in [0, 1] */
+    int64_t ntri;
+    const int32_t *tri;        /* host [ntri][3]; distinct ids, not all in one community */
+} cia_hypergraph;
+
+typedef struct cia_coupling {
+    int32_t model;             /* CIA_MODEL_* */
+    int32_t p;                 /* phase: Fourier order of h, 1..8; flock Fourier: modes per axis */
+    const double *d_sin;       /* host [p+1]; entry 0 ignored (phase model) */
+    const double *d_cos;       /* host [p+1]; entry 0 = constant term d_0 (phase model) */
+    double K;                  /* pairwise strength; the library applies K/N, N = graph n */
+    double K2;                 /* triadic strength; the library applies K2/N^2 */
+    const cia_hypergraph *hyper;   /* triadic model only */
+    double cs_K, cs_sigma, cs_beta;/* flock weight parameters */
+    double cs_L;               /* flock Fourier half-period L (positions must stay in a
+                                  cube of side L so all differences lie in [-L, L]) */
+    int32_t cs_basis;          /* CIA_BASIS_* */
+    int32_t rank;              /* learned basis rank R, 1..64 */
+    int32_t train_iters;       /* learned basis: optimiser steps at build time (0 = default) */
+    int32_t reserved;
+} cia_coupling;
+
+typedef struct cia_options {
+    int32_t method;            /* CIA_METHOD_* */
+    int32_t precision;         /* CIA_F32 or CIA_F64 */
+    int32_t stepper;           /* CIA_RK4 or CIA_EULER */
+    uint32_t flags;            /* CIA_FLAG_* */
+    double dense_alpha;        /* P1 cost rule: keep community c dense iff
+                                  nnz(S-neg_c) + dense_alpha * lambda_c < nnz(intra_c) */
+    int32_t unit_work;         /* target remainder entries per work unit (0 = default) */
+    int32_t block;             /* threads per block of the stage kernels, 256 or 512 (0 = default) */
+    double judge_tol;          /* learned basis: max relative weight error per community */
+    int32_t device;            /* HIP device ordinal, -1 = the current device */
+    int32_t reserved;
+} cia_options;
+
+/* Fill defaults: CIA method, F32, RK4, no flags, dense_alpha 2, judge_tol 1e-3. */
+void cia_options_default(cia_options *o);
+/* Fill defaults: phase model, p = 1, h = sin (d_sin = {0,1}, d_cos = {0,0}), K = 1. */
+void cia_coupling_default(cia_coupling *c);
+
+/*
+ * cia_build -- pre-simulation steps P1 and P2 (Sec. 3.1, App. A.1).
+ *  g       : the network (host).  CSR graphs are validated (symmetric, sorted,
+ *            no self-loops or duplicates) unless CIA_FLAG_NO_VALIDATE.
+ *  labels  : host [n] community of every node, -1 = no community (Sec. 3.1
+ *            allows nodes outside every community); NULL = all nodes form one
+ *            community.  Ids need not be dense.  Communities that fail the
+ *            cost rule (see cia_options.dense_alpha) are dissolved into -1.
+ *  c       : coupling (model, Fourier coefficients, strengths).
+ *  omega   : host [n] intrinsic frequencies f_m = omega_m of the phase models;
+ *            NULL = all zero.  Ignored by the flock model.
+ *  o       : options; NULL = defaults.
+ *  out     : receives the plan, owned by the caller until cia_destroy.
+ * Errors: CIA_EINVAL (bad argument, malformed graph, label out of range),
+ * CIA_ENOMEM, CIA_EHIP (no device or a HIP call failed), CIA_EUNSUPPORTED.
+ * On error *out is set to NULL and nothing leaks.
+ */
+cia_status cia_build(const cia_graph *g, const int32_t *labels, const cia_coupling *c,
+                     const double *omega, const cia_options *o, cia_plan **out);
+
+/*
+ * cia_rhs -- one evaluation H(state) (steps E1 and E2 of Sec. 3.2 for the CIA
+ * method; the plain sum of eq. 2.2 for the direct method).
+ *  state  : device, user order, read only.
+ *  dstate : device, user order, written (must not alias state).
+ */
+cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream);
+
+/*
+ * cia_integrate -- `steps` steps of the plan's stepper with step size dt,
+ * every stage evaluated as in cia_rhs.
+ *  state   : device, user order, updated in place.  Phase states are returned
+ *            wrapped into [0, 2 pi).
+ *  r_trace : optional host [steps+1]; receives the global order parameter
+ *            r(t_n) = |(1/N) sum_m exp(i theta_m)| (App. A.4) accumulated in
+ *            FP64 (phase models only; NULL = not computed).  When non-NULL the
+ *            call synchronises the stream and returns CIA_ENONFINITE if the
+ *            final state holds a NaN or an Inf.
+ */
+cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
+                         void *stream);
+
+/* Release every host and device resource of the plan (NULL is a no-op). */
+cia_status cia_destroy(cia_plan *p);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char *cia_last_error(void);
+
+/* --------------------------------------------------------------------- */
+/* Introspection                                                          */
+/* --------------------------------------------------------------------- */
+
+typedef struct cia_plan_info {
+    int64_t n;
+    int64_t nnz_graph;        /* directed entries of A (CSR) */
+    int64_t nnz_neg;          /* S entries -1: missing intra-community links */
+    int64_t nnz_pos;          /* S entries +1: links leaving a community (or touching
+                                 a node of no community) */
+    int64_t n_unassigned;     /* nodes outside every dense community after P1 */
+    int32_t ncomm;            /* dense communities kept by P1 */
+    int32_t nunits;           /* work units of the stage kernels */
+    int32_t max_comm;         /* largest community */
+    int32_t wide_comms;       /* communities above 1e5 nodes (FP64 observables) */
+    int32_t method, precision, model, p;
+    double bytes_per_rhs;     /* algorithmic HBM bytes of one RHS evaluation */
+    double bytes_per_stage;   /* algorithmic HBM bytes of one fused RK stage launch */
+    int64_t nnz_extra;        /* model-specific remainder entries (triadic pair lists) */
+    int32_t judge_fallbacks;  /* learned basis: communities currently on exact fallback */
+    int32_t reserved;
+} cia_plan_info;
+
+cia_status cia_plan_get_info(const cia_plan *p, cia_plan_info *info);
+
+/* Accumulated kernel time of a plan built with CIA_FLAG_TIMING (milliseconds,
+   from HIP events on the stream the kernels ran on).  Synchronises the
+   stream of the last call.  reset != 0 clears the accumulators. */
+typedef struct cia_timing {
+    double stage_ms;          /* fused E1/E2/combine/stage-update kernels */
+    int64_t stage_launches;
+    double prep_ms;           /* permute-in + first observables */
+    int64_t prep_launches;
+    double aux_ms;            /* order parameter, permute-out, other */
+    int64_t aux_launches;
+} cia_timing;
+
+cia_status cia_plan_get_timing(cia_plan *p, cia_timing *t, int reset);
+
+/* --------------------------------------------------------------------- */
+/* Host-only helpers (no device needed)                                   */
+/* --------------------------------------------------------------------- */
+
+/*
+ * P2 for a sampled coupling (Sec. 3.1, App. A.2): real Fourier coefficients
+ * of h from m >= 2p+1 samples h(2 pi j / m), j = 0..m-1, so that
+ * h(x) ~ d_cos[0] + sum_{k=1..p} d_sin[k] sin(kx) + d_cos[k] cos(kx).
+ * d_sin, d_cos: host [p+1] outputs (d_sin[0] = 0).
+ */
+cia_status cia_fourier_coeffs(const double *samples, int64_t m, int32_t p, double *d_sin,
+                              double *d_cos);
+
+/*
+ * P1 alone, on the host (Sec. 3.1 / App. A.1), for inspection and tests.
+ * cia_p1_build runs validation, the cost rule, the permutation and the
+ * construction of S exactly as cia_build does.
+ * cia_p1_sizes writes {n, ncomm, nnz_neg, nnz_pos, n_unassigned, nnz_graph}.
+ * cia_p1_export fills caller buffers (any may be NULL):
+ *   perm     [n]        user id of the node at community-order position i
+ *   comm_off [ncomm+1]  community c occupies positions [comm_off[c], comm_off[c+1])
+ *   negptr   [n+1], neg [nnz_neg]  missing intra partners of position i, as
+ *                                  community-order positions, increasing
+ *   posptr   [n+1], pos [nnz_pos]  remaining (+1) partners, positions, increasing
+ */
+typedef struct cia_p1 cia_p1;
+cia_status cia_p1_build(const cia_graph *g, const int32_t *labels, const cia_options *o,
+                        cia_p1 **out);
+cia_status cia_p1_sizes(const cia_p1 *p1, int64_t sizes[6]);
+cia_status cia_p1_export(const cia_p1 *p1, int32_t *perm, int32_t *comm_off, int64_t *negptr,
+                         int32_t *neg, int64_t *posptr, int32_t *pos);
+cia_status cia_p1_free(cia_p1 *p1);
+
+/* sizeof of an ABI struct by its name ("cia_graph", "cia_hypergraph",
+   "cia_coupling", "cia_options", "cia_plan_info", "cia_timing"); 0 if unknown.
+   Lets bindings check their struct layouts. */
+size_t cia_abi_sizeof(const char *name);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CIA_H */

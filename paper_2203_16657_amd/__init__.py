@@ -1,0 +1,329 @@
+"""Python binding of libcia (the C ABI in include/cia.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libcia.so.  Functions carry the C names (cia_build, cia_rhs,
+cia_integrate, cia_destroy, ...); `Plan` is a small convenience wrapper.
+Device memory and streams come from PyTorch tensors (data_ptr / cuda_stream).
+
+The library must be built (``python -m paper_2203_16657_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcia.so")
+
+# ---- constants (mirror of cia.h) ----
+CIA_OK, CIA_EINVAL, CIA_ENOMEM, CIA_EHIP, CIA_EUNSUPPORTED, CIA_ENONFINITE = 0, -1, -2, -3, -4, -5
+CIA_GRAPH_CSR, CIA_GRAPH_COMPLETE = 0, 1
+CIA_MODEL_PHASE, CIA_MODEL_TRIADIC, CIA_MODEL_FLOCK = 0, 1, 2
+CIA_METHOD_CIA, CIA_METHOD_DIRECT = 0, 1
+CIA_F32, CIA_F64 = 0, 1
+CIA_RK4, CIA_EULER = 0, 1
+CIA_BASIS_EXACT, CIA_BASIS_FOURIER, CIA_BASIS_LEARNED = 0, 1, 2
+CIA_FLAG_KEEP_LABELS, CIA_FLAG_TIMING, CIA_FLAG_NO_VALIDATE, CIA_FLAG_HIPGRAPH = 0x1, 0x2, 0x4, 0x8
+CIA_FLAG_FORCE_WIDE, CIA_FLAG_FORCE_NEG32, CIA_FLAG_NO_LDS = 0x100, 0x200, 0x400
+
+_c = ctypes
+_vp = ctypes.c_void_p
+
+
+class cia_graph(_c.Structure):
+    _fields_ = [("n", _c.c_int64), ("kind", _c.c_int32), ("reserved", _c.c_int32),
+                ("row_ptr", _vp), ("col", _vp)]
+
+
+class cia_hypergraph(_c.Structure):
+    _fields_ = [("seed", _c.c_uint64), ("p_intra", _c.c_double), ("ntri", _c.c_int64), ("tri", _vp)]
+
+
+class cia_coupling(_c.Structure):
+    _fields_ = [("model", _c.c_int32), ("p", _c.c_int32), ("d_sin", _vp), ("d_cos", _vp),
+                ("K", _c.c_double), ("K2", _c.c_double), ("hyper", _vp),
+                ("cs_K", _c.c_double), ("cs_sigma", _c.c_double), ("cs_beta", _c.c_double),
+                ("cs_L", _c.c_double), ("cs_basis", _c.c_int32), ("rank", _c.c_int32),
+                ("train_iters", _c.c_int32), ("reserved", _c.c_int32)]
+
+
+class cia_options(_c.Structure):
+    _fields_ = [("method", _c.c_int32), ("precision", _c.c_int32), ("stepper", _c.c_int32),
+                ("flags", _c.c_uint32), ("dense_alpha", _c.c_double), ("unit_work", _c.c_int32),
+                ("block", _c.c_int32), ("judge_tol", _c.c_double), ("device", _c.c_int32),
+                ("reserved", _c.c_int32)]
+
+
+class cia_plan_info(_c.Structure):
+    _fields_ = [("n", _c.c_int64), ("nnz_graph", _c.c_int64), ("nnz_neg", _c.c_int64),
+                ("nnz_pos", _c.c_int64), ("n_unassigned", _c.c_int64), ("ncomm", _c.c_int32),
+                ("nunits", _c.c_int32), ("max_comm", _c.c_int32), ("wide_comms", _c.c_int32),
+                ("method", _c.c_int32), ("precision", _c.c_int32), ("model", _c.c_int32),
+                ("p", _c.c_int32), ("bytes_per_rhs", _c.c_double), ("bytes_per_stage", _c.c_double),
+                ("nnz_extra", _c.c_int64), ("judge_fallbacks", _c.c_int32), ("reserved", _c.c_int32)]
+
+
+class cia_timing(_c.Structure):
+    _fields_ = [("stage_ms", _c.c_double), ("stage_launches", _c.c_int64), ("prep_ms", _c.c_double),
+                ("prep_launches", _c.c_int64), ("aux_ms", _c.c_double), ("aux_launches", _c.c_int64)]
+
+
+EXPORTS = ["cia_build", "cia_rhs", "cia_integrate", "cia_destroy", "cia_last_error",
+           "cia_options_default", "cia_coupling_default", "cia_plan_get_info", "cia_plan_get_timing",
+           "cia_fourier_coeffs", "cia_p1_build", "cia_p1_sizes", "cia_p1_export", "cia_p1_free",
+           "cia_abi_sizeof"]
+
+_lib = None
+
+
+class CIAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("cia status %d: %s" % (status, msg))
+        self.status = status
+
+
+def load():
+    """Load libcia.so (no fallback: the HIP library is the only implementation)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcia.so is not built (%s); run paper_2203_16657_amd/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = _c.POINTER
+    lib.cia_build.restype = _c.c_int
+    lib.cia_build.argtypes = [P(cia_graph), _vp, P(cia_coupling), _vp, P(cia_options), P(_vp)]
+    lib.cia_rhs.restype = _c.c_int
+    lib.cia_rhs.argtypes = [_vp, _vp, _vp, _vp]
+    lib.cia_integrate.restype = _c.c_int
+    lib.cia_integrate.argtypes = [_vp, _vp, _c.c_double, _c.c_int64, _vp, _vp]
+    lib.cia_destroy.restype = _c.c_int
+    lib.cia_destroy.argtypes = [_vp]
+    lib.cia_last_error.restype = _c.c_char_p
+    lib.cia_last_error.argtypes = []
+    lib.cia_options_default.restype = None
+    lib.cia_options_default.argtypes = [P(cia_options)]
+    lib.cia_coupling_default.restype = None
+    lib.cia_coupling_default.argtypes = [P(cia_coupling)]
+    lib.cia_plan_get_info.restype = _c.c_int
+    lib.cia_plan_get_info.argtypes = [_vp, P(cia_plan_info)]
+    lib.cia_plan_get_timing.restype = _c.c_int
+    lib.cia_plan_get_timing.argtypes = [_vp, P(cia_timing), _c.c_int]
+    lib.cia_fourier_coeffs.restype = _c.c_int
+    lib.cia_fourier_coeffs.argtypes = [_vp, _c.c_int64, _c.c_int32, _vp, _vp]
+    lib.cia_p1_build.restype = _c.c_int
+    lib.cia_p1_build.argtypes = [P(cia_graph), _vp, P(cia_options), P(_vp)]
+    lib.cia_p1_sizes.restype = _c.c_int
+    lib.cia_p1_sizes.argtypes = [_vp, _vp]
+    lib.cia_p1_export.restype = _c.c_int
+    lib.cia_p1_export.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.cia_p1_free.restype = _c.c_int
+    lib.cia_p1_free.argtypes = [_vp]
+    lib.cia_abi_sizeof.restype = _c.c_size_t
+    lib.cia_abi_sizeof.argtypes = [_c.c_char_p]
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != CIA_OK:
+        raise CIAError(st, cia_last_error())
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(_vp)
+
+
+def _dev_ptr(t):
+    """Device pointer of a tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# the C functions, one to one
+# ---------------------------------------------------------------------------
+
+def cia_last_error() -> str:
+    return load().cia_last_error().decode(errors="replace")
+
+
+def cia_options_default() -> cia_options:
+    o = cia_options()
+    load().cia_options_default(_c.byref(o))
+    return o
+
+
+def cia_coupling_default() -> cia_coupling:
+    c = cia_coupling()
+    load().cia_coupling_default(_c.byref(c))
+    return c
+
+
+def cia_build(graph: cia_graph, labels, coupling: cia_coupling, omega, options: cia_options | None):
+    """Returns the plan handle (int).  labels/omega: numpy arrays or None.
+    The caller keeps the arrays referenced by `graph` / `coupling` alive for
+    the duration of the call."""
+    lib = load()
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
+    out = _vp()
+    st = lib.cia_build(_c.byref(graph), _np_ptr(lab), _c.byref(coupling), _np_ptr(om),
+                       None if options is None else _c.byref(options), _c.byref(out))
+    _check(st)
+    return out.value
+
+
+def cia_rhs(plan, state, dstate, stream=None) -> None:
+    _check(load().cia_rhs(plan, _dev_ptr(state), _dev_ptr(dstate), _stream_ptr(stream)))
+
+
+def cia_integrate(plan, state, dt: float, steps: int, r_trace=None, stream=None) -> None:
+    rt = None
+    if r_trace is not None:
+        assert r_trace.dtype == np.float64 and r_trace.flags.c_contiguous and len(r_trace) >= steps + 1
+        rt = _np_ptr(r_trace)
+    _check(load().cia_integrate(plan, _dev_ptr(state), float(dt), int(steps), rt, _stream_ptr(stream)))
+
+
+def cia_destroy(plan) -> None:
+    if plan:
+        _check(load().cia_destroy(plan))
+
+
+def cia_plan_get_info(plan) -> cia_plan_info:
+    info = cia_plan_info()
+    _check(load().cia_plan_get_info(plan, _c.byref(info)))
+    return info
+
+
+def cia_plan_get_timing(plan, reset: bool = False) -> cia_timing:
+    t = cia_timing()
+    _check(load().cia_plan_get_timing(plan, _c.byref(t), int(bool(reset))))
+    return t
+
+
+def cia_fourier_coeffs(samples, p: int):
+    s = np.ascontiguousarray(samples, dtype=np.float64)
+    ds = np.zeros(p + 1)
+    dc = np.zeros(p + 1)
+    _check(load().cia_fourier_coeffs(_np_ptr(s), len(s), int(p), _np_ptr(ds), _np_ptr(dc)))
+    return ds, dc
+
+
+def cia_abi_sizeof(name: str) -> int:
+    return int(load().cia_abi_sizeof(name.encode()))
+
+
+def cia_p1(n, row_ptr, col, labels=None, options=None, complete=False):
+    """Run P1 on the host and return a dict of numpy arrays (perm, comm_off,
+    negptr, neg, posptr, pos) plus the sizes."""
+    lib = load()
+    rp = None if complete else np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = None if complete else np.ascontiguousarray(col, dtype=np.int32)
+    g = cia_graph(n=n, kind=CIA_GRAPH_COMPLETE if complete else CIA_GRAPH_CSR, reserved=0,
+                  row_ptr=_np_ptr(rp), col=_np_ptr(cl))
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
+    h = _vp()
+    _check(lib.cia_p1_build(_c.byref(g), _np_ptr(lab), None if options is None else _c.byref(options),
+                            _c.byref(h)))
+    try:
+        sz = np.zeros(6, dtype=np.int64)
+        _check(lib.cia_p1_sizes(h, _np_ptr(sz)))
+        n_, ncomm, nneg, npos, nun, nnz = (int(x) for x in sz)
+        out = dict(perm=np.empty(n_, np.int32), comm_off=np.empty(ncomm + 1, np.int32),
+                   negptr=np.zeros(n_ + 1, np.int64), neg=np.empty(max(nneg, 1), np.int32),
+                   posptr=np.zeros(n_ + 1, np.int64), pos=np.empty(max(npos, 1), np.int32))
+        _check(lib.cia_p1_export(h, *[_np_ptr(out[k]) for k in
+                                      ("perm", "comm_off", "negptr", "neg", "posptr", "pos")]))
+        out["neg"] = out["neg"][:nneg]
+        out["pos"] = out["pos"][:npos]
+        out.update(n=n_, ncomm=ncomm, nnz_neg=nneg, nnz_pos=npos, n_unassigned=nun, nnz_graph=nnz)
+        return out
+    finally:
+        lib.cia_p1_free(h)
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+class Plan:
+    """Owns a cia_plan.  Build with Plan.phase(...) (more models below)."""
+
+    def __init__(self, handle, n, precision, model, dim=1):
+        self.handle = handle
+        self.n = n
+        self.precision = precision
+        self.model = model
+        self.dim = dim
+
+    @classmethod
+    def phase(cls, n, row_ptr=None, col=None, labels=None, omega=None, K=1.0, d_sin=(0.0, 1.0),
+              d_cos=(0.0, 0.0), method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4,
+              flags=0, complete=False, unit_work=0, block=0, dense_alpha=2.0, device=-1):
+        load()
+        rp = None if complete else np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = None if complete else np.ascontiguousarray(col, dtype=np.int32)
+        g = cia_graph(n=int(n), kind=CIA_GRAPH_COMPLETE if complete else CIA_GRAPH_CSR, reserved=0,
+                      row_ptr=_np_ptr(rp), col=_np_ptr(cl))
+        ds = np.ascontiguousarray(d_sin, dtype=np.float64)
+        dc = np.ascontiguousarray(d_cos, dtype=np.float64)
+        c = cia_coupling_default()
+        c.model = CIA_MODEL_PHASE
+        c.p = len(ds) - 1
+        c.d_sin = _np_ptr(ds)
+        c.d_cos = _np_ptr(dc)
+        c.K = float(K)
+        o = cia_options_default()
+        o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
+        o.unit_work, o.block, o.dense_alpha, o.device = unit_work, block, dense_alpha, device
+        h = cia_build(g, labels, c, omega, o)
+        return cls(h, int(n), precision, CIA_MODEL_PHASE)
+
+    @property
+    def dtype_np(self):
+        return np.float64 if self.precision == CIA_F64 else np.float32
+
+    def rhs(self, state, dstate, stream=None):
+        cia_rhs(self.handle, state, dstate, stream)
+
+    def integrate(self, state, dt, steps, r_trace=None, stream=None):
+        cia_integrate(self.handle, state, dt, steps, r_trace, stream)
+
+    def info(self) -> cia_plan_info:
+        return cia_plan_get_info(self.handle)
+
+    def timing(self, reset=False) -> cia_timing:
+        return cia_plan_get_timing(self.handle, reset)
+
+    def close(self):
+        if self.handle:
+            cia_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,204 @@
+// The C ABI of libcia: argument checks, device selection, dispatch to the
+// model implementations, kernel timing and plan introspection.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "plan.h"
+
+namespace cia {
+
+cia_status timing_begin(cia_plan *p, hipStream_t s, int kind) {
+    if (!(p->flags & CIA_FLAG_TIMING)) return CIA_OK;
+    if (p->ev_used == p->events.size()) {
+        cia_plan::EvPair e;
+        CIA_HIP(hipEventCreate(&e.a));
+        CIA_HIP(hipEventCreate(&e.b));
+        e.kind = kind;
+        p->events.push_back(e);
+    }
+    auto &e = p->events[p->ev_used];
+    e.kind = kind;
+    CIA_HIP(hipEventRecord(e.a, s));
+    p->last_stream = s;
+    return CIA_OK;
+}
+
+cia_status timing_end(cia_plan *p, hipStream_t s) {
+    if (!(p->flags & CIA_FLAG_TIMING)) return CIA_OK;
+    CIA_HIP(hipEventRecord(p->events[p->ev_used].b, s));
+    p->ev_used++;
+    // bound the number of events in flight
+    if (p->ev_used >= 8192) CIA_TRY(timing_collect(p));
+    return CIA_OK;
+}
+
+cia_status timing_collect(cia_plan *p) {
+    if (p->ev_used == 0) return CIA_OK;
+    CIA_HIP(hipEventSynchronize(p->events[p->ev_used - 1].b));
+    for (size_t k = 0; k < p->ev_used; k++) {
+        float ms = 0.f;
+        CIA_HIP(hipEventElapsedTime(&ms, p->events[k].a, p->events[k].b));
+        p->t_ms[p->events[k].kind] += ms;
+        p->t_count[p->events[k].kind]++;
+    }
+    p->ev_used = 0;
+    return CIA_OK;
+}
+
+static cia_status select_device(cia_plan *p) {
+    int cur = 0;
+    CIA_HIP(hipGetDevice(&cur));
+    if (cur != p->device) CIA_HIP(hipSetDevice(p->device));
+    return CIA_OK;
+}
+
+static void free_plan(cia_plan *p) {
+    if (!p) return;
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+    for (auto &e : p->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (void *q : p->dev_allocs)
+        if (q) (void)hipFree(q);
+    phase_free(p);
+    if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
+    delete p;
+}
+
+}  // namespace cia
+
+using namespace cia;
+
+extern "C" {
+
+cia_status cia_build(const cia_graph *g, const int32_t *labels, const cia_coupling *c,
+                     const double *omega, const cia_options *o, cia_plan **out) {
+    clear_error();
+    if (!out) return set_error(CIA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g) return set_error(CIA_EINVAL, "graph is NULL");
+    if (!c) return set_error(CIA_EINVAL, "coupling is NULL");
+    cia_options def;
+    cia_options_default(&def);
+    if (!o) o = &def;
+    if (o->method != CIA_METHOD_CIA && o->method != CIA_METHOD_DIRECT)
+        return set_error(CIA_EINVAL, "options.method = %d", o->method);
+    if (o->precision != CIA_F32 && o->precision != CIA_F64)
+        return set_error(CIA_EINVAL, "options.precision = %d", o->precision);
+    if (o->stepper != CIA_RK4 && o->stepper != CIA_EULER)
+        return set_error(CIA_EINVAL, "options.stepper = %d", o->stepper);
+    if (g->n <= 0) return set_error(CIA_EINVAL, "graph: n = %lld, need n >= 1", (long long)g->n);
+
+    int ndev = 0;
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return set_error(CIA_EHIP, "no HIP device available (%s)", hipGetErrorString(he));
+    }
+    cia_plan *p = new (std::nothrow) cia_plan();
+    if (!p) return set_error(CIA_ENOMEM, "host allocation failed");
+    p->model = c->model;
+    p->method = o->method;
+    p->precision = o->precision;
+    p->stepper = o->stepper;
+    p->flags = o->flags;
+    p->n = g->n;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) cur = 0;
+    p->device = o->device >= 0 ? o->device : cur;
+    if (p->device >= ndev) {
+        delete p;
+        return set_error(CIA_EINVAL, "options.device = %d but only %d devices", o->device, ndev);
+    }
+    cia_status st = select_device(p);
+    if (st == CIA_OK) {
+        try {
+            switch (c->model) {
+                case CIA_MODEL_PHASE: st = phase_build(p, g, labels, c, omega, o); break;
+                case CIA_MODEL_TRIADIC:
+                case CIA_MODEL_FLOCK:
+                    st = set_error(CIA_EUNSUPPORTED, "model %d is not available in this build", c->model);
+                    break;
+                default: st = set_error(CIA_EINVAL, "coupling.model = %d", c->model);
+            }
+        } catch (const std::bad_alloc &) {
+            st = set_error(CIA_ENOMEM, "host allocation failed");
+        }
+    }
+    if (st != CIA_OK) {
+        std::string msg = cia_last_error();
+        free_plan(p);
+        set_error(st, "%s", msg.c_str());
+        return st;
+    }
+    *out = p;
+    return CIA_OK;
+}
+
+cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    if (!state || !dstate) return set_error(CIA_EINVAL, "state/dstate is NULL");
+    if (state == dstate) return set_error(CIA_EINVAL, "dstate must not alias state");
+    CIA_TRY(select_device(p));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    cia_status st;
+    switch (p->model) {
+        case CIA_MODEL_PHASE: st = phase_rhs(p, state, dstate, s); break;
+        default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
+    }
+    if (st == CIA_OK && (p->flags & CIA_FLAG_TIMING)) st = timing_collect(p);
+    return st;
+}
+
+cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
+                         void *stream) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    if (!state) return set_error(CIA_EINVAL, "state is NULL");
+    if (steps < 0) return set_error(CIA_EINVAL, "steps = %lld < 0", (long long)steps);
+    if (!std::isfinite(dt)) return set_error(CIA_EINVAL, "dt is not finite");
+    CIA_TRY(select_device(p));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    cia_status st;
+    switch (p->model) {
+        case CIA_MODEL_PHASE: st = phase_integrate(p, state, dt, steps, r_trace, s); break;
+        default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
+    }
+    if (st == CIA_OK && (p->flags & CIA_FLAG_TIMING)) st = timing_collect(p);
+    return st;
+}
+
+cia_status cia_destroy(cia_plan *p) {
+    clear_error();
+    free_plan(p);
+    return CIA_OK;
+}
+
+cia_status cia_plan_get_info(const cia_plan *p, cia_plan_info *info) {
+    clear_error();
+    if (!p || !info) return set_error(CIA_EINVAL, "NULL pointer");
+    *info = p->info;
+    return CIA_OK;
+}
+
+cia_status cia_plan_get_timing(cia_plan *p, cia_timing *t, int reset) {
+    clear_error();
+    if (!p || !t) return set_error(CIA_EINVAL, "NULL pointer");
+    CIA_TRY(timing_collect(p));
+    t->stage_ms = p->t_ms[KK_STAGE];
+    t->stage_launches = p->t_count[KK_STAGE];
+    t->prep_ms = p->t_ms[KK_PREP];
+    t->prep_launches = p->t_count[KK_PREP];
+    t->aux_ms = p->t_ms[KK_AUX];
+    t->aux_launches = p->t_count[KK_AUX];
+    if (reset) {
+        for (int k = 0; k < 3; k++) p->t_ms[k] = 0, p->t_count[k] = 0;
+    }
+    return CIA_OK;
+}
+
+}  // extern "C"

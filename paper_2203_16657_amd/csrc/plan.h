@@ -1,0 +1,89 @@
+// The plan object behind the opaque cia_plan handle, and helpers shared by
+// the model implementations.
+#pragma once
+
+#include <memory>
+
+#include "internal.h"
+
+namespace cia {
+
+enum KernelKind { KK_STAGE = 0, KK_PREP = 1, KK_AUX = 2 };
+
+struct PhaseState;
+struct TriadicState;
+struct FlockState;
+
+}  // namespace cia
+
+struct cia_plan {
+    int32_t model = 0, method = 0, precision = 0, stepper = 0;
+    uint32_t flags = 0;
+    int device = 0;
+    int64_t n = 0;
+    cia_plan_info info{};
+    std::vector<void *> dev_allocs;
+
+    // per-kernel timing (CIA_FLAG_TIMING)
+    struct EvPair {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<EvPair> events;
+    size_t ev_used = 0;
+    double t_ms[3] = {0, 0, 0};
+    int64_t t_count[3] = {0, 0, 0};
+    hipStream_t last_stream = nullptr;
+
+    cia::PhaseState *phase = nullptr;
+    cia::TriadicState *tri = nullptr;
+    cia::FlockState *flock = nullptr;
+};
+
+namespace cia {
+
+template <typename T>
+cia_status dalloc(cia_plan *p, T **ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * count);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(e == hipErrorOutOfMemory ? CIA_ENOMEM : CIA_EHIP,
+                         "hipMalloc of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
+    }
+    p->dev_allocs.push_back(q);
+    *ptr = static_cast<T *>(q);
+    return CIA_OK;
+}
+
+template <typename T>
+cia_status dupload(cia_plan *p, T **ptr, const T *host, size_t count) {
+    CIA_TRY(dalloc(p, ptr, count));
+    if (count) CIA_HIP(hipMemcpy(*ptr, host, sizeof(T) * count, hipMemcpyHostToDevice));
+    return CIA_OK;
+}
+
+// Event bracketing of kernel launches (only with CIA_FLAG_TIMING).
+cia_status timing_begin(cia_plan *p, hipStream_t s, int kind);
+cia_status timing_end(cia_plan *p, hipStream_t s);
+cia_status timing_collect(cia_plan *p);
+
+// model entry points (phase model: cia_phase.hip)
+cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
+                       const double *omega, const cia_options *o);
+cia_status phase_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t s);
+cia_status phase_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
+                           hipStream_t s);
+void phase_free(cia_plan *p);
+
+cia_status triadic_build(cia_plan *p, const cia_graph *g, const int32_t *labels,
+                         const cia_coupling *c, const double *omega, const cia_options *o);
+cia_status flock_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
+                       const cia_options *o);
+cia_status flock_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t s);
+cia_status flock_integrate(cia_plan *p, void *state, double dt, int64_t steps, hipStream_t s);
+void flock_free(cia_plan *p);
+
+}  // namespace cia
