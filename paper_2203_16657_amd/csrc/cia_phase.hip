@@ -12,35 +12,65 @@
 // so E1 and E2 add before the (eq. FastHdense) broadcast-combine.  The
 // diagonal of the dense block (l = m) contributes h(0), removed analytically.
 //
-// Kernel structure on gfx950: one launch per RK stage.  A work unit (a block)
-// owns a contiguous row range of one community.  It
+// Data layout in HBM (sliced ELLPACK with one wavefront per slice): inside
+// every community the rows are ordered by decreasing remainder length (the
+// order inside a community is free in step P1), and cut into slices of 64
+// consecutive rows.  A slice stores chunk k (16 bytes) of all 64 rows
+// contiguously, so lane l of a wavefront owns row l of the slice, streams its
+// list with fully coalesced 1 KiB loads and accumulates in registers: no
+// segmented reduction and no barrier inside the gather.  Rows of communities
+// whose z values are staged in LDS store uint16 indices local to the
+// community (8 per chunk, pad = lambda, an LDS slot holding 0); all other rows
+// store int32 positions (4 per chunk, pad = N, a z slot holding 0).
+//
+// Kernel structure on gfx950: one launch per RK stage.  A block owns a run
+// of slices of one community.  It
 //   1. sums the previous stage's per-unit partial observables of its
-//      community in a fixed order (deterministic, no float atomics);
-//   2. stages the community's z values in LDS (S-neg partners are local);
-//   3. gathers T for a chunk of rows with a group of lanes per row;
-//   4. combines, adds omega, applies the RK stage update, and computes the
-//      next stage's z and its partial observables in the same pass.
+//      community in a fixed order (deterministic, no float atomics) and
+//      stages the community's z values in LDS (S-neg partners are local);
+//   2. each wavefront takes slices in turn: gather T over S-neg (LDS) and
+//      S-pos (global), then combine, add omega, apply the RK stage update and
+//      compute the next stage's z and its partial observables, per lane;
+//   3. reduces the partial observables of the block in a fixed order.
 // The direct method runs the same kernel with every node outside any
 // community and the whole adjacency in the +1 list.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 
 #include "plan.h"
 
 namespace cia {
 
 constexpr int PMAX = 8;
-constexpr double WIDE_COMMUNITY = 1e5;     // FP64 observables above this size
-constexpr size_t LDS_STAGE_BYTES = 64 * 1024;
+constexpr double WIDE_COMMUNITY = 1e5;   // FP64 observables above this size
+constexpr size_t LDS_BYTES = 64 * 1024;  // dynamic LDS budget of a stage block
+constexpr int SLICE = 64;                // rows per slice = lanes per wavefront
 
 // unit flag bits
-constexpr int UF_STAGED = 1;   // community z staged in LDS
+constexpr int UF_STAGED = 1;   // community z staged in LDS, S-neg as uint16 local indices
 constexpr int UF_WIDE = 2;     // FP64 observables and combine (F32 plans)
-constexpr int UF_NEG32 = 4;    // S-neg entries stored as int32 positions
-constexpr int UF_LPR_SHIFT = 8;
+constexpr int UF_ASSIGNED = 4; // rows of a dense community (E1 applies)
 
+// 64 rows of one community; chunk k of lane l sits at beg + 64 k + l.
+struct alignas(16) Slice {
+    int32_t row0, rows;   // first row (community order), number of rows (1..64)
+    uint32_t nbeg;        // S-neg block: first chunk, chunks per lane
+    int32_t nw;
+    uint32_t pbeg;        // S-pos block
+    int32_t pw;
+    int32_t r0, r1;       // unused (keeps the descriptor at 32 bytes)
+};
+
+// A work unit (one block): a run of slices of one community or of the rows
+// outside every community, with everything needed to start in one load.
 struct alignas(16) Unit {
-    int32_t r0, r1, comm, flags;
+    int32_t s0, s1;      // slices [s0, s1)
+    int32_t flags;       // UF_*
+    int32_t off, lam;    // community rows [off, off + lam); lam = 0 outside communities
+    int32_t qslot;       // slot of this unit's partial observables
+    int32_t qbeg, qend;  // slots of every unit of the community, in increasing row order
 };
 
 template <typename R>
@@ -100,23 +130,19 @@ enum Mode { M_PREP = 0, M_RHS = 1, M_RK4 = 2, M_EULER = 3 };
 template <typename R>
 struct PhaseArgs {
     const Unit *units;
-    const int32_t *comm_off;
-    const int32_t *cu_off;    // community -> range in cu_list
-    const int32_t *cu_list;   // unit ids grouped by community
-    const int64_t *negptr;
-    const uint16_t *neg16;
-    const int32_t *neg32;
-    const int64_t *posptr;
-    const int32_t *pos;
-    const int32_t *perm;
+    const Slice *slices;
+    const uint4 *negdata;     // S-neg slice blocks
+    const uint4 *posdata;     // S-pos slice blocks
+    const int32_t *cnt;       // [n] |S+| - |S-| per row (only when d_0 != 0)
+    const int32_t *perm;      // community order -> user order
     const R *omega;
     R *theta_n;               // theta at the start of the step (community order)
     R *acc;                   // RK4 accumulator
     const R *theta_cur;       // theta of the current stage (wide units only)
     R *theta_next;            // theta of the next stage (wide units only)
-    const cx<R> *cs_in;       // z of the current stage
+    const cx<R> *cs_in;       // z of the current stage, [n+1], z[n] = 0
     cx<R> *cs_out;            // z of the next stage
-    const double2 *q_in;      // [nunits][P] partial observables of the current stage
+    const double2 *q_in;      // [slots][P] partial observables of the current stage
     double2 *q_out;
     double2 *r_part;          // [nunits] partial sum of z for the order parameter
     const R *state_in;        // user order (M_PREP)
@@ -124,42 +150,106 @@ struct PhaseArgs {
     R Kn, dt, d0, hzero;
     R dsin[PMAX + 1], dcos[PMAX + 1];
     int32_t stage, mode, want_r, lds_cap;
+    uint32_t pad_pos;         // position whose z is 0 (= n): target of padded int32 entries
 };
 
-template <typename R, int P, int BLOCK>
+// The remainder streams are read once per stage: non-temporal loads keep
+// them from evicting the z values that the gathers reuse from L2.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_stream(const uint4 *p) {
+    const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+template <typename R, int P>
+__device__ __forceinline__ void acc_z(cx<R> (&T)[P], cx<R> z, R sign) {
+    cx<R> zk = z;
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        T[k].x += sign * zk.x;
+        T[k].y += sign * zk.y;
+        if (k + 1 < P) zk = cmul(zk, z);
+    }
+}
+
+// Stream `w` chunks of one lane's row (stride 64 chunks), U in flight.
+// staged: 8 uint16 LDS indices per chunk; otherwise 4 int32 global positions.
+template <typename R, int P, int U, bool STAGED>
+__device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restrict__ col, int w,
+                                            const cx<R> *zsh, const cx<R> *__restrict__ cs, R sign,
+                                            uint4 padv) {
+    for (int k = 0; k < w; k += U) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = k + u < w ? ld_stream(col + (size_t)(k + u) * SLICE) : padv;
+        if (STAGED) {
+            cx<R> z[U][8];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    z[u][2 * q] = zsh[q4[q] & 0xffffu];
+                    z[u][2 * q + 1] = zsh[q4[q] >> 16];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+#pragma unroll
+                for (int q = 0; q < 8; q++) acc_z<R, P>(T, z[u][q], sign);
+        } else {
+            cx<R> z[U][4];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                z[u][0] = cs[v[u].x];
+                z[u][1] = cs[v[u].y];
+                z[u][2] = cs[v[u].z];
+                z[u][3] = cs[v[u].w];
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) acc_z<R, P>(T, z[u][q], sign);
+        }
+    }
+}
+
+// DIRECT: every row is an outside row with its whole adjacency in the +1
+// list (no observables, no staging).  WIDE: the FP64 path of very large
+// communities is compiled in (F32 plans that have such communities).
+template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE>
 __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     constexpr int NW = BLOCK / 64;
+    constexpr int U = P >= 4 ? 1 : 4 / P;   // chunks in flight per lane
     extern __shared__ __align__(16) unsigned char smem[];
-    cx<R> *zsh = reinterpret_cast<cx<R> *>(smem);                         // [lds_cap]
-    cx<R> *tsh = reinterpret_cast<cx<R> *>(smem + sizeof(cx<R>) * a.lds_cap);  // [BLOCK][P]
+    cx<R> *zsh = reinterpret_cast<cx<R> *>(smem);   // [lds_cap + 1]
     __shared__ double2 qsh[P];
     __shared__ float red_s[NW][2 * P], red_c[NW][2 * P];
     __shared__ double red_d[NW][2 * P];
     __shared__ double2 red_r[NW];
 
-    const Unit U = a.units[blockIdx.x];
+    const Unit Un = a.units[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    const int c = U.comm;
-    const bool assigned = c >= 0;
-    const bool staged = (U.flags & UF_STAGED) != 0;
-    const bool wide = (U.flags & UF_WIDE) != 0;
-    const bool neg32 = (U.flags & UF_NEG32) != 0;
+    const bool assigned = !DIRECT && (Un.flags & UF_ASSIGNED) != 0;
+    const bool staged = !DIRECT && (Un.flags & UF_STAGED) != 0;
+    const bool wide = WIDE && (Un.flags & UF_WIDE) != 0;
     const int mode = a.mode;
-    int off = 0, lam = 0;
-    if (assigned) {
-        off = a.comm_off[c];
-        lam = a.comm_off[c + 1] - off;
-    }
+    const bool gather = mode != M_PREP;
+    const int off = Un.off, lam = Un.lam;
 
-    // ---- 1. community observables of the current stage (E1, fixed order) ----
-    if (mode != M_PREP && assigned) {
-        if (wid == 0) {
-            const int b = a.cu_off[c], e = a.cu_off[c + 1];
+    // ---- 1. unit start: the community's z in LDS and its observables (E1,
+    //      fixed order over the units of the community) ----
+    if (gather && assigned) {
+        if (staged) {
+            for (int j = tid; j < lam; j += BLOCK) zsh[j] = a.cs_in[off + j];
+            if (tid == 0) zsh[lam] = cx<R>{(R)0, (R)0};   // slot of the padding index
+        }
+        if (wid == NW - 1) {
             for (int k = 0; k < P; k++) {
                 double sx = 0.0, sy = 0.0;
-                for (int j = b + lane; j < e; j += 64) {
-                    double2 q = a.q_in[(size_t)a.cu_list[j] * P + k];
+                for (int j = Un.qbeg + lane; j < Un.qend; j += 64) {
+                    double2 q = a.q_in[(size_t)j * P + k];
                     sx += q.x;
                     sy += q.y;
                 }
@@ -170,14 +260,12 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                 if (lane == 0) qsh[k] = make_double2(sx, sy);
             }
         }
-        if (staged)
-            for (int j = tid; j < lam; j += BLOCK) zsh[j] = a.cs_in[off + j];
     }
     __syncthreads();
 
     R qx[P], qy[P];
     double qdx[P], qdy[P];
-    if (mode != M_PREP && assigned) {
+    if (gather && assigned) {
 #pragma unroll
         for (int k = 0; k < P; k++) {
             qdx[k] = qsh[k].x;
@@ -197,112 +285,83 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     for (int k = 0; k < 2 * P; k++) ps[k] = pc[k] = 0.f, pd[k] = 0.0;
     double rx = 0.0, ry = 0.0;
 
-    const int lpr_log = (U.flags >> UF_LPR_SHIFT) & 15;
-    const int lpr = 1 << lpr_log;
-    const int groups = BLOCK >> lpr_log;
-    const int grp = tid >> lpr_log, gl = tid & (lpr - 1);
+    const uint32_t pad16 = (uint32_t)lam | ((uint32_t)lam << 16);
+    const uint4 padl = make_uint4(pad16, pad16, pad16, pad16);
+    const uint4 padp = make_uint4(a.pad_pos, a.pad_pos, a.pad_pos, a.pad_pos);
 
-    for (int base = U.r0; base < U.r1; base += BLOCK) {
-        const int nrows = min(BLOCK, U.r1 - base);
-        // ---- 2. E2 gather: T_{m,k} over S for this chunk ----
-        if (mode != M_PREP) {
-            for (int rr = grp; rr < nrows; rr += groups) {
-                const int i = base + rr;
-                cx<R> T[P];
-#pragma unroll
-                for (int k = 0; k < P; k++) T[k].x = T[k].y = (R)0;
-                const int64_t nb = a.negptr[i], ne = a.negptr[i + 1];
-                for (int64_t e = nb + gl; e < ne; e += lpr) {
-                    cx<R> z;
-                    if (neg32) z = a.cs_in[a.neg32[e]];
-                    else if (staged) z = zsh[a.neg16[e]];
-                    else z = a.cs_in[off + (int)a.neg16[e]];
-                    cx<R> zk = z;
-#pragma unroll
-                    for (int k = 0; k < P; k++) {
-                        T[k].x -= zk.x;
-                        T[k].y -= zk.y;
-                        if (k + 1 < P) zk = cmul(zk, z);
-                    }
-                }
-                const int64_t pb = a.posptr[i], pe = a.posptr[i + 1];
-                for (int64_t e = pb + gl; e < pe; e += lpr) {
-                    cx<R> z = a.cs_in[a.pos[e]];
-                    cx<R> zk = z;
-#pragma unroll
-                    for (int k = 0; k < P; k++) {
-                        T[k].x += zk.x;
-                        T[k].y += zk.y;
-                        if (k + 1 < P) zk = cmul(zk, z);
-                    }
-                }
-                for (int o = lpr >> 1; o > 0; o >>= 1) {
-#pragma unroll
-                    for (int k = 0; k < P; k++) {
-                        T[k].x += __shfl_xor(T[k].x, o);
-                        T[k].y += __shfl_xor(T[k].y, o);
-                    }
-                }
-                if (gl == 0) {
-#pragma unroll
-                    for (int k = 0; k < P; k++) tsh[rr * P + k] = T[k];
-                }
+    // ---- 2. slices, one wavefront each, one row per lane ----
+    for (int sl = Un.s0 + wid; sl < Un.s1; sl += NW) {
+        const Slice S = a.slices[sl];
+        const bool mine = lane < S.rows;
+        const int i = S.row0 + lane;
+        // operands of the combine / stage update, loaded before the gather
+        R tn = (R)0, om = (R)0, av = (R)0, thc = (R)0;
+        int cv = 0;
+        if (mine) {
+            if (mode == M_PREP) {
+                tn = a.state_in[a.perm[i]];
+            } else {
+                if (mode != M_RHS) tn = a.theta_n[i];
+                if (a.omega) om = a.omega[i];
+                if (mode == M_RK4 && a.stage > 0) av = a.acc[i];
+                if (a.d0 != (R)0) cv = a.cnt[i];
+                if (WIDE && wide) thc = a.theta_cur[i];
             }
-            __syncthreads();
+        }
+        cx<R> T[P];
+#pragma unroll
+        for (int k = 0; k < P; k++) T[k].x = T[k].y = (R)0;
+        if (gather) {
+            if (!DIRECT) {
+                if (staged)
+                    gather_rows<R, P, U, true>(T, a.negdata + S.nbeg + lane, S.nw, zsh, a.cs_in, (R)-1, padl);
+                else
+                    gather_rows<R, P, U, false>(T, a.negdata + S.nbeg + lane, S.nw, zsh, a.cs_in, (R)-1, padp);
+            }
+            gather_rows<R, P, U, false>(T, a.posdata + S.pbeg + lane, S.pw, zsh, a.cs_in, (R)1, padp);
         }
 
-        // ---- 3. combine (eq. FastHdense + E2), stage update, next z ----
-        if (tid < nrows) {
-            const int i = base + tid;
+        // ---- combine (eq. FastHdense + E2), stage update, next z ----
+        if (mine) {
             R theta_new = (R)0;
             bool emit = true;
             if (mode == M_PREP) {
-                theta_new = a.state_in[a.perm[i]];
+                theta_new = tn;
                 a.theta_n[i] = theta_new;
             } else {
                 R H;
-                const R om = a.omega ? a.omega[i] : (R)0;
                 if (!wide) {
                     cx<R> z = staged ? zsh[i - off] : a.cs_in[i];
                     R s = (R)0;
-                    if (a.d0 != (R)0) {
-                        R cnt = (R)((a.posptr[i + 1] - a.posptr[i]) - (a.negptr[i + 1] - a.negptr[i]));
-                        s = a.d0 * ((assigned ? (R)lam : (R)0) + cnt);
-                    }
+                    if (a.d0 != (R)0) s = a.d0 * ((assigned ? (R)lam : (R)0) + (R)cv);
                     if (assigned) s -= a.hzero;
                     cx<R> zk = z;
 #pragma unroll
                     for (int k = 0; k < P; k++) {
-                        cx<R> A = {qx[k] + tsh[tid * P + k].x, qy[k] + tsh[tid * P + k].y};
-                        cx<R> zc = {zk.x, -zk.y};
-                        cx<R> B = cmul(A, zc);
+                        cx<R> A = {qx[k] + T[k].x, qy[k] + T[k].y};
+                        cx<R> B = cmul(A, cx<R>{zk.x, -zk.y});
                         s += a.dcos[k + 1] * B.x + a.dsin[k + 1] * B.y;
                         if (k + 1 < P) zk = cmul(zk, z);
                     }
                     H = om + a.Kn * s;
                 } else {
                     // FP64 observables and combine for very large communities
-                    double t = (double)a.theta_cur[i];
                     double zs, zc0;
-                    sincos(t, &zs, &zc0);
+                    sincos((double)thc, &zs, &zc0);
                     cx<double> z = {zc0, zs};
                     double s = 0.0;
-                    if (a.d0 != (R)0) {
-                        double cnt = (double)((a.posptr[i + 1] - a.posptr[i]) - (a.negptr[i + 1] - a.negptr[i]));
-                        s = (double)a.d0 * ((double)lam + cnt);
-                    }
+                    if (a.d0 != (R)0) s = (double)a.d0 * ((double)lam + (double)cv);
                     s -= (double)a.hzero;
                     cx<double> zk = z;
 #pragma unroll
                     for (int k = 0; k < P; k++) {
-                        cx<double> A = {qdx[k] + (double)tsh[tid * P + k].x, qdy[k] + (double)tsh[tid * P + k].y};
+                        cx<double> A = {qdx[k] + (double)T[k].x, qdy[k] + (double)T[k].y};
                         cx<double> B = cmul(A, cx<double>{zk.x, -zk.y});
                         s += (double)a.dcos[k + 1] * B.x + (double)a.dsin[k + 1] * B.y;
                         if (k + 1 < P) zk = cmul(zk, z);
                     }
                     H = (R)((double)om + (double)a.Kn * s);
                 }
-                const R tn = mode == M_RHS ? (R)0 : a.theta_n[i];
                 if (mode == M_RHS) {
                     a.state_out[a.perm[i]] = H;
                     emit = false;
@@ -315,13 +374,13 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                         a.acc[i] = H;
                         theta_new = tn + (R)0.5 * a.dt * H;
                     } else if (st == 1) {
-                        a.acc[i] += (R)2 * H;
+                        a.acc[i] = av + (R)2 * H;
                         theta_new = tn + (R)0.5 * a.dt * H;
                     } else if (st == 2) {
-                        a.acc[i] += (R)2 * H;
+                        a.acc[i] = av + (R)2 * H;
                         theta_new = tn + a.dt * H;
                     } else {
-                        theta_new = wrap_2pi<R>(tn + a.dt / (R)6 * (a.acc[i] + H));
+                        theta_new = wrap_2pi<R>(tn + a.dt / (R)6 * (av + H));
                         a.theta_n[i] = theta_new;
                     }
                 }
@@ -365,11 +424,10 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                 ry += (double)zs;
             }
         }
-        if (mode != M_PREP) __syncthreads();   // tsh is reused by the next chunk
     }
     if (mode == M_RHS) return;
 
-    // ---- 4. unit partials: deterministic block reduction ----
+    // ---- 3. unit partials: deterministic block reduction ----
     if (assigned) {
         if (sizeof(R) == 4 && !wide) {
 #pragma unroll
@@ -422,7 +480,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                         vy += red_d[w][2 * k + 1];
                     }
                 }
-                a.q_out[(size_t)blockIdx.x * P + k] = make_double2(vx, vy);
+                a.q_out[(size_t)Un.qslot * P + k] = make_double2(vx, vy);
             }
         }
         if (a.want_r) {
@@ -482,13 +540,7 @@ __global__ __launch_bounds__(BLOCK) void all2all_kernel(int64_t n, const cx<R> *
         const int lim = (int)min((int64_t)BLOCK, n - t0);
         for (int q = 0; q < lim; q++) {
             if (t0 + q == i) continue;
-            cx<R> z = tile[q], zk = z;
-#pragma unroll
-            for (int k = 0; k < P; k++) {
-                T[k].x += zk.x;
-                T[k].y += zk.y;
-                if (k + 1 < P) zk = cmul(zk, z);
-            }
+            acc_z<R, P>(T, tile[q], (R)1);
         }
         __syncthreads();
     }
@@ -580,6 +632,7 @@ struct PhaseState {
     int P = 1;
     bool f64 = false, direct = false, complete_direct = false;
     int block = 256;
+    bool has_wide = false;   // F32 plan with at least one FP64-observable community
     int32_t nunits = 0, ncomm = 0;
     int lds_cap = 0;
     size_t smem = 0;
@@ -587,10 +640,9 @@ struct PhaseState {
     double dsin[PMAX + 1] = {0}, dcos[PMAX + 1] = {0};
     // device
     Unit *units = nullptr;
-    int32_t *comm_off = nullptr, *cu_off = nullptr, *cu_list = nullptr;
-    int64_t *negptr = nullptr, *posptr = nullptr;
-    uint16_t *neg16 = nullptr;
-    int32_t *neg32 = nullptr, *pos = nullptr, *perm = nullptr;
+    Slice *slices = nullptr;
+    uint4 *negdata = nullptr, *posdata = nullptr;
+    int32_t *cnt = nullptr, *perm = nullptr;
     void *omega = nullptr, *theta_n = nullptr, *acc = nullptr, *theta_st[2] = {nullptr, nullptr};
     void *cs[2] = {nullptr, nullptr};
     double2 *q[2] = {nullptr, nullptr};
@@ -601,74 +653,220 @@ struct PhaseState {
     void *coef = nullptr;   // [2][PMAX+1] device copy of dsin/dcos (all-to-all kernel)
 };
 
-static int ilog2_ceil(int64_t v) {
-    int l = 0;
-    while ((int64_t(1) << l) < v) l++;
-    return l;
+// Row lists handed to the packer: old-order CSR of remainder entries.
+struct RowLists {
+    const std::vector<int64_t> *negptr = nullptr;   // may be null (no S-neg)
+    const int32_t *neg = nullptr;                   // local index inside the row's community
+    const std::vector<int64_t> *posptr = nullptr;
+    const int32_t *pos = nullptr;                   // old positions
+};
+
+struct Sell {
+    std::vector<int32_t> newpos;   // old position -> new position
+    std::vector<Slice> slices;
+    std::vector<int32_t> seg_slice_off;   // segment -> first slice
+    std::vector<uint4> neg, pos;
+};
+
+// Order rows inside every segment by decreasing remainder length, cut the
+// segments into 64-row slices and pack the sliced blocks.  Segments are the
+// communities [comm_off[c], comm_off[c+1]) and the tail of rows outside every
+// community; seg_staged[c] selects uint16 local indices for S-neg.
+static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, int32_t ncomm,
+                             const std::vector<char> &seg_staged, const RowLists &L, Sell &out) {
+    const int32_t nseg = ncomm + 1;
+    std::vector<int64_t> sb(nseg + 1);
+    for (int32_t c = 0; c <= ncomm; c++) sb[c] = c < ncomm ? comm_off[c] : (ncomm ? comm_off[ncomm] : 0);
+    sb[nseg] = n;
+    auto nneg = [&](int64_t i) -> int64_t { return L.negptr ? (*L.negptr)[i + 1] - (*L.negptr)[i] : 0; };
+    auto npos = [&](int64_t i) -> int64_t { return (*L.posptr)[i + 1] - (*L.posptr)[i]; };
+    out.newpos.resize(n);
+    std::vector<int32_t> oldpos(n);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t c = 0; c < nseg; c++) {
+        const int64_t b = sb[c], e = sb[c + 1];
+        const int64_t per = (c < ncomm && seg_staged[c]) ? 8 : 4;
+        std::vector<int32_t> idx(e - b);
+        for (int64_t k = 0; k < e - b; k++) idx[k] = (int32_t)(b + k);
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+            int64_t nx = (nneg(x) + per - 1) / per, ny = (nneg(y) + per - 1) / per;
+            if (nx != ny) return nx > ny;
+            return (npos(x) + 3) / 4 > (npos(y) + 3) / 4;
+        });
+        for (int64_t k = 0; k < e - b; k++) {
+            oldpos[b + k] = idx[k];
+            out.newpos[idx[k]] = (int32_t)(b + k);
+        }
+    }
+    // slices and their widths
+    out.slices.clear();
+    out.seg_slice_off.assign(nseg + 1, 0);
+    uint64_t ntot = 0, ptot = 0;
+    for (int32_t c = 0; c < nseg; c++) {
+        out.seg_slice_off[c] = (int32_t)out.slices.size();
+        const int64_t per = (c < ncomm && seg_staged[c]) ? 8 : 4;
+        for (int64_t r = sb[c]; r < sb[c + 1]; r += SLICE) {
+            Slice S{};
+            S.row0 = (int32_t)r;
+            S.rows = (int32_t)std::min<int64_t>(SLICE, sb[c + 1] - r);
+            int64_t nw = 0, pw = 0;
+            for (int l = 0; l < S.rows; l++) {
+                int64_t o = oldpos[r + l];
+                nw = std::max(nw, (nneg(o) + per - 1) / per);
+                pw = std::max(pw, (npos(o) + 3) / 4);
+            }
+            S.nbeg = (uint32_t)ntot;
+            S.nw = (int32_t)nw;
+            S.pbeg = (uint32_t)ptot;
+            S.pw = (int32_t)pw;
+            ntot += (uint64_t)nw * SLICE;
+            ptot += (uint64_t)pw * SLICE;
+            if (ntot > 0xffffffffULL || ptot > 0xffffffffULL)
+                return set_error(CIA_EUNSUPPORTED, "remainder stream above 64 GiB");
+            out.slices.push_back(S);
+        }
+    }
+    out.seg_slice_off[nseg] = (int32_t)out.slices.size();
+    try {
+        out.neg.resize(std::max<uint64_t>(ntot, 1));
+        out.pos.resize(std::max<uint64_t>(ptot, 1));
+    } catch (const std::bad_alloc &) {
+        return set_error(CIA_ENOMEM, "host allocation of the sliced remainder failed");
+    }
+    // fill, slice by slice
+    const int64_t nsl = (int64_t)out.slices.size();
+    std::vector<int32_t> seg_of_slice(nsl);
+    for (int32_t c = 0; c < nseg; c++)
+        for (int32_t k = out.seg_slice_off[c]; k < out.seg_slice_off[c + 1]; k++) seg_of_slice[k] = c;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nsl; k++) {
+        const Slice &S = out.slices[k];
+        const int32_t c = seg_of_slice[k];
+        const bool st = c < ncomm && seg_staged[c];
+        const int64_t off = sb[c], lam = sb[c + 1] - sb[c];
+        uint32_t *nw32 = reinterpret_cast<uint32_t *>(out.neg.data() + S.nbeg);
+        uint16_t *nw16 = reinterpret_cast<uint16_t *>(out.neg.data() + S.nbeg);
+        uint32_t *pw32 = reinterpret_cast<uint32_t *>(out.pos.data() + S.pbeg);
+        for (int l = 0; l < SLICE; l++) {
+            const int64_t o = l < S.rows ? oldpos[S.row0 + l] : -1;
+            // S-neg
+            const int64_t nn = o >= 0 ? nneg(o) : 0;
+            if (st) {
+                for (int64_t q = 0; q < (int64_t)S.nw * 8; q++) {
+                    uint16_t v = (uint16_t)lam;
+                    if (q < nn) v = (uint16_t)(out.newpos[off + L.neg[(*L.negptr)[o] + q]] - off);
+                    nw16[((q / 8) * SLICE + l) * 8 + (q % 8)] = v;
+                }
+            } else {
+                for (int64_t q = 0; q < (int64_t)S.nw * 4; q++) {
+                    uint32_t v = (uint32_t)n;
+                    if (q < nn) v = (uint32_t)out.newpos[off + L.neg[(*L.negptr)[o] + q]];
+                    nw32[((q / 4) * SLICE + l) * 4 + (q % 4)] = v;
+                }
+            }
+            // S-pos
+            const int64_t np = o >= 0 ? npos(o) : 0;
+            for (int64_t q = 0; q < (int64_t)S.pw * 4; q++) {
+                uint32_t v = (uint32_t)n;
+                if (q < np) v = (uint32_t)out.newpos[L.pos[(*L.posptr)[o] + q]];
+                pw32[((q / 4) * SLICE + l) * 4 + (q % 4)] = v;
+            }
+        }
+    }
+    return CIA_OK;
 }
 
-// Build the work units: contiguous row ranges of one community (or of the
-// nodes outside every community), sized by remainder entries, ordered by
-// decreasing work so the longest units start first.
-static void make_units(const P1 &p1, const std::vector<int64_t> &negptr, const std::vector<int64_t> &posptr,
-                       int64_t target, int block, int lds_cap, bool allow_stage, uint32_t flags,
-                       std::vector<Unit> &units, std::vector<int32_t> &cu_off, std::vector<int32_t> &cu_list) {
-    const int64_t n = p1.n;
+// Build the work units and their launch order.
+//  - a unit is a run of slices of one community (or of the rows outside every
+//    community), sized by slice chunks;
+//  - communities are assigned whole to one of the 8 XCDs (workgroup ids are
+//    dispatched round-robin over the XCDs), largest first onto the least
+//    loaded XCD, so a community's staged z values are read through one L2;
+//  - inside an XCD the longest units start first; the launch order
+//    interleaves the 8 XCD queues (padding with empty units);
+//  - partial-observable slots are numbered community by community in
+//    increasing row order, so a community sums a contiguous slot range in a
+//    fixed order.  Returns the number of slots.
+static int32_t make_units(const Sell &sell, const std::vector<int32_t> &comm_off, int32_t ncomm,
+                          int64_t target_chunks, int min_slices, const std::vector<char> &comm_staged,
+                          uint32_t opt_flags, std::vector<Unit> &units) {
+    const int NX = 8;
     struct U2 {
         Unit u;
         int64_t work;
+        int32_t comm;
     };
-    std::vector<U2> all;
-    const uint32_t opt_flags = flags;
-    auto row_work = [&](int64_t i) {
-        return (negptr[i + 1] - negptr[i]) + (posptr[i + 1] - posptr[i]) + 8;
+    auto sw = [&](int32_t k) -> int64_t {
+        const Slice &S = sell.slices[k];
+        return (int64_t)(S.nw + S.pw + 2) * SLICE;
     };
-    auto emit = [&](int64_t r0, int64_t r1, int32_t comm, int64_t lam) {
-        // lanes per row from the mean remainder length of the range
-        int64_t ent = 0;
-        for (int64_t i = r0; i < r1; i++) ent += (negptr[i + 1] - negptr[i]) + (posptr[i + 1] - posptr[i]);
-        double mean = (double)ent / (double)std::max<int64_t>(1, r1 - r0);
-        int lg = ilog2_ceil((int64_t)std::ceil(mean / 2.0));
-        lg = std::max(0, std::min(6, lg));
-        int flags = lg << UF_LPR_SHIFT;
-        if (comm >= 0) {
-            if ((double)lam > WIDE_COMMUNITY || (opt_flags & CIA_FLAG_FORCE_WIDE)) flags |= UF_WIDE;
-            if (lam > 65536 || (opt_flags & CIA_FLAG_FORCE_NEG32)) flags |= UF_NEG32;
-            if (allow_stage && lam <= lds_cap && !(flags & (UF_WIDE | UF_NEG32))) flags |= UF_STAGED;
-        }
-        all.push_back({Unit{(int32_t)r0, (int32_t)r1, comm, flags}, ent + 8 * (r1 - r0)});
-    };
-    auto split = [&](int64_t b, int64_t e, int32_t comm, int64_t lam) {
-        // at least ~block rows per unit unless the range is shorter
-        int64_t r = b;
-        while (r < e) {
-            int64_t w = 0, r1 = r;
-            while (r1 < e && (w < target || r1 - r < std::min<int64_t>(64, e - r))) {
-                w += row_work(r1);
-                r1++;
+    std::vector<std::vector<U2>> groups;
+    auto make_group = [&](int32_t k0, int32_t k1, int32_t comm, int64_t off, int64_t lam) {
+        std::vector<U2> g;
+        int32_t k = k0;
+        while (k < k1) {
+            int64_t w = 0;
+            int32_t e = k;
+            while (e < k1 && (w < target_chunks || e - k < std::min(min_slices, k1 - k))) {
+                w += sw(e);
+                e++;
             }
-            emit(r, r1, comm, lam);
-            r = r1;
+            int flags = 0;
+            if (comm >= 0) {
+                flags |= UF_ASSIGNED;
+                if ((double)lam > WIDE_COMMUNITY || (opt_flags & CIA_FLAG_FORCE_WIDE)) flags |= UF_WIDE;
+                if (comm_staged[comm]) flags |= UF_STAGED;
+            }
+            Unit u{k, e, flags, (int32_t)(comm >= 0 ? off : 0), (int32_t)(comm >= 0 ? lam : 0), 0, 0, 0};
+            g.push_back({u, w, comm});
+            k = e;
         }
+        groups.push_back(std::move(g));
     };
-    for (int32_t c = 0; c < p1.ncomm; c++)
-        split(p1.comm_off[c], p1.comm_off[c + 1], c, p1.comm_off[c + 1] - p1.comm_off[c]);
-    split(p1.ncomm ? p1.comm_off[p1.ncomm] : 0, n, -1, 0);
-    std::stable_sort(all.begin(), all.end(), [](const U2 &x, const U2 &y) { return x.work > y.work; });
+    for (int32_t c = 0; c < ncomm; c++)
+        make_group(sell.seg_slice_off[c], sell.seg_slice_off[c + 1], c, comm_off[c], comm_off[c + 1] - comm_off[c]);
+    {
+        make_group(sell.seg_slice_off[ncomm], sell.seg_slice_off[ncomm + 1], -1, 0, 0);
+        std::vector<U2> rest = std::move(groups.back());
+        groups.pop_back();
+        for (auto &u : rest) groups.push_back(std::vector<U2>{u});
+    }
+    int32_t slot = 0;
+    for (auto &g : groups) {
+        if (g.empty() || g[0].comm < 0) continue;
+        int32_t qb = slot;
+        for (auto &u : g) u.u.qslot = slot++;
+        for (auto &u : g) {
+            u.u.qbeg = qb;
+            u.u.qend = slot;
+        }
+    }
+    std::vector<int64_t> gw(groups.size(), 0);
+    for (size_t k = 0; k < groups.size(); k++)
+        for (auto &u : groups[k]) gw[k] += u.work;
+    std::vector<size_t> order(groups.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return gw[x] > gw[y]; });
+    std::vector<std::vector<U2>> xq(NX);
+    std::vector<int64_t> xl(NX, 0);
+    for (size_t k : order) {
+        int best = 0;
+        for (int x = 1; x < NX; x++)
+            if (xl[x] < xl[best]) best = x;
+        for (auto &u : groups[k]) xq[best].push_back(u);
+        xl[best] += gw[k];
+    }
+    size_t depth = 0;
+    for (int x = 0; x < NX; x++) {
+        std::stable_sort(xq[x].begin(), xq[x].end(), [](const U2 &a, const U2 &b) { return a.work > b.work; });
+        depth = std::max(depth, xq[x].size());
+    }
     units.clear();
-    for (auto &x : all) units.push_back(x.u);
-    cu_off.assign(p1.ncomm + 1, 0);
-    for (auto &u : units)
-        if (u.comm >= 0) cu_off[u.comm + 1]++;
-    for (int32_t c = 0; c < p1.ncomm; c++) cu_off[c + 1] += cu_off[c];
-    cu_list.assign(cu_off[p1.ncomm], 0);
-    std::vector<int32_t> fill(cu_off.begin(), cu_off.end());
-    // units of one community listed in increasing row order (fixed summation order)
-    std::vector<int32_t> ids(units.size());
-    for (size_t k = 0; k < units.size(); k++) ids[k] = (int32_t)k;
-    std::stable_sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) { return units[x].r0 < units[y].r0; });
-    for (int32_t k : ids)
-        if (units[k].comm >= 0) cu_list[fill[units[k].comm]++] = k;
+    for (size_t j = 0; j < depth; j++)
+        for (int x = 0; x < NX; x++)
+            units.push_back(j < xq[x].size() ? xq[x][j].u : Unit{0, 0, 0, 0, 0, 0, 0, 0});
+    while (!units.empty() && units.back().s0 == units.back().s1) units.pop_back();
+    return slot;
 }
 
 cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
@@ -681,6 +879,9 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     s->direct = o->method == CIA_METHOD_DIRECT;
     if (c->p < 1 || c->p > PMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, PMAX);
     if (!c->d_sin || !c->d_cos) return set_error(CIA_EINVAL, "coupling.d_sin/d_cos are NULL");
+    for (int k = 0; k <= c->p; k++)
+        if (!std::isfinite(c->d_sin[k]) || !std::isfinite(c->d_cos[k]))
+            return set_error(CIA_EINVAL, "coupling coefficients must be finite");
     s->P = c->p;
     s->K = c->K;
     s->Kn = c->K / (double)g->n;
@@ -692,40 +893,63 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         s->hzero += c->d_cos[k];
     }
     if (!std::isfinite(s->Kn)) return set_error(CIA_EINVAL, "coupling.K is not finite");
-    s->block = o->block == 512 ? 512 : 256;
     if (o->block != 0 && o->block != 256 && o->block != 512)
         return set_error(CIA_EINVAL, "options.block = %d; use 0, 256 or 512", o->block);
+    s->block = o->block == 512 ? 512 : 256;
+    if (omega)
+        for (int64_t i = 0; i < g->n; i++)
+            if (!std::isfinite(omega[i])) return set_error(CIA_EINVAL, "omega[%lld] is not finite", (long long)i);
     const bool validate = (o->flags & CIA_FLAG_NO_VALIDATE) == 0;
     const bool keep = (o->flags & CIA_FLAG_KEEP_LABELS) != 0;
     const int64_t n = g->n;
     const size_t rs = f64 ? sizeof(double) : sizeof(float);
+    const int64_t zbytes = f64 ? 16 : 8;
+
+    // LDS staging capacity (community z values, plus one zero slot); uint16
+    // local indices also bound it (the padding index lambda must fit)
+    int64_t cap = (int64_t)LDS_BYTES / zbytes - 1;
+    if (s->direct || (o->flags & (CIA_FLAG_NO_LDS | CIA_FLAG_FORCE_NEG32))) cap = 0;
+    cap = std::min<int64_t>(cap, 65535);
 
     P1 p1;
-    std::vector<int64_t> negptr, posptr;
-    std::vector<int32_t> poscol;
-    std::vector<uint16_t> neg16;
-    std::vector<int32_t> neg32;
-    bool any_neg32 = false;
+    Sell sell;
+    std::vector<int32_t> cnt_old;
+    std::vector<char> comm_staged;
+    int64_t nnz_neg = 0, nnz_pos = 0, nnz_neg_staged = 0;
     try {
         if (!s->direct) {
             CIA_TRY(p1_build(g, labels, o->dense_alpha, keep, validate, true, p1));
-            negptr.swap(p1.negptr);
-            posptr.swap(p1.posptr);
-            poscol.swap(p1.pos);
-            for (int32_t cc = 0; cc < p1.ncomm; cc++)
-                if (p1.comm_off[cc + 1] - p1.comm_off[cc] > 65536) any_neg32 = true;
-            if (o->flags & CIA_FLAG_FORCE_NEG32) any_neg32 = true;
-            neg16.resize(p1.neg_local.size());
-            if (any_neg32) neg32.resize(p1.neg_local.size());
-            for (int64_t i = 0; i < n; i++) {
-                int32_t cc = p1.comm_of_pos[i];
-                if (cc < 0) continue;
-                for (int64_t e = negptr[i]; e < negptr[i + 1]; e++) {
-                    neg16[e] = (uint16_t)p1.neg_local[e];
-                    if (any_neg32) neg32[e] = p1.neg_local[e] + p1.comm_off[cc];
-                }
+            nnz_neg = (int64_t)p1.neg_local.size();
+            nnz_pos = (int64_t)p1.pos.size();
+            comm_staged.assign(p1.ncomm, 0);
+            for (int32_t cc = 0; cc < p1.ncomm; cc++) {
+                int64_t lam = p1.comm_off[cc + 1] - p1.comm_off[cc];
+                bool wide = (double)lam > WIDE_COMMUNITY || (o->flags & CIA_FLAG_FORCE_WIDE);
+                comm_staged[cc] = lam <= cap && !wide;
+                if (comm_staged[cc]) nnz_neg_staged += p1.negptr[p1.comm_off[cc + 1]] - p1.negptr[p1.comm_off[cc]];
+            }
+            if (!p1.complete) {
+                RowLists L;
+                L.negptr = &p1.negptr;
+                L.neg = p1.neg_local.data();
+                L.posptr = &p1.posptr;
+                L.pos = p1.pos.data();
+                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, L, sell));
+            } else {
+                std::vector<int64_t> zp(n + 1, 0);
+                RowLists L;
+                L.negptr = &zp;
+                L.posptr = &zp;
+                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, L, sell));
+            }
+            if (s->d0 != 0.0) {
+                // |S+| - |S-| per row (all zero for a complete graph)
+                cnt_old.resize(n);
+                for (int64_t i = 0; i < n; i++)
+                    cnt_old[i] = (int32_t)((p1.posptr[i + 1] - p1.posptr[i]) - (p1.negptr[i + 1] - p1.negptr[i]));
             }
             std::vector<int32_t>().swap(p1.neg_local);
+            std::vector<int32_t>().swap(p1.pos);
         } else {
             // direct method: community order for locality, no remainder split;
             // every node is "outside" and its whole row is the +1 list
@@ -733,50 +957,79 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
             if (g->kind == CIA_GRAPH_COMPLETE) {
                 s->complete_direct = true;
             } else {
-                CIA_TRY(p1_permuted_adjacency(g, p1, posptr, poscol));
-                negptr.assign(n + 1, 0);
+                std::vector<int64_t> arp;
+                std::vector<int32_t> acol;
+                CIA_TRY(p1_permuted_adjacency(g, p1, arp, acol));
+                nnz_pos = arp[n];
+                // rows sorted by degree inside each community segment
+                RowLists L;
+                L.posptr = &arp;
+                L.pos = acol.data();
+                std::vector<char> none(p1.ncomm, 0);
+                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, none, L, sell));
+                if (s->d0 != 0.0) {
+                    cnt_old.resize(n);
+                    for (int64_t i = 0; i < n; i++) cnt_old[i] = (int32_t)(arp[i + 1] - arp[i]);
+                }
             }
         }
     } catch (const std::bad_alloc &) {
         return set_error(CIA_ENOMEM, "host allocation failed");
     }
 
-    // LDS staging capacity (community z values)
-    int64_t maxlam = 0;
-    for (int32_t cc = 0; cc < p1.ncomm; cc++) maxlam = std::max<int64_t>(maxlam, p1.comm_off[cc + 1] - p1.comm_off[cc]);
-    const int64_t zbytes = f64 ? 16 : 8;
-    // total dynamic LDS (staging + per-chunk T values) stays within 64 KB
-    const int64_t tsh_bytes = zbytes * s->block * s->P;
-    int64_t cap = ((int64_t)LDS_STAGE_BYTES - tsh_bytes - 4096) / zbytes;
-    if (cap < 0) cap = 0;
-    if (s->direct) cap = 0;
-    s->lds_cap = (int)std::min<int64_t>(cap, maxlam);
+    // final node order: P1 permutation refined by the in-community sort
+    std::vector<int32_t> perm2(n);
+    if (!s->complete_direct) {
+        for (int64_t i = 0; i < n; i++) perm2[sell.newpos[i]] = p1.perm[i];
+    } else {
+        for (int64_t i = 0; i < n; i++) perm2[i] = p1.perm[i];
+    }
+    std::vector<int32_t> cnt;
+    if (!cnt_old.empty()) {
+        cnt.resize(n);
+        for (int64_t i = 0; i < n; i++) cnt[sell.newpos[i]] = cnt_old[i];
+    }
+
+    int64_t maxlam = 0, maxstaged = 0;
+    for (int32_t cc = 0; cc < p1.ncomm; cc++) {
+        int64_t lam = p1.comm_off[cc + 1] - p1.comm_off[cc];
+        maxlam = std::max<int64_t>(maxlam, lam);
+        if (!s->direct && comm_staged[cc]) maxstaged = std::max<int64_t>(maxstaged, lam);
+    }
+    s->lds_cap = (int)maxstaged;
 
     // work units
     std::vector<Unit> units;
-    std::vector<int32_t> cu_off, cu_list;
+    int32_t nslots = 0;
     if (!s->complete_direct) {
-        P1 q = p1;
-        if (s->direct) {
-            q.ncomm = 0;
-            q.comm_off.assign(1, 0);
-        }
+        const int32_t nc = s->direct ? 0 : p1.ncomm;
         int64_t target = o->unit_work > 0 ? o->unit_work : 16384;
-        make_units(q, negptr, posptr, target, s->block, s->lds_cap,
-                   !s->direct && !(o->flags & CIA_FLAG_NO_LDS), o->flags, units, cu_off, cu_list);
-        s->ncomm = q.ncomm;
+        if (s->direct) {
+            // the direct path has one segment per community too; treat all as outside rows
+            Sell flat;
+            flat.slices = sell.slices;
+            flat.seg_slice_off = {0, (int32_t)sell.slices.size()};
+            nslots = make_units(flat, std::vector<int32_t>{0}, 0, target, 4, comm_staged, o->flags, units);
+        } else {
+            nslots = make_units(sell, p1.comm_off, nc, target, 4, comm_staged, o->flags, units);
+        }
+        s->ncomm = nc;
     }
+    if (f64)
+        for (Unit &u : units) u.flags &= ~UF_WIDE;   // FP64 plans compute everything in FP64
+    for (const Unit &u : units)
+        if (u.flags & UF_WIDE) s->has_wide = true;
     s->nunits = (int32_t)units.size();
-    s->smem = (size_t)zbytes * s->lds_cap + (size_t)zbytes * s->block * s->P;
-    if (s->smem > LDS_STAGE_BYTES) return set_error(CIA_EUNSUPPORTED, "LDS request too large");
+    s->smem = (size_t)zbytes * (s->lds_cap + 1);
+    if (s->smem > LDS_BYTES) return set_error(CIA_EUNSUPPORTED, "LDS request too large");
 
     // info
     cia_plan_info &inf = p->info;
     inf.n = n;
     inf.nnz_graph = p1.nnz_graph;
-    inf.nnz_neg = s->direct ? 0 : (int64_t)neg16.size();
-    inf.nnz_pos = (int64_t)poscol.size();
-    inf.n_unassigned = n - (p1.ncomm ? p1.comm_off[p1.ncomm] : 0);
+    inf.nnz_neg = nnz_neg;
+    inf.nnz_pos = nnz_pos;
+    inf.n_unassigned = s->direct ? n : n - (p1.ncomm ? p1.comm_off[p1.ncomm] : 0);
     inf.ncomm = s->direct ? 0 : p1.ncomm;
     inf.nunits = s->nunits;
     inf.max_comm = (int32_t)maxlam;
@@ -788,62 +1041,51 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     inf.precision = o->precision;
     inf.model = CIA_MODEL_PHASE;
     inf.p = c->p;
-    // algorithmic bytes of one RHS: state in, omega, out, two row pointers
-    // per node, remainder indices (2 B local / 4 B global) and, per node, its
-    // z value written once and read once
     {
-        double per_node = 3.0 * rs + 16.0 + 2.0 * 2 * rs;
-        double idx = s->direct ? 4.0 * inf.nnz_pos : 2.0 * inf.nnz_neg + 4.0 * inf.nnz_pos;
-        if (any_neg32) idx += 2.0 * inf.nnz_neg;
-        inf.bytes_per_rhs = per_node * n + idx;
-        // fused RK stage: theta_n, omega, acc in/out, z in/out, row pointers
-        double stage_node = rs * 4 + 2.0 * 2 * rs + 16.0;
-        inf.bytes_per_stage = stage_node * n + idx;
-        if (s->complete_direct) inf.bytes_per_rhs = inf.bytes_per_stage = (double)n * (2 * 2 * rs + 2 * rs);
+        // Algorithmic bytes (no padding).  Per node and RHS: theta in, omega,
+        // H out, its z written once and read once; per remainder entry its
+        // index (2 B local for LDS-staged communities, else 4 B).  The fused
+        // RK stage replaces "theta in / H out" by theta_n in plus acc in and
+        // out.
+        double idx = 2.0 * (double)nnz_neg_staged + 4.0 * (double)(nnz_neg - nnz_neg_staged) + 4.0 * (double)nnz_pos;
+        double zb = 2.0 * rs;
+        inf.bytes_per_rhs = (3.0 * rs + 2.0 * zb) * (double)n + idx;
+        inf.bytes_per_stage = (4.0 * rs + 2.0 * zb) * (double)n + idx;
+        if (s->complete_direct) inf.bytes_per_rhs = inf.bytes_per_stage = (double)n * (2 * zb + 2 * rs);
     }
 
     // ---- device upload ----
-    std::vector<int32_t> perm32(p1.perm.begin(), p1.perm.end());
-    CIA_TRY(dupload(p, &s->perm, perm32.data(), n));
+    CIA_TRY(dupload(p, &s->perm, perm2.data(), n));
     if (!s->complete_direct) {
+        if (units.empty()) units.push_back(Unit{0, 0, 0, 0, 0, 0, 0, 0});
         CIA_TRY(dupload(p, &s->units, units.data(), units.size()));
-        std::vector<int32_t> coff(p1.comm_off.begin(), p1.comm_off.end());
-        if (coff.empty()) coff.push_back(0);
-        CIA_TRY(dupload(p, &s->comm_off, coff.data(), coff.size()));
-        if (cu_off.empty()) cu_off.push_back(0);
-        CIA_TRY(dupload(p, &s->cu_off, cu_off.data(), cu_off.size()));
-        if (cu_list.empty()) cu_list.push_back(0);
-        CIA_TRY(dupload(p, &s->cu_list, cu_list.data(), cu_list.size()));
-        CIA_TRY(dupload(p, &s->negptr, negptr.data(), negptr.size()));
-        CIA_TRY(dupload(p, &s->posptr, posptr.data(), posptr.size()));
-        if (neg16.empty()) neg16.push_back(0);
-        CIA_TRY(dupload(p, &s->neg16, neg16.data(), neg16.size()));
-        if (any_neg32) CIA_TRY(dupload(p, &s->neg32, neg32.data(), neg32.size()));
-        if (poscol.empty()) poscol.push_back(0);
-        CIA_TRY(dupload(p, &s->pos, poscol.data(), poscol.size()));
+        if (sell.slices.empty()) sell.slices.push_back(Slice{});
+        CIA_TRY(dupload(p, &s->slices, sell.slices.data(), sell.slices.size()));
+        CIA_TRY(dupload(p, &s->negdata, sell.neg.data(), sell.neg.size()));
+        CIA_TRY(dupload(p, &s->posdata, sell.pos.data(), sell.pos.size()));
+        // the kernels read cnt[i] only when d_0 != 0, and then it holds n entries
+        if (s->d0 != 0.0 && (int64_t)cnt.size() != n)
+            return set_error(CIA_EINVAL, "internal: row counts missing for d_0 != 0");
+        if (!cnt.empty()) CIA_TRY(dupload(p, &s->cnt, cnt.data(), cnt.size()));
+        else CIA_TRY(dalloc(p, &s->cnt, 1));
     }
-    {
-        std::vector<int32_t>().swap(poscol);
-        std::vector<uint16_t>().swap(neg16);
-        std::vector<int32_t>().swap(neg32);
-    }
+    std::vector<uint4>().swap(sell.neg);
+    std::vector<uint4>().swap(sell.pos);
     // omega in community order
     if (omega) {
         if (f64) {
             std::vector<double> om(n);
-            for (int64_t i = 0; i < n; i++) om[i] = omega[p1.perm[i]];
+            for (int64_t i = 0; i < n; i++) om[i] = omega[perm2[i]];
             double *d;
             CIA_TRY(dupload(p, &d, om.data(), n));
             s->omega = d;
         } else {
             std::vector<float> om(n);
-            for (int64_t i = 0; i < n; i++) om[i] = (float)omega[p1.perm[i]];
+            for (int64_t i = 0; i < n; i++) om[i] = (float)omega[perm2[i]];
             float *d;
             CIA_TRY(dupload(p, &d, om.data(), n));
             s->omega = d;
         }
-        for (int64_t i = 0; i < n; i++)
-            if (!std::isfinite(omega[i])) return set_error(CIA_EINVAL, "omega[%lld] is not finite", (long long)i);
     }
     unsigned char *raw;
     CIA_TRY(dalloc(p, &raw, rs * n));
@@ -851,13 +1093,15 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     CIA_TRY(dalloc(p, &raw, rs * n));
     s->acc = raw;
     for (int b = 0; b < 2; b++) {
-        CIA_TRY(dalloc(p, &raw, 2 * rs * n));
+        // z arrays carry one extra zero slot at position n (the padding target)
+        CIA_TRY(dalloc(p, &raw, 2 * rs * (n + 1)));
+        CIA_HIP(hipMemset(raw + 2 * rs * n, 0, 2 * rs));
         s->cs[b] = raw;
         if ((wide || (o->flags & CIA_FLAG_FORCE_WIDE)) && !f64) {
             CIA_TRY(dalloc(p, &raw, rs * n));
             s->theta_st[b] = raw;
         }
-        CIA_TRY(dalloc(p, &s->q[b], (size_t)std::max(1, s->nunits) * s->P));
+        CIA_TRY(dalloc(p, &s->q[b], (size_t)std::max(1, nslots) * s->P));
     }
     CIA_TRY(dalloc(p, &s->r_part, (size_t)std::max(1, s->nunits) + 1024));
     if (s->complete_direct) {
@@ -891,18 +1135,14 @@ void phase_free(cia_plan *p) {
 // ---------------------------------------------------------------------------
 
 template <typename R>
-static PhaseArgs<R> base_args(PhaseState *s) {
+static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
     PhaseArgs<R> a;
     std::memset(&a, 0, sizeof(a));
     a.units = s->units;
-    a.comm_off = s->comm_off;
-    a.cu_off = s->cu_off;
-    a.cu_list = s->cu_list;
-    a.negptr = s->negptr;
-    a.neg16 = s->neg16;
-    a.neg32 = s->neg32;
-    a.posptr = s->posptr;
-    a.pos = s->pos;
+    a.slices = s->slices;
+    a.negdata = s->negdata;
+    a.posdata = s->posdata;
+    a.cnt = s->cnt;
     a.perm = s->perm;
     a.omega = static_cast<const R *>(s->omega);
     a.theta_n = static_cast<R *>(s->theta_n);
@@ -915,17 +1155,26 @@ static PhaseArgs<R> base_args(PhaseState *s) {
         a.dcos[k] = (R)s->dcos[k];
     }
     a.lds_cap = s->lds_cap;
+    a.pad_pos = (uint32_t)p->n;
     return a;
+}
+
+template <typename R, int P, int BLOCK>
+static void launch_stage_v(PhaseState *s, const PhaseArgs<R> &a, hipStream_t st) {
+    if (s->direct)
+        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, true, false>), dim3(s->nunits), dim3(BLOCK), s->smem, st, a);
+    else if (sizeof(R) == 4 && s->has_wide)
+        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, true>), dim3(s->nunits), dim3(BLOCK), s->smem, st, a);
+    else
+        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, false>), dim3(s->nunits), dim3(BLOCK), s->smem, st, a);
 }
 
 template <typename R, int P>
 static cia_status launch_stage_p(cia_plan *p, PhaseState *s, const PhaseArgs<R> &a, hipStream_t st, int kind) {
     if (s->nunits == 0) return CIA_OK;
     CIA_TRY(timing_begin(p, st, kind));
-    if (s->block == 512)
-        hipLaunchKernelGGL((phase_stage_kernel<R, P, 512>), dim3(s->nunits), dim3(512), s->smem, st, a);
-    else
-        hipLaunchKernelGGL((phase_stage_kernel<R, P, 256>), dim3(s->nunits), dim3(256), s->smem, st, a);
+    if (s->block == 512) launch_stage_v<R, P, 512>(s, a, st);
+    else launch_stage_v<R, P, 256>(s, a, st);
     CIA_HIP(hipGetLastError());
     return timing_end(p, st);
 }
@@ -1011,7 +1260,7 @@ static cia_status rhs_impl(cia_plan *p, PhaseState *s, const void *state, void *
         CIA_HIP(hipGetLastError());
         return timing_end(p, st);
     }
-    PhaseArgs<R> a = base_args<R>(s);
+    PhaseArgs<R> a = base_args<R>(p, s);
     a.mode = M_PREP;
     a.state_in = static_cast<const R *>(state);
     a.cs_out = static_cast<cx<R> *>(s->cs[0]);
@@ -1019,7 +1268,7 @@ static cia_status rhs_impl(cia_plan *p, PhaseState *s, const void *state, void *
     a.theta_next = static_cast<R *>(s->theta_st[0]);
     a.r_part = s->r_part;
     CIA_TRY(launch_stage<R>(p, s, a, st, KK_PREP));
-    a = base_args<R>(s);
+    a = base_args<R>(p, s);
     a.mode = M_RHS;
     a.cs_in = static_cast<const cx<R> *>(s->cs[0]);
     a.q_in = s->q[0];
@@ -1077,7 +1326,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
             }
         }
     } else {
-        PhaseArgs<R> a = base_args<R>(s);
+        PhaseArgs<R> a = base_args<R>(p, s);
         a.mode = M_PREP;
         a.state_in = static_cast<const R *>(state);
         a.cs_out = static_cast<cx<R> *>(s->cs[0]);
@@ -1090,7 +1339,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         for (int64_t k = 0; k < steps; k++) {
             const int nst = rk4 ? 4 : 1;
             for (int q = 0; q < nst; q++) {
-                a = base_args<R>(s);
+                a = base_args<R>(p, s);
                 a.mode = rk4 ? M_RK4 : M_EULER;
                 a.stage = q;
                 a.dt = (R)dt;
