@@ -138,8 +138,8 @@ struct PhaseArgs {
     const R *omega;
     R *theta_n;               // theta at the start of the step (community order)
     R *acc;                   // RK4 accumulator
-    const R *theta_cur;       // theta of the current stage (wide units only)
-    R *theta_next;            // theta of the next stage (wide units only)
+    const R *th_in;           // theta of the current stage, [n+1] (random gathers, FP64 path)
+    R *th_out;                // theta of the next stage
     const cx<R> *cs_in;       // z of the current stage, [n+1], z[n] = 0
     cx<R> *cs_out;            // z of the next stage
     const double2 *q_in;      // [slots][P] partial observables of the current stage
@@ -172,17 +172,22 @@ __device__ __forceinline__ void acc_z(cx<R> (&T)[P], cx<R> z, R sign) {
     }
 }
 
-// Stream `w` chunks of one lane's row (stride 64 chunks), U in flight.
-// staged: 8 uint16 LDS indices per chunk; otherwise 4 int32 global positions.
-template <typename R, int P, int U, bool STAGED>
+// Stream `w` chunks of one lane's row (stride 64 chunks, U per batch).
+// STAGED: 8 uint16 LDS indices per chunk, one batch in flight (the LDS
+// gathers of a batch give enough independent work).  Otherwise 4 int32
+// global positions per chunk, double-buffered: batch j+1's loads are in
+// flight while batch j's partners are gathered, as z (GATHER_Z) or as theta
+// with z recomputed.
+template <typename R, int P, int U, bool STAGED, bool GATHER_Z>
 __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restrict__ col, int w,
-                                            const cx<R> *zsh, const cx<R> *__restrict__ cs, R sign,
-                                            uint4 padv) {
-    for (int k = 0; k < w; k += U) {
-        uint4 v[U];
+                                            const cx<R> *zsh, const cx<R> *__restrict__ cs,
+                                            const R *__restrict__ th, uint32_t pad, R sign, uint4 padv) {
+    if (w <= 0) return;
+    if (STAGED) {
+        for (int k = 0; k < w; k += U) {
+            uint4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) v[u] = k + u < w ? ld_stream(col + (size_t)(k + u) * SLICE) : padv;
-        if (STAGED) {
+            for (int u = 0; u < U; u++) v[u] = k + u < w ? ld_stream(col + (size_t)(k + u) * SLICE) : padv;
             cx<R> z[U][8];
 #pragma unroll
             for (int u = 0; u < U; u++) {
@@ -197,8 +202,18 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
             for (int u = 0; u < U; u++)
 #pragma unroll
                 for (int q = 0; q < 8; q++) acc_z<R, P>(T, z[u][q], sign);
-        } else {
-            cx<R> z[U][4];
+        }
+        return;
+    }
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) v[u] = u < w ? ld_stream(col + (size_t)u * SLICE) : padv;
+    for (int k = 0; k < w; k += U) {
+        uint4 vn[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) vn[u] = k + U + u < w ? ld_stream(col + (size_t)(k + U + u) * SLICE) : padv;
+        cx<R> z[U][4];
+        if (GATHER_Z) {
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 z[u][0] = cs[v[u].x];
@@ -206,11 +221,35 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
                 z[u][2] = cs[v[u].z];
                 z[u][3] = cs[v[u].w];
             }
+        } else {
+            // theta gathers (half the footprint of z), z recomputed; the
+            // padding position contributes 0
+            R t[U][4];
 #pragma unroll
-            for (int u = 0; u < U; u++)
+            for (int u = 0; u < U; u++) {
+                t[u][0] = th[v[u].x];
+                t[u][1] = th[v[u].y];
+                t[u][2] = th[v[u].z];
+                t[u][3] = th[v[u].w];
+            }
 #pragma unroll
-                for (int q = 0; q < 4; q++) acc_z<R, P>(T, z[u][q], sign);
+            for (int u = 0; u < U; u++) {
+                const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    R sn, cs0;
+                    dsincos(t[u][q], &sn, &cs0);
+                    const bool ok = q4[q] != pad;
+                    z[u][q] = cx<R>{ok ? cs0 : (R)0, ok ? sn : (R)0};
+                }
+            }
         }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc_z<R, P>(T, z[u][q], sign);
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = vn[u];
     }
 }
 
@@ -220,7 +259,8 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
 template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE>
 __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     constexpr int NW = BLOCK / 64;
-    constexpr int U = P >= 4 ? 1 : 4 / P;   // chunks in flight per lane
+    constexpr int UL = P >= 4 ? 1 : 4 / P;  // chunks per batch, LDS-gathered rows
+    constexpr int UG = P >= 2 ? 1 : 2;      // chunks per batch, global-gathered rows (two in flight)
     extern __shared__ __align__(16) unsigned char smem[];
     cx<R> *zsh = reinterpret_cast<cx<R> *>(smem);   // [lds_cap + 1]
     __shared__ double2 qsh[P];
@@ -305,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                 if (a.omega) om = a.omega[i];
                 if (mode == M_RK4 && a.stage > 0) av = a.acc[i];
                 if (a.d0 != (R)0) cv = a.cnt[i];
-                if (WIDE && wide) thc = a.theta_cur[i];
+                if (WIDE && wide) thc = a.th_in[i];
             }
         }
         cx<R> T[P];
@@ -314,11 +354,11 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
         if (gather) {
             if (!DIRECT) {
                 if (staged)
-                    gather_rows<R, P, U, true>(T, a.negdata + S.nbeg + lane, S.nw, zsh, a.cs_in, (R)-1, padl);
+                    gather_rows<R, P, UL, true, false>(T, a.negdata + S.nbeg + lane, S.nw, zsh, a.cs_in, a.th_in, a.pad_pos, (R)-1, padl);
                 else
-                    gather_rows<R, P, U, false>(T, a.negdata + S.nbeg + lane, S.nw, zsh, a.cs_in, (R)-1, padp);
+                    gather_rows<R, P, UG, false, false>(T, a.negdata + S.nbeg + lane, S.nw, zsh, a.cs_in, a.th_in, a.pad_pos, (R)-1, padp);
             }
-            gather_rows<R, P, U, false>(T, a.posdata + S.pbeg + lane, S.pw, zsh, a.cs_in, (R)1, padp);
+            gather_rows<R, P, UG, false, DIRECT>(T, a.posdata + S.pbeg + lane, S.pw, zsh, a.cs_in, a.th_in, a.pad_pos, (R)1, padp);
         }
 
         // ---- combine (eq. FastHdense + E2), stage update, next z ----
@@ -391,7 +431,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                 double zs, zc0;
                 sincos((double)theta_new, &zs, &zc0);
                 a.cs_out[i] = cx<R>{(R)zc0, (R)zs};
-                a.theta_next[i] = theta_new;
+                a.th_out[i] = theta_new;
                 cx<double> z = {zc0, zs}, zk = z;
 #pragma unroll
                 for (int k = 0; k < P; k++) {
@@ -406,6 +446,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                 dsincos(theta_new, &zs, &zc0);
                 cx<R> z = {zc0, zs};
                 a.cs_out[i] = z;
+                if (!DIRECT) a.th_out[i] = theta_new;
                 if (assigned) {
                     cx<R> zk = z;
 #pragma unroll
@@ -643,7 +684,7 @@ struct PhaseState {
     Slice *slices = nullptr;
     uint4 *negdata = nullptr, *posdata = nullptr;
     int32_t *cnt = nullptr, *perm = nullptr;
-    void *omega = nullptr, *theta_n = nullptr, *acc = nullptr, *theta_st[2] = {nullptr, nullptr};
+    void *omega = nullptr, *theta_n = nullptr, *acc = nullptr, *th[2] = {nullptr, nullptr};
     void *cs[2] = {nullptr, nullptr};
     double2 *q[2] = {nullptr, nullptr};
     double2 *r_part = nullptr;
@@ -796,9 +837,11 @@ static int32_t make_units(const Sell &sell, const std::vector<int32_t> &comm_off
         int64_t work;
         int32_t comm;
     };
+    // cost of a slice in chunk units: its chunks plus a fixed cost for the
+    // combine operands and the row-order round trips
     auto sw = [&](int32_t k) -> int64_t {
         const Slice &S = sell.slices[k];
-        return (int64_t)(S.nw + S.pw + 2) * SLICE;
+        return (int64_t)(S.nw + S.pw + 16) * SLICE;
     };
     std::vector<std::vector<U2>> groups;
     auto make_group = [&](int32_t k0, int32_t k1, int32_t comm, int64_t off, int64_t lam) {
@@ -1097,10 +1140,10 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         CIA_TRY(dalloc(p, &raw, 2 * rs * (n + 1)));
         CIA_HIP(hipMemset(raw + 2 * rs * n, 0, 2 * rs));
         s->cs[b] = raw;
-        if ((wide || (o->flags & CIA_FLAG_FORCE_WIDE)) && !f64) {
-            CIA_TRY(dalloc(p, &raw, rs * n));
-            s->theta_st[b] = raw;
-        }
+        // stage theta (random S-pos gathers and the FP64 path), with a zero slot
+        CIA_TRY(dalloc(p, &raw, rs * (n + 1)));
+        CIA_HIP(hipMemset(raw + rs * n, 0, rs));
+        s->th[b] = raw;
         CIA_TRY(dalloc(p, &s->q[b], (size_t)std::max(1, nslots) * s->P));
     }
     CIA_TRY(dalloc(p, &s->r_part, (size_t)std::max(1, s->nunits) + 1024));
@@ -1265,14 +1308,14 @@ static cia_status rhs_impl(cia_plan *p, PhaseState *s, const void *state, void *
     a.state_in = static_cast<const R *>(state);
     a.cs_out = static_cast<cx<R> *>(s->cs[0]);
     a.q_out = s->q[0];
-    a.theta_next = static_cast<R *>(s->theta_st[0]);
+    a.th_out = static_cast<R *>(s->th[0]);
     a.r_part = s->r_part;
     CIA_TRY(launch_stage<R>(p, s, a, st, KK_PREP));
     a = base_args<R>(p, s);
     a.mode = M_RHS;
     a.cs_in = static_cast<const cx<R> *>(s->cs[0]);
     a.q_in = s->q[0];
-    a.theta_cur = static_cast<const R *>(s->theta_n);
+    a.th_in = static_cast<const R *>(s->th[0]);
     a.state_out = static_cast<R *>(dstate);
     return launch_stage<R>(p, s, a, st, KK_STAGE);
 }
@@ -1331,7 +1374,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         a.state_in = static_cast<const R *>(state);
         a.cs_out = static_cast<cx<R> *>(s->cs[0]);
         a.q_out = s->q[0];
-        a.theta_next = static_cast<R *>(s->theta_st[0]);
+        a.th_out = static_cast<R *>(s->th[0]);
         a.r_part = s->r_part;
         a.want_r = want_r;
         CIA_TRY(launch_stage<R>(p, s, a, st, KK_PREP));
@@ -1347,8 +1390,8 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
                 a.cs_out = static_cast<cx<R> *>(s->cs[cur ^ 1]);
                 a.q_in = s->q[cur];
                 a.q_out = s->q[cur ^ 1];
-                a.theta_cur = static_cast<const R *>(q == 0 ? s->theta_n : s->theta_st[cur]);
-                a.theta_next = static_cast<R *>(s->theta_st[cur ^ 1]);
+                a.th_in = static_cast<const R *>(s->th[cur]);
+                a.th_out = static_cast<R *>(s->th[cur ^ 1]);
                 a.r_part = s->r_part;
                 a.want_r = want_r && q == nst - 1;
                 CIA_TRY(launch_stage<R>(p, s, a, st, KK_STAGE));
