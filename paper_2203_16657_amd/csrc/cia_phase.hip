@@ -1046,7 +1046,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     int32_t nslots = 0;
     if (!s->complete_direct) {
         const int32_t nc = s->direct ? 0 : p1.ncomm;
-        int64_t target = o->unit_work > 0 ? o->unit_work : 16384;
+        int64_t target = o->unit_work > 0 ? o->unit_work : 32768;
         if (s->direct) {
             // the direct path has one segment per community too; treat all as outside rows
             Sell flat;
