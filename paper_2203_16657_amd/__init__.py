@@ -295,6 +295,31 @@ class Plan:
         h = cia_build(g, labels, c, omega, o)
         return cls(h, int(n), precision, CIA_MODEL_PHASE)
 
+    @classmethod
+    def triadic(cls, n, row_ptr, col, labels, omega=None, K1=1.0, K2=1.0, tri_seed=0, p_tri=0.9,
+                cross_tri=None, method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4, flags=0,
+                unit_work=0, block=0, device=-1):
+        """Higher-order Kuramoto model on a hypergraph: pairwise sine coupling
+        (K1/N) plus the triadic term (K2/N^2); intra-community triples by the
+        seeded predicate with probability p_tri, cross triples listed."""
+        load()
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        g = cia_graph(n=int(n), kind=CIA_GRAPH_CSR, reserved=0, row_ptr=_np_ptr(rp), col=_np_ptr(cl))
+        tri = np.ascontiguousarray(np.zeros((0, 3)) if cross_tri is None else cross_tri, dtype=np.int32)
+        h = cia_hypergraph(seed=int(tri_seed) & 0xFFFFFFFFFFFFFFFF, p_intra=float(p_tri), ntri=len(tri),
+                           tri=_np_ptr(tri) if len(tri) else None)
+        c = cia_coupling_default()
+        c.model = CIA_MODEL_TRIADIC
+        c.K = float(K1)
+        c.K2 = float(K2)
+        c.hyper = ctypes.cast(ctypes.pointer(h), _vp)
+        o = cia_options_default()
+        o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
+        o.unit_work, o.block, o.device = unit_work, block, device
+        handle = cia_build(g, labels, c, omega, o)
+        return cls(handle, int(n), precision, CIA_MODEL_TRIADIC)
+
     @property
     def dtype_np(self):
         return np.float64 if self.precision == CIA_F64 else np.float32

@@ -117,8 +117,8 @@ cia_status cia_build(const cia_graph *g, const int32_t *labels, const cia_coupli
     if (st == CIA_OK) {
         try {
             switch (c->model) {
-                case CIA_MODEL_PHASE: st = phase_build(p, g, labels, c, omega, o); break;
-                case CIA_MODEL_TRIADIC:
+                case CIA_MODEL_PHASE:
+                case CIA_MODEL_TRIADIC: st = phase_build(p, g, labels, c, omega, o); break;
                 case CIA_MODEL_FLOCK:
                     st = set_error(CIA_EUNSUPPORTED, "model %d is not available in this build", c->model);
                     break;
@@ -147,7 +147,8 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     cia_status st;
     switch (p->model) {
-        case CIA_MODEL_PHASE: st = phase_rhs(p, state, dstate, s); break;
+        case CIA_MODEL_PHASE:
+        case CIA_MODEL_TRIADIC: st = phase_rhs(p, state, dstate, s); break;
         default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
     }
     if (st == CIA_OK && (p->flags & CIA_FLAG_TIMING)) st = timing_collect(p);
@@ -165,7 +166,8 @@ cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, dou
     hipStream_t s = static_cast<hipStream_t>(stream);
     cia_status st;
     switch (p->model) {
-        case CIA_MODEL_PHASE: st = phase_integrate(p, state, dt, steps, r_trace, s); break;
+        case CIA_MODEL_PHASE:
+        case CIA_MODEL_TRIADIC: st = phase_integrate(p, state, dt, steps, r_trace, s); break;
         default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
     }
     if (st == CIA_OK && (p->flags & CIA_FLAG_TIMING)) st = timing_collect(p);

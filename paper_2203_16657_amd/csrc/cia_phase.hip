@@ -53,14 +53,15 @@ constexpr int UF_STAGED = 1;   // community z staged in LDS, S-neg as uint16 loc
 constexpr int UF_WIDE = 2;     // FP64 observables and combine (F32 plans)
 constexpr int UF_ASSIGNED = 4; // rows of a dense community (E1 applies)
 
-// 64 rows of one community; chunk k of lane l sits at beg + 64 k + l.
+// 64 rows of one community; chunk k of lane l of stream q sits at
+// beg[q] + 64 k + l.  Streams: 0 = S-neg, 1 = S-pos (pairwise remainder),
+// 2 = missing intra-community hyperedges, 3 = hyperedges across communities
+// (triadic model; each entry a partner pair).
 struct alignas(16) Slice {
     int32_t row0, rows;   // first row (community order), number of rows (1..64)
-    uint32_t nbeg;        // S-neg block: first chunk, chunks per lane
-    int32_t nw;
-    uint32_t pbeg;        // S-pos block
-    int32_t pw;
-    int32_t r0, r1;       // unused (keeps the descriptor at 32 bytes)
+    uint32_t beg[4];      // first 16-byte chunk of each stream's block
+    int32_t w[4];         // chunks per lane of each stream
+    int32_t pad0, pad1;   // keeps the descriptor at 48 bytes
 };
 
 // A work unit (one block): a run of slices of one community or of the rows
@@ -81,6 +82,15 @@ struct cx {
 template <typename R>
 __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// key of a triple of user ids: sorted a < b < c packed as a | b << 21 | c << 42
+__host__ __device__ static inline uint64_t triple_key(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t t;
+    if (a > b) { t = a; a = b; b = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    if (a > b) { t = a; a = b; b = t; }
+    return (uint64_t)a | ((uint64_t)b << 21) | ((uint64_t)c << 42);
 }
 
 __device__ __forceinline__ void dsincos(float t, float *s, float *c) { sincosf(t, s, c); }
@@ -133,6 +143,9 @@ struct PhaseArgs {
     const Slice *slices;
     const uint4 *negdata;     // S-neg slice blocks
     const uint4 *posdata;     // S-pos slice blocks
+    const uint4 *tnegdata;    // missing intra-community hyperedges (triadic)
+    const uint4 *tposdata;    // hyperedges across communities (triadic)
+    const cx<R> *h_extra;     // direct triadic: sum over present intra pairs of z_j z_k
     const int32_t *cnt;       // [n] |S+| - |S-| per row (only when d_0 != 0)
     const int32_t *perm;      // community order -> user order
     const R *omega;
@@ -148,6 +161,7 @@ struct PhaseArgs {
     const R *state_in;        // user order (M_PREP)
     R *state_out;             // user order (M_RHS)
     R Kn, dt, d0, hzero;
+    R K2n;                    // triadic strength K2 / N^2
     R dsin[PMAX + 1], dcos[PMAX + 1];
     int32_t stage, mode, want_r, lds_cap;
     uint32_t pad_pos;         // position whose z is 0 (= n): target of padded int32 entries
@@ -253,10 +267,52 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
     }
 }
 
+// Stream a lane's list of partner pairs (j, k) and return sum z_j z_k.
+// STAGED: 4 pairs of uint16 local indices per chunk (LDS gathers, pad
+// lambda holds 0); otherwise 2 pairs of int32 positions per chunk, gathered
+// as z (GATHER_Z) or as theta with z recomputed; pad position contributes 0.
+template <typename R, int U, bool STAGED, bool GATHER_Z>
+__device__ __forceinline__ cx<R> gather_pairs(const uint4 *__restrict__ col, int w, const cx<R> *zsh,
+                                              const cx<R> *__restrict__ cs, const R *__restrict__ th,
+                                              uint32_t pad, uint4 padv) {
+    cx<R> M = {(R)0, (R)0};
+    auto zof = [&](uint32_t j) -> cx<R> {
+        if (GATHER_Z) return cs[j];
+        R sn, c0;
+        dsincos(th[j], &sn, &c0);
+        return j != pad ? cx<R>{c0, sn} : cx<R>{(R)0, (R)0};
+    };
+    for (int k = 0; k < w; k += U) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = k + u < w ? ld_stream(col + (size_t)(k + u) * SLICE) : padv;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (STAGED) {
+                const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const cx<R> p = cmul(zsh[q4[q] & 0xffffu], zsh[q4[q] >> 16]);
+                    M.x += p.x;
+                    M.y += p.y;
+                }
+            } else {
+                const cx<R> p0 = cmul(zof(v[u].x), zof(v[u].y));
+                const cx<R> p1 = cmul(zof(v[u].z), zof(v[u].w));
+                M.x += p0.x + p1.x;
+                M.y += p0.y + p1.y;
+            }
+        }
+    }
+    return M;
+}
+
 // DIRECT: every row is an outside row with its whole adjacency in the +1
 // list (no observables, no staging).  WIDE: the FP64 path of very large
 // communities is compiled in (F32 plans that have such communities).
-template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE>
+// TRI: the triadic term of the higher-order model (P = 2 observables give
+// S1 = sum z and S2 = sum z^2 per community).
+template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE, bool TRI>
 __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     constexpr int NW = BLOCK / 64;
     constexpr int UL = P >= 4 ? 1 : 4 / P;  // chunks per batch, LDS-gathered rows
@@ -354,11 +410,24 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
         if (gather) {
             if (!DIRECT) {
                 if (staged)
-                    gather_rows<R, P, UL, true, false>(T, a.negdata + S.nbeg + lane, S.nw, zsh, a.cs_in, a.th_in, a.pad_pos, (R)-1, padl);
+                    gather_rows<R, P, UL, true, false>(T, a.negdata + S.beg[0] + lane, S.w[0], zsh, a.cs_in, a.th_in, a.pad_pos, (R)-1, padl);
                 else
-                    gather_rows<R, P, UG, false, false>(T, a.negdata + S.nbeg + lane, S.nw, zsh, a.cs_in, a.th_in, a.pad_pos, (R)-1, padp);
+                    gather_rows<R, P, UG, false, false>(T, a.negdata + S.beg[0] + lane, S.w[0], zsh, a.cs_in, a.th_in, a.pad_pos, (R)-1, padp);
             }
-            gather_rows<R, P, UG, false, DIRECT>(T, a.posdata + S.pbeg + lane, S.pw, zsh, a.cs_in, a.th_in, a.pad_pos, (R)1, padp);
+            gather_rows<R, P, UG, false, DIRECT>(T, a.posdata + S.beg[1] + lane, S.w[1], zsh, a.cs_in, a.th_in, a.pad_pos, (R)1, padp);
+        }
+        cx<R> Mt = {(R)0, (R)0}, Xt = {(R)0, (R)0};   // missing intra / cross hyperedge pair sums
+        if (TRI && gather) {
+            if (!DIRECT) {
+                if (staged)
+                    Mt = gather_pairs<R, 2, true, false>(a.tnegdata + S.beg[2] + lane, S.w[2], zsh, a.cs_in, a.th_in,
+                                                          a.pad_pos, padl);
+                else
+                    Mt = gather_pairs<R, 2, false, false>(a.tnegdata + S.beg[2] + lane, S.w[2], zsh, a.cs_in, a.th_in,
+                                                           a.pad_pos, padp);
+            }
+            Xt = gather_pairs<R, 2, false, DIRECT>(a.tposdata + S.beg[3] + lane, S.w[3], zsh, a.cs_in, a.th_in,
+                                                   a.pad_pos, padp);
         }
 
         // ---- combine (eq. FastHdense + E2), stage update, next z ----
@@ -384,6 +453,27 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                         if (k + 1 < P) zk = cmul(zk, z);
                     }
                     H = om + a.Kn * s;
+                    if (TRI) {
+                        // sum over ordered distinct partner pairs of z_j z_k, then
+                        // Im(conj(z_m)^2 * .) (App. A.7 with lambda = (1,1,-2))
+                        const cx<R> z2 = cmul(z, z);
+                        cx<R> D;
+                        if (DIRECT) {
+                            const cx<R> E = a.h_extra[i];
+                            D = cx<R>{(R)2 * (E.x + Xt.x), (R)2 * (E.y + Xt.y)};
+                        } else {
+                            D = cx<R>{(R)0, (R)0};
+                            if (assigned) {
+                                const cx<R> A1 = {qx[0] - z.x, qy[0] - z.y};
+                                const cx<R> A2 = {qx[1] - z2.x, qy[1] - z2.y};
+                                const cx<R> A11 = cmul(A1, A1);
+                                D = cx<R>{A11.x - A2.x, A11.y - A2.y};
+                            }
+                            D.x += (R)2 * (Xt.x - Mt.x);
+                            D.y += (R)2 * (Xt.y - Mt.y);
+                        }
+                        H += a.K2n * cmul(D, cx<R>{z2.x, -z2.y}).y;
+                    }
                 } else {
                     // FP64 observables and combine for very large communities
                     double zs, zc0;
@@ -535,6 +625,53 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     }
 }
 
+// Direct triadic baseline: for every centre, the sum of z_j z_k over the
+// present intra-community hyperedges {m, j, k}, j < k, found by evaluating
+// the hyperedge predicate for every pair of the community (O(lambda^2) per
+// centre).  One block per (community, 256 centres); z and user ids staged.
+struct alignas(16) TriBlock {
+    int32_t off, lam, row0, rows;
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void triadic_present_kernel(const TriBlock *blocks, const int32_t *perm,
+                                                              const cx<R> *cs, uint64_t seed, uint64_t thr,
+                                                              cx<R> *out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const TriBlock B = blocks[blockIdx.x];
+    cx<R> *zs = reinterpret_cast<cx<R> *>(smem);
+    uint32_t *us = reinterpret_cast<uint32_t *>(smem + sizeof(cx<R>) * B.lam);
+    for (int j = threadIdx.x; j < B.lam; j += 256) {
+        zs[j] = cs[B.off + j];
+        us[j] = (uint32_t)perm[B.off + j];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x >= B.rows) return;
+    const int i = B.row0 + threadIdx.x;
+    const int me = i - B.off;
+    const uint32_t ui = us[me];
+    cx<R> E = {(R)0, (R)0};
+    for (int x = 0; x < B.lam; x++) {
+        if (x == me) continue;
+        const uint32_t ux = us[x];
+        const cx<R> zx = zs[x];
+        for (int y = x + 1; y < B.lam; y++) {
+            if (y == me) continue;
+            const uint64_t key = triple_key(ui, ux, us[y]);
+            uint64_t z = (seed ^ key) + 0x9E3779B97F4A7C15ULL;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+            z ^= z >> 31;
+            if (z < thr) {
+                const cx<R> p = cmul(zx, zs[y]);
+                E.x += p.x;
+                E.y += p.y;
+            }
+        }
+    }
+    out[i] = E;
+}
+
 // r(t) = |(1/N) sum z| from the unit partials, fixed order, one block.
 __global__ __launch_bounds__(256) void order_reduce_kernel(const double2 *r_part, int nunits,
                                                            double invN, double *r_out) {
@@ -674,6 +811,13 @@ struct PhaseState {
     bool f64 = false, direct = false, complete_direct = false;
     int block = 256;
     bool has_wide = false;   // F32 plan with at least one FP64-observable community
+    bool tri = false;        // triadic model
+    double K2n = 0;
+    uint64_t tri_seed = 0, tri_thr = 0;
+    TriBlock *tri_blocks = nullptr;   // direct triadic: (community, centres) blocks
+    int32_t ntri_blocks = 0;
+    size_t tri_smem = 0;
+    void *h_extra = nullptr;
     int32_t nunits = 0, ncomm = 0;
     int lds_cap = 0;
     size_t smem = 0;
@@ -682,7 +826,7 @@ struct PhaseState {
     // device
     Unit *units = nullptr;
     Slice *slices = nullptr;
-    uint4 *negdata = nullptr, *posdata = nullptr;
+    uint4 *negdata = nullptr, *posdata = nullptr, *tnegdata = nullptr, *tposdata = nullptr;
     int32_t *cnt = nullptr, *perm = nullptr;
     void *omega = nullptr, *theta_n = nullptr, *acc = nullptr, *th[2] = {nullptr, nullptr};
     void *cs[2] = {nullptr, nullptr};
@@ -694,123 +838,127 @@ struct PhaseState {
     void *coef = nullptr;   // [2][PMAX+1] device copy of dsin/dcos (all-to-all kernel)
 };
 
-// Row lists handed to the packer: old-order CSR of remainder entries.
-struct RowLists {
-    const std::vector<int64_t> *negptr = nullptr;   // may be null (no S-neg)
-    const int32_t *neg = nullptr;                   // local index inside the row's community
-    const std::vector<int64_t> *posptr = nullptr;
-    const int32_t *pos = nullptr;                   // old positions
+// Row lists handed to the packer: old-order CSR lists of up to four streams.
+// Stream entries are either local indices inside the row's community
+// (`local`) or old positions; pair streams hold two ints per entry.
+struct StreamIn {
+    const std::vector<int64_t> *ptr = nullptr;   // [n+1] in entries (null: empty stream)
+    const int32_t *val = nullptr;
+    bool local = false;
+    bool pair = false;
 };
 
 struct Sell {
-    std::vector<int32_t> newpos;   // old position -> new position
+    std::vector<int32_t> newpos;          // old position -> new position
     std::vector<Slice> slices;
     std::vector<int32_t> seg_slice_off;   // segment -> first slice
-    std::vector<uint4> neg, pos;
+    std::vector<uint4> data[4];
 };
 
-// Order rows inside every segment by decreasing remainder length, cut the
-// segments into 64-row slices and pack the sliced blocks.  Segments are the
-// communities [comm_off[c], comm_off[c+1]) and the tail of rows outside every
-// community; seg_staged[c] selects uint16 local indices for S-neg.
+// Order rows inside every segment by decreasing remainder work, cut the
+// segments into 64-row slices and pack the sliced blocks of every stream.
+// Segments are the communities [comm_off[c], comm_off[c+1]) and the tail of
+// rows outside every community.  In segments with seg_staged[c], local
+// entries are stored as uint16 indices (8 per chunk, pairs 4 per chunk, pad
+// lambda); everything else as int32 new positions (4 per chunk, pairs 2 per
+// chunk, pad n).
 static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, int32_t ncomm,
-                             const std::vector<char> &seg_staged, const RowLists &L, Sell &out) {
+                             const std::vector<char> &seg_staged, const StreamIn (&S)[4], Sell &out) {
     const int32_t nseg = ncomm + 1;
     std::vector<int64_t> sb(nseg + 1);
     for (int32_t c = 0; c <= ncomm; c++) sb[c] = c < ncomm ? comm_off[c] : (ncomm ? comm_off[ncomm] : 0);
     sb[nseg] = n;
-    auto nneg = [&](int64_t i) -> int64_t { return L.negptr ? (*L.negptr)[i + 1] - (*L.negptr)[i] : 0; };
-    auto npos = [&](int64_t i) -> int64_t { return (*L.posptr)[i + 1] - (*L.posptr)[i]; };
+    auto len = [&](int q, int64_t i) -> int64_t { return S[q].ptr ? (*S[q].ptr)[i + 1] - (*S[q].ptr)[i] : 0; };
+    // entries per 16-byte chunk of stream q in segment c
+    auto per = [&](int q, int32_t c) -> int64_t {
+        const bool st = c < ncomm && seg_staged[c] && S[q].local;
+        const int64_t eb = (st ? 2 : 4) * (S[q].pair ? 2 : 1);
+        return 16 / eb;
+    };
+    auto chunks = [&](int q, int32_t c, int64_t i) -> int64_t { return (len(q, i) + per(q, c) - 1) / per(q, c); };
     out.newpos.resize(n);
     std::vector<int32_t> oldpos(n);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t c = 0; c < nseg; c++) {
         const int64_t b = sb[c], e = sb[c + 1];
-        const int64_t per = (c < ncomm && seg_staged[c]) ? 8 : 4;
-        std::vector<int32_t> idx(e - b);
-        for (int64_t k = 0; k < e - b; k++) idx[k] = (int32_t)(b + k);
-        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
-            int64_t nx = (nneg(x) + per - 1) / per, ny = (nneg(y) + per - 1) / per;
-            if (nx != ny) return nx > ny;
-            return (npos(x) + 3) / 4 > (npos(y) + 3) / 4;
-        });
+        std::vector<int64_t> key(e - b);
         for (int64_t k = 0; k < e - b; k++) {
-            oldpos[b + k] = idx[k];
-            out.newpos[idx[k]] = (int32_t)(b + k);
+            key[k] = 0;
+            for (int q = 0; q < 4; q++) key[k] += chunks(q, c, b + k);
+        }
+        std::vector<int32_t> idx(e - b);
+        for (int64_t k = 0; k < e - b; k++) idx[k] = (int32_t)k;
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return key[x] > key[y]; });
+        for (int64_t k = 0; k < e - b; k++) {
+            oldpos[b + k] = (int32_t)(b + idx[k]);
+            out.newpos[b + idx[k]] = (int32_t)(b + k);
         }
     }
     // slices and their widths
     out.slices.clear();
     out.seg_slice_off.assign(nseg + 1, 0);
-    uint64_t ntot = 0, ptot = 0;
+    uint64_t tot[4] = {0, 0, 0, 0};
     for (int32_t c = 0; c < nseg; c++) {
         out.seg_slice_off[c] = (int32_t)out.slices.size();
-        const int64_t per = (c < ncomm && seg_staged[c]) ? 8 : 4;
         for (int64_t r = sb[c]; r < sb[c + 1]; r += SLICE) {
-            Slice S{};
-            S.row0 = (int32_t)r;
-            S.rows = (int32_t)std::min<int64_t>(SLICE, sb[c + 1] - r);
-            int64_t nw = 0, pw = 0;
-            for (int l = 0; l < S.rows; l++) {
-                int64_t o = oldpos[r + l];
-                nw = std::max(nw, (nneg(o) + per - 1) / per);
-                pw = std::max(pw, (npos(o) + 3) / 4);
+            Slice Sl{};
+            Sl.row0 = (int32_t)r;
+            Sl.rows = (int32_t)std::min<int64_t>(SLICE, sb[c + 1] - r);
+            for (int q = 0; q < 4; q++) {
+                int64_t w = 0;
+                for (int l = 0; l < Sl.rows; l++) w = std::max(w, chunks(q, c, oldpos[r + l]));
+                Sl.beg[q] = (uint32_t)tot[q];
+                Sl.w[q] = (int32_t)w;
+                tot[q] += (uint64_t)w * SLICE;
+                if (tot[q] > 0xffffffffULL) return set_error(CIA_EUNSUPPORTED, "remainder stream above 64 GiB");
             }
-            S.nbeg = (uint32_t)ntot;
-            S.nw = (int32_t)nw;
-            S.pbeg = (uint32_t)ptot;
-            S.pw = (int32_t)pw;
-            ntot += (uint64_t)nw * SLICE;
-            ptot += (uint64_t)pw * SLICE;
-            if (ntot > 0xffffffffULL || ptot > 0xffffffffULL)
-                return set_error(CIA_EUNSUPPORTED, "remainder stream above 64 GiB");
-            out.slices.push_back(S);
+            out.slices.push_back(Sl);
         }
     }
     out.seg_slice_off[nseg] = (int32_t)out.slices.size();
     try {
-        out.neg.resize(std::max<uint64_t>(ntot, 1));
-        out.pos.resize(std::max<uint64_t>(ptot, 1));
+        for (int q = 0; q < 4; q++) out.data[q].resize(std::max<uint64_t>(tot[q], 1));
     } catch (const std::bad_alloc &) {
         return set_error(CIA_ENOMEM, "host allocation of the sliced remainder failed");
     }
-    // fill, slice by slice
     const int64_t nsl = (int64_t)out.slices.size();
     std::vector<int32_t> seg_of_slice(nsl);
     for (int32_t c = 0; c < nseg; c++)
         for (int32_t k = out.seg_slice_off[c]; k < out.seg_slice_off[c + 1]; k++) seg_of_slice[k] = c;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nsl; k++) {
-        const Slice &S = out.slices[k];
+        const Slice &Sl = out.slices[k];
         const int32_t c = seg_of_slice[k];
-        const bool st = c < ncomm && seg_staged[c];
         const int64_t off = sb[c], lam = sb[c + 1] - sb[c];
-        uint32_t *nw32 = reinterpret_cast<uint32_t *>(out.neg.data() + S.nbeg);
-        uint16_t *nw16 = reinterpret_cast<uint16_t *>(out.neg.data() + S.nbeg);
-        uint32_t *pw32 = reinterpret_cast<uint32_t *>(out.pos.data() + S.pbeg);
-        for (int l = 0; l < SLICE; l++) {
-            const int64_t o = l < S.rows ? oldpos[S.row0 + l] : -1;
-            // S-neg
-            const int64_t nn = o >= 0 ? nneg(o) : 0;
-            if (st) {
-                for (int64_t q = 0; q < (int64_t)S.nw * 8; q++) {
-                    uint16_t v = (uint16_t)lam;
-                    if (q < nn) v = (uint16_t)(out.newpos[off + L.neg[(*L.negptr)[o] + q]] - off);
-                    nw16[((q / 8) * SLICE + l) * 8 + (q % 8)] = v;
+        for (int q = 0; q < 4; q++) {
+            if (!S[q].ptr || Sl.w[q] == 0) continue;
+            const int64_t pc = per(q, c);
+            const bool st16 = c < ncomm && seg_staged[c] && S[q].local;
+            const int ne = S[q].pair ? 2 : 1;   // ints per entry
+            uint16_t *w16 = reinterpret_cast<uint16_t *>(out.data[q].data() + Sl.beg[q]);
+            uint32_t *w32 = reinterpret_cast<uint32_t *>(out.data[q].data() + Sl.beg[q]);
+            for (int l = 0; l < SLICE; l++) {
+                const int64_t o = l < Sl.rows ? oldpos[Sl.row0 + l] : -1;
+                const int64_t nn = o >= 0 ? len(q, o) : 0;
+                const int32_t *src = o >= 0 ? S[q].val + (*S[q].ptr)[o] * ne : nullptr;
+                for (int64_t e = 0; e < (int64_t)Sl.w[q] * pc; e++) {
+                    const int64_t chunk = e / pc, slot = e % pc;
+                    for (int t = 0; t < ne; t++) {
+                        const int64_t word = ((chunk * SLICE + l) * pc + slot) * ne + t;
+                        if (st16) {
+                            uint16_t v = (uint16_t)lam;
+                            if (e < nn) v = (uint16_t)(out.newpos[off + src[e * ne + t]] - off);
+                            w16[word] = v;
+                        } else {
+                            uint32_t v = (uint32_t)n;
+                            if (e < nn) {
+                                const int64_t old = S[q].local ? off + src[e * ne + t] : src[e * ne + t];
+                                v = (uint32_t)out.newpos[old];
+                            }
+                            w32[word] = v;
+                        }
+                    }
                 }
-            } else {
-                for (int64_t q = 0; q < (int64_t)S.nw * 4; q++) {
-                    uint32_t v = (uint32_t)n;
-                    if (q < nn) v = (uint32_t)out.newpos[off + L.neg[(*L.negptr)[o] + q]];
-                    nw32[((q / 4) * SLICE + l) * 4 + (q % 4)] = v;
-                }
-            }
-            // S-pos
-            const int64_t np = o >= 0 ? npos(o) : 0;
-            for (int64_t q = 0; q < (int64_t)S.pw * 4; q++) {
-                uint32_t v = (uint32_t)n;
-                if (q < np) v = (uint32_t)out.newpos[L.pos[(*L.posptr)[o] + q]];
-                pw32[((q / 4) * SLICE + l) * 4 + (q % 4)] = v;
             }
         }
     }
@@ -841,7 +989,7 @@ static int32_t make_units(const Sell &sell, const std::vector<int32_t> &comm_off
     // combine operands and the row-order round trips
     auto sw = [&](int32_t k) -> int64_t {
         const Slice &S = sell.slices[k];
-        return (int64_t)(S.nw + S.pw + 16) * SLICE;
+        return (int64_t)(S.w[0] + S.w[1] + S.w[2] + S.w[3] + 16) * SLICE;
     };
     std::vector<std::vector<U2>> groups;
     auto make_group = [&](int32_t k0, int32_t k1, int32_t comm, int64_t off, int64_t lam) {
@@ -912,6 +1060,107 @@ static int32_t make_units(const Sell &sell, const std::vector<int32_t> &comm_off
     return slot;
 }
 
+// ---------------------------------------------------------------------------
+// triadic model: hyperedge lists per centre (App. A.7 on a hypergraph)
+// ---------------------------------------------------------------------------
+
+// splitmix64 output for state x (Steele, Lea, Flood, OOPSLA 2014)
+static inline uint64_t splitmix64_out(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+static uint64_t triple_threshold(double p) {
+    if (p <= 0.0) return 0;
+    if (p >= 1.0) return UINT64_MAX;
+    return (uint64_t)std::ldexp(p, 64);
+}
+
+// For every centre of every community: the partner pairs (j, k), j < k, of
+// intra-community triples that are NOT hyperedges (local indices packed as
+// two int32 per entry), and, for every centre, the partner pairs of the
+// explicit cross-community hyperedges (old positions).  Lists are in P1's
+// (old) position order.
+static cia_status triadic_lists(const P1 &p1, const cia_hypergraph *h, bool want_missing,
+                                std::vector<int64_t> &mptr, std::vector<int32_t> &mval,
+                                std::vector<int64_t> &xptr, std::vector<int32_t> &xval, int64_t &n_missing) {
+    const int64_t n = p1.n;
+    const uint64_t thr = triple_threshold(h->p_intra);
+    const uint64_t seed = h->seed;
+    mptr.assign(n + 1, 0);
+    n_missing = 0;
+    if (want_missing && thr != UINT64_MAX) {
+        // count, then fill (the predicate is evaluated twice; no extra memory)
+        for (int pass = 0; pass < 2; pass++) {
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t i = 0; i < (p1.ncomm ? p1.comm_off[p1.ncomm] : 0); i++) {
+                const int32_t c = p1.comm_of_pos[i];
+                const int64_t off = p1.comm_off[c], lam = p1.comm_off[c + 1] - off;
+                const uint32_t ui = (uint32_t)p1.perm[i];
+                const int64_t me = i - off;
+                int64_t cnt = 0;
+                int32_t *w = pass ? mval.data() + 2 * mptr[i] : nullptr;
+                for (int64_t a = 0; a < lam; a++) {
+                    if (a == me) continue;
+                    const uint32_t ua = (uint32_t)p1.perm[off + a];
+                    for (int64_t b = a + 1; b < lam; b++) {
+                        if (b == me) continue;
+                        const uint32_t ub = (uint32_t)p1.perm[off + b];
+                        if (splitmix64_out(seed ^ triple_key(ui, ua, ub)) >= thr) {
+                            if (pass) {
+                                w[2 * cnt] = (int32_t)a;
+                                w[2 * cnt + 1] = (int32_t)b;
+                            }
+                            cnt++;
+                        }
+                    }
+                }
+                if (!pass) mptr[i + 1] = cnt;
+            }
+            if (!pass) {
+                for (int64_t i = 0; i < n; i++) mptr[i + 1] += mptr[i];
+                n_missing = mptr[n];
+                try {
+                    mval.resize(2 * std::max<int64_t>(n_missing, 1));
+                } catch (const std::bad_alloc &) {
+                    return set_error(CIA_ENOMEM, "host allocation of %lld missing hyperedge pairs failed",
+                                     (long long)n_missing);
+                }
+            }
+        }
+    }
+    // explicit hyperedges, three centres each
+    xptr.assign(n + 1, 0);
+    const int32_t *t = h->tri;
+    if (h->ntri > 0 && !t) return set_error(CIA_EINVAL, "hypergraph: tri is NULL");
+    for (int64_t q = 0; q < h->ntri; q++) {
+        const int32_t a = t[3 * q], b = t[3 * q + 1], d = t[3 * q + 2];
+        if (a < 0 || b < 0 || d < 0 || a >= n || b >= n || d >= n || a == b || b == d || a == d)
+            return set_error(CIA_EINVAL, "hypergraph: triangle %lld is not three distinct nodes", (long long)q);
+        const int32_t ca = p1.comm_of_pos[p1.inv[a]], cb = p1.comm_of_pos[p1.inv[b]], cd = p1.comm_of_pos[p1.inv[d]];
+        if (ca >= 0 && ca == cb && cb == cd)
+            return set_error(CIA_EINVAL, "hypergraph: triangle %lld lies inside one community "
+                                         "(such triples are given by the predicate)", (long long)q);
+        xptr[p1.inv[a] + 1]++;
+        xptr[p1.inv[b] + 1]++;
+        xptr[p1.inv[d] + 1]++;
+    }
+    for (int64_t i = 0; i < n; i++) xptr[i + 1] += xptr[i];
+    xval.assign(2 * std::max<int64_t>(xptr[n], 1), 0);
+    std::vector<int64_t> fill(xptr.begin(), xptr.end() - 1);
+    for (int64_t q = 0; q < h->ntri; q++) {
+        const int32_t v[3] = {p1.inv[t[3 * q]], p1.inv[t[3 * q + 1]], p1.inv[t[3 * q + 2]]};
+        for (int r = 0; r < 3; r++) {
+            const int64_t at = fill[v[r]]++;
+            xval[2 * at] = v[(r + 1) % 3];
+            xval[2 * at + 1] = v[(r + 2) % 3];
+        }
+    }
+    return CIA_OK;
+}
+
 cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
                        const double *omega, const cia_options *o) {
     PhaseState *s = new (std::nothrow) PhaseState();
@@ -920,22 +1169,42 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     const bool f64 = o->precision == CIA_F64;
     s->f64 = f64;
     s->direct = o->method == CIA_METHOD_DIRECT;
-    if (c->p < 1 || c->p > PMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, PMAX);
-    if (!c->d_sin || !c->d_cos) return set_error(CIA_EINVAL, "coupling.d_sin/d_cos are NULL");
-    for (int k = 0; k <= c->p; k++)
-        if (!std::isfinite(c->d_sin[k]) || !std::isfinite(c->d_cos[k]))
-            return set_error(CIA_EINVAL, "coupling coefficients must be finite");
-    s->P = c->p;
+    if (c->model == CIA_MODEL_PHASE) {
+        if (c->p < 1 || c->p > PMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, PMAX);
+        if (!c->d_sin || !c->d_cos) return set_error(CIA_EINVAL, "coupling.d_sin/d_cos are NULL");
+        for (int k = 0; k <= c->p; k++)
+            if (!std::isfinite(c->d_sin[k]) || !std::isfinite(c->d_cos[k]))
+                return set_error(CIA_EINVAL, "coupling coefficients must be finite");
+        s->P = c->p;
+        s->d0 = c->d_cos[0];
+        s->hzero = c->d_cos[0];
+        for (int k = 1; k <= c->p; k++) {
+            s->dsin[k] = c->d_sin[k];
+            s->dcos[k] = c->d_cos[k];
+            s->hzero += c->d_cos[k];
+        }
+    }
     s->K = c->K;
     s->Kn = c->K / (double)g->n;
-    s->d0 = c->d_cos[0];
-    s->hzero = c->d_cos[0];
-    for (int k = 1; k <= c->p; k++) {
-        s->dsin[k] = c->d_sin[k];
-        s->dcos[k] = c->d_cos[k];
-        s->hzero += c->d_cos[k];
-    }
     if (!std::isfinite(s->Kn)) return set_error(CIA_EINVAL, "coupling.K is not finite");
+    if (c->model == CIA_MODEL_TRIADIC) {
+        const cia_hypergraph *h = c->hyper;
+        if (!h) return set_error(CIA_EINVAL, "triadic model: coupling.hyper is NULL");
+        if (!(h->p_intra >= 0.0 && h->p_intra <= 1.0)) return set_error(CIA_EINVAL, "hypergraph: p_intra outside [0,1]");
+        if (h->ntri < 0) return set_error(CIA_EINVAL, "hypergraph: ntri < 0");
+        if (g->n >= (int64_t(1) << 21)) return set_error(CIA_EUNSUPPORTED, "triadic model: n must be below 2^21");
+        if (g->kind != CIA_GRAPH_CSR) return set_error(CIA_EUNSUPPORTED, "triadic model: the pairwise graph must be CSR");
+        if (!std::isfinite(c->K2)) return set_error(CIA_EINVAL, "coupling.K2 is not finite");
+        s->tri = true;
+        s->K2n = c->K2 / ((double)g->n * (double)g->n);
+        s->tri_seed = h->seed;
+        s->tri_thr = triple_threshold(h->p_intra);
+        // pairwise part h = sin, evaluated with order-2 observables (S1, S2)
+        s->P = 2;
+        for (int k = 0; k <= PMAX; k++) s->dsin[k] = s->dcos[k] = 0.0;
+        s->dsin[1] = 1.0;
+        s->d0 = s->hzero = 0.0;
+    }
     if (o->block != 0 && o->block != 256 && o->block != 512)
         return set_error(CIA_EINVAL, "options.block = %d; use 0, 256 or 512", o->block);
     s->block = o->block == 512 ? 512 : 256;
@@ -958,33 +1227,40 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     Sell sell;
     std::vector<int32_t> cnt_old;
     std::vector<char> comm_staged;
-    int64_t nnz_neg = 0, nnz_pos = 0, nnz_neg_staged = 0;
+    int64_t nnz_neg = 0, nnz_pos = 0, nnz_neg_staged = 0, nnz_tri = 0;
     try {
+        std::vector<int64_t> mptr, xptr;
+        std::vector<int32_t> mval, xval;
         if (!s->direct) {
-            CIA_TRY(p1_build(g, labels, o->dense_alpha, keep, validate, true, p1));
+            // triadic hyperedges are defined on the given communities: keep them all
+            CIA_TRY(p1_build(g, labels, o->dense_alpha, keep || s->tri, validate, true, p1));
             nnz_neg = (int64_t)p1.neg_local.size();
             nnz_pos = (int64_t)p1.pos.size();
             comm_staged.assign(p1.ncomm, 0);
             for (int32_t cc = 0; cc < p1.ncomm; cc++) {
                 int64_t lam = p1.comm_off[cc + 1] - p1.comm_off[cc];
                 bool wide = (double)lam > WIDE_COMMUNITY || (o->flags & CIA_FLAG_FORCE_WIDE);
+                if (s->tri && wide) return set_error(CIA_EUNSUPPORTED, "triadic model: community above 1e5 nodes");
                 comm_staged[cc] = lam <= cap && !wide;
                 if (comm_staged[cc]) nnz_neg_staged += p1.negptr[p1.comm_off[cc + 1]] - p1.negptr[p1.comm_off[cc]];
             }
-            if (!p1.complete) {
-                RowLists L;
-                L.negptr = &p1.negptr;
-                L.neg = p1.neg_local.data();
-                L.posptr = &p1.posptr;
-                L.pos = p1.pos.data();
-                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, L, sell));
-            } else {
-                std::vector<int64_t> zp(n + 1, 0);
-                RowLists L;
-                L.negptr = &zp;
-                L.posptr = &zp;
-                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, L, sell));
+            StreamIn S[4];
+            S[0].ptr = &p1.negptr;
+            S[0].val = p1.neg_local.data();
+            S[0].local = true;
+            S[1].ptr = &p1.posptr;
+            S[1].val = p1.pos.data();
+            if (s->tri) {
+                CIA_TRY(triadic_lists(p1, c->hyper, true, mptr, mval, xptr, xval, nnz_tri));
+                S[2].ptr = &mptr;
+                S[2].val = mval.data();
+                S[2].local = true;
+                S[2].pair = true;
+                S[3].ptr = &xptr;
+                S[3].val = xval.data();
+                S[3].pair = true;
             }
+            CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, S, sell));
             if (s->d0 != 0.0) {
                 // |S+| - |S-| per row (all zero for a complete graph)
                 cnt_old.resize(n);
@@ -1005,11 +1281,17 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
                 CIA_TRY(p1_permuted_adjacency(g, p1, arp, acol));
                 nnz_pos = arp[n];
                 // rows sorted by degree inside each community segment
-                RowLists L;
-                L.posptr = &arp;
-                L.pos = acol.data();
+                StreamIn S[4];
+                S[1].ptr = &arp;
+                S[1].val = acol.data();
+                if (s->tri) {
+                    CIA_TRY(triadic_lists(p1, c->hyper, false, mptr, mval, xptr, xval, nnz_tri));
+                    S[3].ptr = &xptr;
+                    S[3].val = xval.data();
+                    S[3].pair = true;
+                }
                 std::vector<char> none(p1.ncomm, 0);
-                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, none, L, sell));
+                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, none, S, sell));
                 if (s->d0 != 0.0) {
                     cnt_old.resize(n);
                     for (int64_t i = 0; i < n; i++) cnt_old[i] = (int32_t)(arp[i + 1] - arp[i]);
@@ -1082,8 +1364,9 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     inf.wide_comms = s->direct ? 0 : wide;
     inf.method = o->method;
     inf.precision = o->precision;
-    inf.model = CIA_MODEL_PHASE;
-    inf.p = c->p;
+    inf.model = s->tri ? CIA_MODEL_TRIADIC : CIA_MODEL_PHASE;
+    inf.p = s->P;
+    inf.nnz_extra = nnz_tri;
     {
         // Algorithmic bytes (no padding).  Per node and RHS: theta in, omega,
         // H out, its z written once and read once; per remainder entry its
@@ -1104,16 +1387,17 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         CIA_TRY(dupload(p, &s->units, units.data(), units.size()));
         if (sell.slices.empty()) sell.slices.push_back(Slice{});
         CIA_TRY(dupload(p, &s->slices, sell.slices.data(), sell.slices.size()));
-        CIA_TRY(dupload(p, &s->negdata, sell.neg.data(), sell.neg.size()));
-        CIA_TRY(dupload(p, &s->posdata, sell.pos.data(), sell.pos.size()));
+        CIA_TRY(dupload(p, &s->negdata, sell.data[0].data(), sell.data[0].size()));
+        CIA_TRY(dupload(p, &s->posdata, sell.data[1].data(), sell.data[1].size()));
+        CIA_TRY(dupload(p, &s->tnegdata, sell.data[2].data(), sell.data[2].size()));
+        CIA_TRY(dupload(p, &s->tposdata, sell.data[3].data(), sell.data[3].size()));
         // the kernels read cnt[i] only when d_0 != 0, and then it holds n entries
         if (s->d0 != 0.0 && (int64_t)cnt.size() != n)
             return set_error(CIA_EINVAL, "internal: row counts missing for d_0 != 0");
         if (!cnt.empty()) CIA_TRY(dupload(p, &s->cnt, cnt.data(), cnt.size()));
         else CIA_TRY(dalloc(p, &s->cnt, 1));
     }
-    std::vector<uint4>().swap(sell.neg);
-    std::vector<uint4>().swap(sell.pos);
+    for (int q = 0; q < 4; q++) std::vector<uint4>().swap(sell.data[q]);
     // omega in community order
     if (omega) {
         if (f64) {
@@ -1147,6 +1431,25 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         CIA_TRY(dalloc(p, &s->q[b], (size_t)std::max(1, nslots) * s->P));
     }
     CIA_TRY(dalloc(p, &s->r_part, (size_t)std::max(1, s->nunits) + 1024));
+    if (s->tri && s->direct) {
+        // present-pair enumeration blocks: 256 centres of one community each
+        std::vector<TriBlock> tb;
+        size_t maxl = 0;
+        for (int32_t cc = 0; cc < p1.ncomm; cc++) {
+            const int32_t off = p1.comm_off[cc], lam = p1.comm_off[cc + 1] - off;
+            maxl = std::max<size_t>(maxl, (size_t)lam);
+            for (int32_t r = 0; r < lam; r += 256) tb.push_back(TriBlock{off, lam, off + r, std::min(256, lam - r)});
+        }
+        s->tri_smem = maxl * (2 * rs + 4);
+        if (s->tri_smem > LDS_BYTES)
+            return set_error(CIA_EUNSUPPORTED, "direct triadic: community of %zu nodes does not fit in LDS", maxl);
+        s->ntri_blocks = (int32_t)tb.size();
+        if (tb.empty()) tb.push_back(TriBlock{0, 0, 0, 0});
+        CIA_TRY(dupload(p, &s->tri_blocks, tb.data(), tb.size()));
+        CIA_TRY(dalloc(p, &raw, 2 * rs * n));
+        CIA_HIP(hipMemset(raw, 0, 2 * rs * n));
+        s->h_extra = raw;
+    }
     if (s->complete_direct) {
         CIA_TRY(dalloc(p, &raw, rs * n));
         s->hbuf = raw;
@@ -1185,6 +1488,10 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
     a.slices = s->slices;
     a.negdata = s->negdata;
     a.posdata = s->posdata;
+    a.tnegdata = s->tnegdata;
+    a.tposdata = s->tposdata;
+    a.h_extra = static_cast<const cx<R> *>(s->h_extra);
+    a.K2n = (R)s->K2n;
     a.cnt = s->cnt;
     a.perm = s->perm;
     a.omega = static_cast<const R *>(s->omega);
@@ -1204,17 +1511,33 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
 
 template <typename R, int P, int BLOCK>
 static void launch_stage_v(PhaseState *s, const PhaseArgs<R> &a, hipStream_t st) {
+    const dim3 g(s->nunits), b(BLOCK);
+    if (s->tri) {
+        if constexpr (P == 2) {
+            if (s->direct) hipLaunchKernelGGL((phase_stage_kernel<R, 2, BLOCK, true, false, true>), g, b, s->smem, st, a);
+            else hipLaunchKernelGGL((phase_stage_kernel<R, 2, BLOCK, false, false, true>), g, b, s->smem, st, a);
+        }
+        return;
+    }
     if (s->direct)
-        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, true, false>), dim3(s->nunits), dim3(BLOCK), s->smem, st, a);
+        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, true, false, false>), g, b, s->smem, st, a);
     else if (sizeof(R) == 4 && s->has_wide)
-        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, true>), dim3(s->nunits), dim3(BLOCK), s->smem, st, a);
+        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, true, false>), g, b, s->smem, st, a);
     else
-        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, false>), dim3(s->nunits), dim3(BLOCK), s->smem, st, a);
+        hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, false, false>), g, b, s->smem, st, a);
 }
 
 template <typename R, int P>
 static cia_status launch_stage_p(cia_plan *p, PhaseState *s, const PhaseArgs<R> &a, hipStream_t st, int kind) {
     if (s->nunits == 0) return CIA_OK;
+    if (s->tri && s->direct && a.mode != M_PREP && s->ntri_blocks > 0) {
+        CIA_TRY(timing_begin(p, st, KK_AUX));
+        hipLaunchKernelGGL((triadic_present_kernel<R>), dim3(s->ntri_blocks), dim3(256), s->tri_smem, st,
+                           s->tri_blocks, s->perm, a.cs_in, (uint64_t)s->tri_seed, (uint64_t)s->tri_thr,
+                           static_cast<cx<R> *>(s->h_extra));
+        CIA_HIP(hipGetLastError());
+        CIA_TRY(timing_end(p, st));
+    }
     CIA_TRY(timing_begin(p, st, kind));
     if (s->block == 512) launch_stage_v<R, P, 512>(s, a, st);
     else launch_stage_v<R, P, 256>(s, a, st);

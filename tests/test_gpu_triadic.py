@@ -1,0 +1,113 @@
+"""GPU parity of the higher-order (triadic) Kuramoto path against the FP64
+oracle (App. A.7 on a hypergraph: seeded intra-community triples plus listed
+cross-community triples, pairwise sine coupling)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2203_16657_amd as cia
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cia.load()
+    return cia, torch
+
+
+def rel_inf(got, want):
+    return float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
+
+
+def plan_for(cia, T, method, precision=0, **kw):
+    g = T.graph
+    return cia.Plan.triadic(g.n, g.row_ptr, g.col, g.labels, None, K1=T.K1, K2=T.K2, tri_seed=T.tri_seed,
+                            p_tri=T.p_tri, cross_tri=T.cross_tri, method=method, precision=precision, **kw)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_triadic_rhs_small(env, method, precision):
+    cia, torch = env
+    T = W.triadic(seed=31, n=1500, lo=60, hi=400, tri_per_node=1.0)
+    g = T.graph
+    say("triadic rhs n", g.n, "comms", g.ncomm, "method", method, "prec", precision)
+    plan = plan_for(cia, T, method, precision)
+    dt = torch.float64 if precision else torch.float32
+    th = torch.as_tensor(T.theta0, dtype=dt, device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    info = plan.info()
+    th64 = th.cpu().numpy().astype(np.float64)
+    got = out.cpu().numpy().astype(np.float64)
+    want = oracle.triadic_rhs(g.n, g.row_ptr, g.col, g.labels, T.tri_seed, T.p_tri, T.cross_tri, None,
+                              T.K1, T.K2, th64)
+    err = rel_inf(got, want)
+    say("   rel_inf", err, "missing pairs", info.nnz_extra)
+    assert err < (1e-12 if precision else 1e-5)
+    if method == 0:
+        assert info.nnz_extra > 0
+    plan.close()
+
+
+def test_triadic_p_tri_extremes(env):
+    """p_tri = 1: no missing triples (E2 empty); p_tri = 0: no intra triples."""
+    cia, torch = env
+    for p in (1.0, 0.0):
+        T = W.triadic(seed=7, n=900, lo=40, hi=200, p_tri=p, tri_per_node=0.5)
+        g = T.graph
+        plan = plan_for(cia, T, 0, 1)
+        th = torch.as_tensor(T.theta0, dtype=torch.float64, device="cuda")
+        out = torch.empty_like(th)
+        plan.rhs(th, out)
+        got = out.cpu().numpy()
+        want = oracle.triadic_rhs(g.n, g.row_ptr, g.col, g.labels, T.tri_seed, T.p_tri, T.cross_tri, None,
+                                  T.K1, T.K2, T.theta0)
+        say("p_tri", p, rel_inf(got, want), plan.info().nnz_extra)
+        assert rel_inf(got, want) < 1e-12
+        plan.close()
+
+
+def test_triadic_trajectory(env):
+    cia, torch = env
+    T = W.triadic(seed=12, n=600, lo=40, hi=150, tri_per_node=1.0)
+    g = T.graph
+    steps = 60
+    want_th, want_r = oracle.triadic_integrate(g.n, g.row_ptr, g.col, g.labels, T.tri_seed, T.p_tri,
+                                               T.cross_tri, T.omega, T.K1, T.K2, T.theta0, T.dt, steps)
+    for method in (0, 1):
+        plan = cia.Plan.triadic(g.n, g.row_ptr, g.col, g.labels, T.omega, K1=T.K1, K2=T.K2,
+                                tri_seed=T.tri_seed, p_tri=T.p_tri, cross_tri=T.cross_tri, method=method,
+                                precision=1)
+        th = torch.as_tensor(T.theta0, dtype=torch.float64, device="cuda")
+        r = np.zeros(steps + 1)
+        plan.integrate(th, T.dt, steps, r)
+        circ = np.abs(np.angle(np.exp(1j * (th.cpu().numpy() - want_th))))
+        say("triadic traj method", method, circ.max(), np.abs(r - want_r).max())
+        assert circ.max() < 1e-9 and np.abs(r - want_r).max() < 1e-9
+        plan.close()
+
+
+def test_triadic_rejects_intra_listed_triangle(env):
+    cia, torch = env
+    T = W.triadic(seed=5, n=300, lo=40, hi=100, tri_per_node=0.2)
+    g = T.graph
+    lab = g.labels
+    c0 = np.flatnonzero(lab == lab[lab >= 0][0])[:3]
+    bad = np.vstack([T.cross_tri, np.sort(c0)[None, :]])
+    with pytest.raises(cia.CIAError) as e:
+        cia.Plan.triadic(g.n, g.row_ptr, g.col, g.labels, None, K1=1, K2=1, tri_seed=T.tri_seed, p_tri=T.p_tri,
+                         cross_tri=bad)
+    assert "inside one community" in cia.cia_last_error()
