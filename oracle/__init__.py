@@ -33,11 +33,11 @@ _vp = ctypes.c_void_p
 
 def build(force: bool = False) -> str:
     """Compile the oracle: gcc -O2, no fast-math (libm sin/cos, IEEE FP64)."""
-    src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "basis.c")]
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in srcs):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-                               "-shared", "-fPIC", "-std=c11", "-o", tmp, src, "-lm"])
+                               "-shared", "-fPIC", "-std=c11", "-o", tmp] + srcs + ["-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -75,6 +75,22 @@ def _load():
         lib.oracle_cs_integrate.restype = ctypes.c_int
         lib.oracle_cs_integrate.argtypes = [i64, ctypes.c_int, _vp, _vp, ctypes.c_int, d, d, d, _vp,
                                             _vp, d, i64, ctypes.c_int]
+        lib.oracle_gauss_legendre.restype = None
+        lib.oracle_gauss_legendre.argtypes = [ctypes.c_int, _vp, _vp]
+        lib.oracle_cs_fourier_coeffs.restype = ctypes.c_int
+        lib.oracle_cs_fourier_coeffs.argtypes = [d, d, d, d, ctypes.c_int, ctypes.c_int, _vp]
+        lib.oracle_cs_fourier_weight.restype = d
+        lib.oracle_cs_fourier_weight.argtypes = [_vp, ctypes.c_int, d, _vp]
+        lib.oracle_mlp_param_count.restype = i64
+        lib.oracle_mlp_param_count.argtypes = [ctypes.c_int]
+        lib.oracle_mlp_forward.restype = None
+        lib.oracle_mlp_forward.argtypes = [_vp, ctypes.c_int, _vp, _vp, i64, _vp, _vp]
+        lib.oracle_mlp_loss_grad.restype = ctypes.c_int
+        lib.oracle_mlp_loss_grad.argtypes = [_vp, ctypes.c_int, _vp, _vp, i64, _vp, _vp, _vp, _vp, _vp]
+        lib.oracle_cs_rhs_separable.restype = ctypes.c_int
+        lib.oracle_cs_rhs_separable.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, _vp, d, d, d,
+                                                ctypes.c_int, _vp, ctypes.c_int, d, _vp, ctypes.c_int,
+                                                _vp, _vp, _vp, _vp, _vp, i64, _vp, _vp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -252,3 +268,83 @@ def dense_cs_rhs(A, K, sigma, beta, s, v):
     w = K / (sigma ** 2 + (ds ** 2).sum(axis=0)) ** beta
     dv = v[:, None, :] - v[:, :, None]
     return v.copy(), (A[None] * w[None] * dv).sum(axis=2) / n
+
+
+# ---------------------------------------------------------------------------
+# separable expansions of the Cucker-Smale weight (basis.c)
+# ---------------------------------------------------------------------------
+
+MLP_HIDDEN = 64
+
+
+def gauss_legendre(m):
+    x = np.empty(m)
+    w = np.empty(m)
+    _load().oracle_gauss_legendre(int(m), _p(x), _p(w))
+    return x, w
+
+
+def cs_fourier_coeffs(K, sigma, beta, L, p, nq=96):
+    """c[a1, a2, a3] for |alpha| = (a1, a2, a3) in 0..p (App. A.6)."""
+    c = np.empty((p + 1) ** 3)
+    if _load().oracle_cs_fourier_coeffs(float(K), float(sigma), float(beta), float(L), int(p), int(nq), _p(c)):
+        raise MemoryError("oracle_cs_fourier_coeffs")
+    return c.reshape(p + 1, p + 1, p + 1)
+
+
+def cs_fourier_weight(c, L, y):
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    p = c.shape[0] - 1
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return float(_load().oracle_cs_fourier_weight(_p(c), p, float(L), _p(y)))
+
+
+def mlp_param_count(R):
+    return int(_load().oracle_mlp_param_count(int(R)))
+
+
+def mlp_forward(params, R, lo, hi, x):
+    """x: [3, n] planes -> phi [n, R]."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.shape[1]
+    out = np.empty((n, R))
+    _load().oracle_mlp_forward(_p(_f64(params)), int(R), _p(_f64(lo)), _p(_f64(hi)), n, _p(x), _p(out))
+    return out
+
+
+def mlp_loss_grad(params, R, lo, hi, a, b, t):
+    """a, b: [P, 3] pair endpoints, t: [P] targets -> (loss, grad like params)."""
+    params = _f64(params)
+    a, b, t = _f64(a), _f64(b), _f64(t)
+    g = np.empty_like(params)
+    loss = np.zeros(1)
+    if _load().oracle_mlp_loss_grad(_p(params), int(R), _p(_f64(lo)), _p(_f64(hi)), len(t), _p(a), _p(b),
+                                    _p(t), _p(g), _p(loss)):
+        raise MemoryError("oracle_mlp_loss_grad")
+    return float(loss[0]), g
+
+
+def cs_rhs_separable(n, row_ptr, col, labels, K, sigma, beta, s, v, basis, fourier=None, L=0.0, mlp=None,
+                     R=0, lo=None, hi=None, exact_comm=None, rows=None, complete=False):
+    """Cucker-Smale RHS with the expanded weight on intra-community present pairs.
+    basis: "fourier" (fourier = coefficient cube, L) or "mlp" (mlp = params, R, lo, hi)."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
+    ex = None if exact_comm is None else np.ascontiguousarray(exact_comm, dtype=np.uint8)
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    sd = np.empty((3, cnt))
+    vd = np.empty((3, cnt))
+    kind = {"fourier": 1, "mlp": 2}[basis]
+    c = _f64(fourier) if kind == 1 else None
+    p = 0 if c is None else np.asarray(fourier).shape[0] - 1
+    rc = lib.oracle_cs_rhs_separable(n, _p(rp), _p(cl), int(bool(complete)), _p(lab), _p(ex), float(K),
+                                     float(sigma), float(beta), kind, _p(c), int(p), float(L),
+                                     _p(_f64(mlp)), int(R), _p(_f64(lo)), _p(_f64(hi)), _p(s), _p(v),
+                                     _p(rws), 0 if rws is None else len(rws), _p(sd), _p(vd))
+    if rc:
+        raise MemoryError("oracle_cs_rhs_separable")
+    return sd, vd
