@@ -90,6 +90,8 @@ typedef enum cia_status {
                                       read them with cia_plan_get_timing */
 #define CIA_FLAG_NO_VALIDATE 0x4u  /* skip the symmetry / sortedness checks of cia_build */
 #define CIA_FLAG_HIPGRAPH 0x8u     /* replay the RK step loop from a captured HIP graph */
+#define CIA_FLAG_NO_JUDGE 0x10u    /* flock model: never check the separable basis against the
+                                      exact weight (no per-community fallback) */
 /* kernel-path overrides, for testing and tuning (results stay within tolerance) */
 #define CIA_FLAG_FORCE_WIDE 0x100u  /* FP64 observables/combine for every community */
 #define CIA_FLAG_FORCE_NEG32 0x200u /* S-neg as int32 positions for every community */
@@ -117,7 +119,8 @@ typedef struct cia_hypergraph {
 
 typedef struct cia_coupling {
     int32_t model;             /* CIA_MODEL_* */
-    int32_t p;                 /* phase: Fourier order of h, 1..8; flock Fourier: modes per axis */
+    int32_t p;                 /* phase: Fourier order of h, 1..8; flock Fourier basis: order p
+                                  in 1..2, multi-indices alpha in {-p..p}^3 ((2p+1)^3 features) */
     const double *d_sin;       /* host [p+1]; entry 0 ignored (phase model) */
     const double *d_cos;       /* host [p+1]; entry 0 = constant term d_0 (phase model) */
     double K;                  /* pairwise strength; the library applies K/N, N = graph n */
@@ -126,9 +129,11 @@ typedef struct cia_coupling {
     double cs_K, cs_sigma, cs_beta;/* flock weight parameters */
     double cs_L;               /* flock Fourier half-period L (positions must stay in a
                                   cube of side L so all differences lie in [-L, L]) */
-    int32_t cs_basis;          /* CIA_BASIS_* */
-    int32_t rank;              /* learned basis rank R, 1..64 */
-    int32_t train_iters;       /* learned basis: optimiser steps at build time (0 = default) */
+    int32_t cs_basis;          /* CIA_BASIS_*; flock model only (the direct method ignores it) */
+    int32_t rank;              /* learned basis rank R: 16, 32, 48 or 64 */
+    int32_t train_iters;       /* learned basis: Adam steps of the first training, which runs on
+                                  the state of the first cia_rhs / cia_integrate call unless
+                                  parameters were set or trained before (0 = 3000) */
     int32_t reserved;
 } cia_coupling;
 
@@ -141,7 +146,10 @@ typedef struct cia_options {
                                   nnz(S-neg_c) + dense_alpha * lambda_c < nnz(intra_c) */
     int32_t unit_work;         /* target remainder entries per work unit (0 = default) */
     int32_t block;             /* threads per block of the stage kernels, 256 or 512 (0 = default) */
-    double judge_tol;          /* learned basis: max relative weight error per community */
+    double judge_tol;          /* flock separable bases: a community falls back to the exact
+                                  weight for a step when, on sampled members, the community
+                                  part of the sum deviates by more than judge_tol times its
+                                  largest exact magnitude (max norm); 0 = never judge */
     int32_t device;            /* HIP device ordinal, -1 = the current device */
     int32_t reserved;
 } cia_options;
@@ -200,6 +208,48 @@ cia_status cia_destroy(cia_plan *p);
 const char *cia_last_error(void);
 
 /* --------------------------------------------------------------------- */
+/* Learned separable basis of the flock weight                            */
+/* --------------------------------------------------------------------- */
+/*
+ * The learned basis (CIA_BASIS_LEARNED) is a perceptron f: R^3 -> R^R,
+ *   u = (2 s - lo - hi) / (hi - lo)  per coordinate (the box [lo, hi] to [-1, 1]),
+ *   h1 = silu(W1 u + b1) (64), h2 = silu(W2 h1 + b2) (64), f = W3 h2 + b3 (R),
+ * with silu(z) = z / (1 + exp(-z)), standing in for the flock weight on
+ * intra-community pairs as wt(a, b) = sum_r sgn_r f_r(a) f_r(b) (the separable
+ * expansion of Sec. 3 / App. A.6 with a learned instead of a Fourier basis).
+ * Parameter vector (float, this order): W1[64][3], b1[64], W2[64][64], b2[64],
+ * W3[R][64], b3[R], sgn[R]; sgn is fixed (not trained).  Layers 2 and 3 run
+ * as bf16 matrix-core products with FP32 accumulation.
+ * Training minimises (1/P) sum_k (wt(a_k, b_k) - w(|a_k - b_k|))^2 over pairs of
+ * members of one dense community drawn from a state, with Adam.
+ */
+/* number of floats in the parameter vector of rank R (16, 32, 48 or 64) */
+cia_status cia_basis_param_count(int32_t rank, int64_t *count);
+/* Copy parameters (host [count]) and the input box lo/hi (host [3] each) into
+   the plan; marks the basis trained.  Synchronises the device. */
+cia_status cia_basis_set_params(cia_plan *p, const float *params, int64_t count, const double lo[3],
+                                const double hi[3]);
+/* Read the parameters and the input box (host outputs; lo/hi may be NULL). */
+cia_status cia_basis_get_params(cia_plan *p, float *params, int64_t count, double lo[3], double hi[3]);
+/* Train on pairs drawn from `state` (device, user order, 6 planes): sets the
+   input box to the positions' bounding box (2% margin), then `iters` Adam
+   steps of 4096 pairs each from the counter-based stream `seed`, continuing
+   from the current parameters.  loss_trace: optional host [iters].  Synchronises. */
+cia_status cia_basis_train(cia_plan *p, const void *state, int32_t iters, uint64_t seed, double *loss_trace,
+                           void *stream);
+/* Loss and gradient at the current parameters for given pairs: a, b device
+   [pairs][3] positions, t device [pairs] targets; grad device [param count]
+   (layout of the parameter vector, sgn entries 0); loss optional host scalar
+   (then the call synchronises). */
+cia_status cia_basis_loss_grad(cia_plan *p, const float *a, const float *b, const float *t, int64_t pairs,
+                               float *grad, double *loss, void *stream);
+/* Features of n points of the plan's separable basis (learned or Fourier):
+   x device [3][n] planes, out device [n][stride], stride = rank for the learned
+   basis and (2p+1)^3 rounded up to a multiple of 4 for the Fourier basis
+   (feature 0 = 1, then cos, sin of pi <alpha, s> / L per multi-index). */
+cia_status cia_basis_features(cia_plan *p, const float *x, int64_t n, float *out, void *stream);
+
+/* --------------------------------------------------------------------- */
 /* Introspection                                                          */
 /* --------------------------------------------------------------------- */
 
@@ -214,11 +264,13 @@ typedef struct cia_plan_info {
     int32_t nunits;           /* work units of the stage kernels */
     int32_t max_comm;         /* largest community */
     int32_t wide_comms;       /* communities above 1e5 nodes (FP64 observables) */
-    int32_t method, precision, model, p;
+    int32_t method, precision, model;
+    int32_t p;                /* phase: Fourier order; flock: Fourier order or learned rank */
     double bytes_per_rhs;     /* algorithmic HBM bytes of one RHS evaluation */
     double bytes_per_stage;   /* algorithmic HBM bytes of one fused RK stage launch */
     int64_t nnz_extra;        /* model-specific remainder entries (triadic pair lists) */
-    int32_t judge_fallbacks;  /* learned basis: communities currently on exact fallback */
+    int32_t judge_fallbacks;  /* flock: communities currently on the exact fallback (read
+                                 from the device; synchronises it) */
     int32_t reserved;
 } cia_plan_info;
 

@@ -27,6 +27,7 @@ CIA_F32, CIA_F64 = 0, 1
 CIA_RK4, CIA_EULER = 0, 1
 CIA_BASIS_EXACT, CIA_BASIS_FOURIER, CIA_BASIS_LEARNED = 0, 1, 2
 CIA_FLAG_KEEP_LABELS, CIA_FLAG_TIMING, CIA_FLAG_NO_VALIDATE, CIA_FLAG_HIPGRAPH = 0x1, 0x2, 0x4, 0x8
+CIA_FLAG_NO_JUDGE = 0x10
 CIA_FLAG_FORCE_WIDE, CIA_FLAG_FORCE_NEG32, CIA_FLAG_NO_LDS = 0x100, 0x200, 0x400
 
 _c = ctypes
@@ -74,7 +75,8 @@ class cia_timing(_c.Structure):
 EXPORTS = ["cia_build", "cia_rhs", "cia_integrate", "cia_destroy", "cia_last_error",
            "cia_options_default", "cia_coupling_default", "cia_plan_get_info", "cia_plan_get_timing",
            "cia_fourier_coeffs", "cia_p1_build", "cia_p1_sizes", "cia_p1_export", "cia_p1_free",
-           "cia_abi_sizeof"]
+           "cia_abi_sizeof", "cia_basis_param_count", "cia_basis_set_params", "cia_basis_get_params",
+           "cia_basis_train", "cia_basis_loss_grad", "cia_basis_features"]
 
 _lib = None
 
@@ -124,6 +126,18 @@ def load():
     lib.cia_p1_free.argtypes = [_vp]
     lib.cia_abi_sizeof.restype = _c.c_size_t
     lib.cia_abi_sizeof.argtypes = [_c.c_char_p]
+    lib.cia_basis_param_count.restype = _c.c_int
+    lib.cia_basis_param_count.argtypes = [_c.c_int32, _vp]
+    lib.cia_basis_set_params.restype = _c.c_int
+    lib.cia_basis_set_params.argtypes = [_vp, _vp, _c.c_int64, _vp, _vp]
+    lib.cia_basis_get_params.restype = _c.c_int
+    lib.cia_basis_get_params.argtypes = [_vp, _vp, _c.c_int64, _vp, _vp]
+    lib.cia_basis_train.restype = _c.c_int
+    lib.cia_basis_train.argtypes = [_vp, _vp, _c.c_int32, _c.c_uint64, _vp, _vp]
+    lib.cia_basis_loss_grad.restype = _c.c_int
+    lib.cia_basis_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _c.c_int64, _vp, _vp, _vp]
+    lib.cia_basis_features.restype = _c.c_int
+    lib.cia_basis_features.argtypes = [_vp, _vp, _c.c_int64, _vp, _vp]
     _lib = lib
     return lib
 
@@ -262,6 +276,47 @@ def cia_p1(n, row_ptr, col, labels=None, options=None, complete=False):
 # convenience wrapper
 # ---------------------------------------------------------------------------
 
+def cia_basis_param_count(rank: int) -> int:
+    cnt = _c.c_int64(0)
+    _check(load().cia_basis_param_count(int(rank), _c.byref(cnt)))
+    return int(cnt.value)
+
+
+def cia_basis_set_params(plan, params, lo, hi) -> None:
+    pr = np.ascontiguousarray(params, dtype=np.float32)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    _check(load().cia_basis_set_params(plan, _np_ptr(pr), len(pr), _np_ptr(lo), _np_ptr(hi)))
+
+
+def cia_basis_get_params(plan, count: int):
+    pr = np.empty(count, dtype=np.float32)
+    lo = np.empty(3)
+    hi = np.empty(3)
+    _check(load().cia_basis_get_params(plan, _np_ptr(pr), count, _np_ptr(lo), _np_ptr(hi)))
+    return pr, lo, hi
+
+
+def cia_basis_train(plan, state, iters: int, seed: int = 1, loss_trace=None, stream=None) -> None:
+    lt = None
+    if loss_trace is not None:
+        assert loss_trace.dtype == np.float64 and loss_trace.flags.c_contiguous and len(loss_trace) >= iters
+        lt = _np_ptr(loss_trace)
+    _check(load().cia_basis_train(plan, _dev_ptr(state), int(iters), int(seed) & 0xFFFFFFFFFFFFFFFF, lt,
+                                  _stream_ptr(stream)))
+
+
+def cia_basis_loss_grad(plan, a, b, t, grad, stream=None) -> float:
+    loss = _c.c_double(0.0)
+    _check(load().cia_basis_loss_grad(plan, _dev_ptr(a), _dev_ptr(b), _dev_ptr(t), int(t.numel()),
+                                      _dev_ptr(grad), _c.byref(loss), _stream_ptr(stream)))
+    return float(loss.value)
+
+
+def cia_basis_features(plan, x, out, stream=None) -> None:
+    _check(load().cia_basis_features(plan, _dev_ptr(x), int(x.shape[1]), _dev_ptr(out), _stream_ptr(stream)))
+
+
 class Plan:
     """Owns a cia_plan.  Build with Plan.phase(...) (more models below)."""
 
@@ -319,6 +374,41 @@ class Plan:
         o.unit_work, o.block, o.device = unit_work, block, device
         handle = cia_build(g, labels, c, omega, o)
         return cls(handle, int(n), precision, CIA_MODEL_TRIADIC)
+
+    @classmethod
+    def flock(cls, n, row_ptr, col, labels=None, K=1.0, sigma=1.0, beta=0.25, basis=CIA_BASIS_EXACT, rank=32,
+              p=1, L=20.0, train_iters=0, method=CIA_METHOD_CIA, stepper=CIA_RK4, flags=0, judge_tol=1e-3,
+              dense_alpha=2.0, device=-1):
+        """Cucker-Smale flocking in 3-D (state: 6 planes s_x, s_y, s_z, v_x, v_y, v_z)."""
+        load()
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        g = cia_graph(n=int(n), kind=CIA_GRAPH_CSR, reserved=0, row_ptr=_np_ptr(rp), col=_np_ptr(cl))
+        c = cia_coupling_default()
+        c.model = CIA_MODEL_FLOCK
+        c.p = int(p)
+        c.cs_K, c.cs_sigma, c.cs_beta, c.cs_L = float(K), float(sigma), float(beta), float(L)
+        c.cs_basis, c.rank, c.train_iters = int(basis), int(rank), int(train_iters)
+        o = cia_options_default()
+        o.method, o.precision, o.stepper, o.flags = method, CIA_F32, stepper, flags
+        o.judge_tol, o.dense_alpha, o.device = float(judge_tol), dense_alpha, device
+        handle = cia_build(g, labels, c, None, o)
+        return cls(handle, int(n), CIA_F32, CIA_MODEL_FLOCK, dim=6)
+
+    def basis_set_params(self, params, lo, hi):
+        cia_basis_set_params(self.handle, params, lo, hi)
+
+    def basis_get_params(self, count):
+        return cia_basis_get_params(self.handle, count)
+
+    def basis_train(self, state, iters, seed=1, loss_trace=None, stream=None):
+        cia_basis_train(self.handle, state, iters, seed, loss_trace, stream)
+
+    def basis_loss_grad(self, a, b, t, grad, stream=None):
+        return cia_basis_loss_grad(self.handle, a, b, t, grad, stream)
+
+    def basis_features(self, x, out, stream=None):
+        cia_basis_features(self.handle, x, out, stream)
 
     @property
     def dtype_np(self):

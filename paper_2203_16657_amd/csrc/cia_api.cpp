@@ -64,6 +64,7 @@ static void free_plan(cia_plan *p) {
     for (void *q : p->dev_allocs)
         if (q) (void)hipFree(q);
     phase_free(p);
+    flock_free(p);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
     delete p;
 }
@@ -119,9 +120,7 @@ cia_status cia_build(const cia_graph *g, const int32_t *labels, const cia_coupli
             switch (c->model) {
                 case CIA_MODEL_PHASE:
                 case CIA_MODEL_TRIADIC: st = phase_build(p, g, labels, c, omega, o); break;
-                case CIA_MODEL_FLOCK:
-                    st = set_error(CIA_EUNSUPPORTED, "model %d is not available in this build", c->model);
-                    break;
+                case CIA_MODEL_FLOCK: st = flock_build(p, g, labels, c, o); break;
                 default: st = set_error(CIA_EINVAL, "coupling.model = %d", c->model);
             }
         } catch (const std::bad_alloc &) {
@@ -149,6 +148,7 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream) {
     switch (p->model) {
         case CIA_MODEL_PHASE:
         case CIA_MODEL_TRIADIC: st = phase_rhs(p, state, dstate, s); break;
+        case CIA_MODEL_FLOCK: st = flock_rhs(p, state, dstate, s); break;
         default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
     }
     if (st == CIA_OK && (p->flags & CIA_FLAG_TIMING)) st = timing_collect(p);
@@ -168,6 +168,10 @@ cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, dou
     switch (p->model) {
         case CIA_MODEL_PHASE:
         case CIA_MODEL_TRIADIC: st = phase_integrate(p, state, dt, steps, r_trace, s); break;
+        case CIA_MODEL_FLOCK:
+            st = r_trace ? set_error(CIA_EINVAL, "r_trace is defined for the phase models only")
+                         : flock_integrate(p, state, dt, steps, s);
+            break;
         default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
     }
     if (st == CIA_OK && (p->flags & CIA_FLAG_TIMING)) st = timing_collect(p);
@@ -184,6 +188,11 @@ cia_status cia_plan_get_info(const cia_plan *p, cia_plan_info *info) {
     clear_error();
     if (!p || !info) return set_error(CIA_EINVAL, "NULL pointer");
     *info = p->info;
+    if (p->model == CIA_MODEL_FLOCK) {
+        cia_plan *q = const_cast<cia_plan *>(p);
+        CIA_TRY(select_device(q));
+        CIA_TRY(flock_judge_count(q, &info->judge_fallbacks));
+    }
     return CIA_OK;
 }
 
@@ -201,6 +210,52 @@ cia_status cia_plan_get_timing(cia_plan *p, cia_timing *t, int reset) {
         for (int k = 0; k < 3; k++) p->t_ms[k] = 0, p->t_count[k] = 0;
     }
     return CIA_OK;
+}
+
+cia_status cia_basis_param_count(int32_t rank, int64_t *count) {
+    clear_error();
+    if (!count) return set_error(CIA_EINVAL, "count is NULL");
+    if (rank < 16 || rank > 64 || rank % 16) return set_error(CIA_EINVAL, "rank = %d", rank);
+    *count = flock_param_count(rank);
+    return CIA_OK;
+}
+
+cia_status cia_basis_set_params(cia_plan *p, const float *params, int64_t count, const double lo[3],
+                                const double hi[3]) {
+    clear_error();
+    if (!p || !lo || !hi) return set_error(CIA_EINVAL, "NULL pointer");
+    CIA_TRY(select_device(p));
+    return flock_basis_set_params(p, params, count, lo, hi);
+}
+
+cia_status cia_basis_get_params(cia_plan *p, float *params, int64_t count, double lo[3], double hi[3]) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    CIA_TRY(select_device(p));
+    return flock_basis_get_params(p, params, count, lo, hi);
+}
+
+cia_status cia_basis_train(cia_plan *p, const void *state, int32_t iters, uint64_t seed, double *loss_trace,
+                           void *stream) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    CIA_TRY(select_device(p));
+    return flock_basis_train(p, state, iters, seed, loss_trace, static_cast<hipStream_t>(stream));
+}
+
+cia_status cia_basis_loss_grad(cia_plan *p, const float *a, const float *b, const float *t, int64_t pairs,
+                               float *grad, double *loss, void *stream) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    CIA_TRY(select_device(p));
+    return flock_basis_loss_grad(p, a, b, t, pairs, grad, loss, static_cast<hipStream_t>(stream));
+}
+
+cia_status cia_basis_features(cia_plan *p, const float *x, int64_t n, float *out, void *stream) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    CIA_TRY(select_device(p));
+    return flock_basis_features(p, x, n, out, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

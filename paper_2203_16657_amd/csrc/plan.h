@@ -78,12 +78,21 @@ cia_status phase_integrate(cia_plan *p, void *state, double dt, int64_t steps, d
                            hipStream_t s);
 void phase_free(cia_plan *p);
 
-cia_status triadic_build(cia_plan *p, const cia_graph *g, const int32_t *labels,
-                         const cia_coupling *c, const double *omega, const cia_options *o);
+// flock model (cia_flock.hip)
 cia_status flock_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
                        const cia_options *o);
 cia_status flock_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t s);
 cia_status flock_integrate(cia_plan *p, void *state, double dt, int64_t steps, hipStream_t s);
 void flock_free(cia_plan *p);
+cia_status flock_judge_count(cia_plan *p, int32_t *count);
+cia_status flock_basis_features(cia_plan *p, const float *x, int64_t n, float *out, hipStream_t s);
+cia_status flock_basis_set_params(cia_plan *p, const float *params, int64_t count, const double lo[3],
+                                  const double hi[3]);
+cia_status flock_basis_get_params(cia_plan *p, float *params, int64_t count, double lo[3], double hi[3]);
+cia_status flock_basis_train(cia_plan *p, const void *state, int32_t iters, uint64_t seed, double *loss_trace,
+                             hipStream_t s);
+cia_status flock_basis_loss_grad(cia_plan *p, const float *a, const float *b, const float *t, int64_t P,
+                                 float *grad, double *loss, hipStream_t s);
+int64_t flock_param_count(int32_t rank);
 
 }  // namespace cia
