@@ -89,9 +89,12 @@ typedef enum cia_status {
 #define CIA_FLAG_TIMING 0x2u       /* record HIP events around every kernel launch;
                                       read them with cia_plan_get_timing */
 #define CIA_FLAG_NO_VALIDATE 0x4u  /* skip the symmetry / sortedness checks of cia_build */
-#define CIA_FLAG_HIPGRAPH 0x8u     /* replay the RK step loop from a captured HIP graph */
+#define CIA_FLAG_HIPGRAPH 0x8u     /* phase models, RK4: capture one step (its four stage
+                                      launches and the order parameter) as a HIP graph once
+                                      and replay it every step */
 #define CIA_FLAG_NO_JUDGE 0x10u    /* flock model: never check the separable basis against the
                                       exact weight (no per-community fallback) */
+#define CIA_FLAG_AUTOTUNE 0x20u    /* phase models: run cia_autotune at the end of cia_build */
 /* kernel-path overrides, for testing and tuning (results stay within tolerance) */
 #define CIA_FLAG_FORCE_WIDE 0x100u  /* FP64 observables/combine for every community */
 #define CIA_FLAG_FORCE_NEG32 0x200u /* S-neg as int32 positions for every community */
@@ -206,6 +209,60 @@ cia_status cia_destroy(cia_plan *p);
 
 /* Message of the calling thread's last failing call ("" if none). */
 const char *cia_last_error(void);
+
+/* --------------------------------------------------------------------- */
+/* Batched ensembles and tuning                                           */
+/* --------------------------------------------------------------------- */
+
+/*
+ * cia_build_batch -- one plan for `count` independent phase-model networks
+ * (eq. 2.1 per instance, each with its own N_b, K_b, omega and communities),
+ * steps P1 and P2 of Sec. 3.1 for all of them.  The instances are joined into
+ * their disjoint union: instance b owns user ids [off_b, off_b + N_b) of the
+ * joined state (off_0 = 0, in the given order), so cia_rhs / cia_integrate
+ * take the concatenated states and every RK stage is one launch over the work
+ * units of all instances.  Each instance keeps its own coupling scale K_b/N_b.
+ *  graphs    : host [count] CSR graphs (CIA_GRAPH_COMPLETE is not batched).
+ *  labels    : host [count] pointers (NULL = every instance one community; a
+ *              NULL entry = that instance one community).
+ *  couplings : host [count]; model CIA_MODEL_PHASE, the same p, d_sin and
+ *              d_cos for every instance (one coupling function h), K per instance.
+ *  omegas    : host [count] pointers or NULL (NULL entry = zero frequencies).
+ *  o         : options as for cia_build.
+ * cia_integrate on a batch plan fills r_trace (host [count][steps+1]) with the
+ * order parameter of every instance, r_b(t) = |(1/N_b) sum_{m in b} exp(i theta_m)|.
+ * Errors as cia_build; CIA_EUNSUPPORTED for other models or graph kinds.
+ */
+cia_status cia_build_batch(int32_t count, const cia_graph *graphs, const int32_t *const *labels,
+                           const cia_coupling *couplings, const double *const *omegas,
+                           const cia_options *o, cia_plan **out);
+
+/* Instances of a plan and their offsets in the state (host [count+1], may be
+   NULL to query the count).  A plan built by cia_build reports one instance. */
+cia_status cia_batch_offsets(const cia_plan *p, int32_t *count, int64_t *offsets);
+
+/* Result of cia_autotune: the chosen remainder entries per work unit and
+   threads per block, the candidates timed, and the median time of one RHS
+   launch before and after. */
+typedef struct cia_tune_report {
+    int32_t unit_work;
+    int32_t block;
+    int32_t candidates;
+    int32_t reserved;
+    double best_us;
+    double default_us;
+} cia_tune_report;
+
+/*
+ * cia_autotune -- choose the work-unit size and block size of the stage
+ * kernel of a phase-model plan by timing one RHS launch (median of five) for
+ * every candidate on the plan's own remainder data (unit sizes 4096 ..
+ * 131072 entries, blocks of 256 and 512 threads), then keep the fastest.
+ * Results are unchanged up to summation order.  Runs on `stream` and
+ * synchronises it.  rep may be NULL.  CIA_EUNSUPPORTED for other models and
+ * for all-to-all direct plans.
+ */
+cia_status cia_autotune(cia_plan *p, void *stream, cia_tune_report *rep);
 
 /* --------------------------------------------------------------------- */
 /* Learned separable basis of the flock weight                            */
@@ -324,7 +381,8 @@ cia_status cia_p1_export(const cia_p1 *p1, int32_t *perm, int32_t *comm_off, int
 cia_status cia_p1_free(cia_p1 *p1);
 
 /* sizeof of an ABI struct by its name ("cia_graph", "cia_hypergraph",
-   "cia_coupling", "cia_options", "cia_plan_info", "cia_timing"); 0 if unknown.
+   "cia_coupling", "cia_options", "cia_plan_info", "cia_timing",
+   "cia_tune_report"); 0 if unknown.
    Lets bindings check their struct layouts. */
 size_t cia_abi_sizeof(const char *name);
 

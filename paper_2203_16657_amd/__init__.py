@@ -27,7 +27,7 @@ CIA_F32, CIA_F64 = 0, 1
 CIA_RK4, CIA_EULER = 0, 1
 CIA_BASIS_EXACT, CIA_BASIS_FOURIER, CIA_BASIS_LEARNED = 0, 1, 2
 CIA_FLAG_KEEP_LABELS, CIA_FLAG_TIMING, CIA_FLAG_NO_VALIDATE, CIA_FLAG_HIPGRAPH = 0x1, 0x2, 0x4, 0x8
-CIA_FLAG_NO_JUDGE = 0x10
+CIA_FLAG_NO_JUDGE, CIA_FLAG_AUTOTUNE = 0x10, 0x20
 CIA_FLAG_FORCE_WIDE, CIA_FLAG_FORCE_NEG32, CIA_FLAG_NO_LDS = 0x100, 0x200, 0x400
 
 _c = ctypes
@@ -67,6 +67,11 @@ class cia_plan_info(_c.Structure):
                 ("nnz_extra", _c.c_int64), ("judge_fallbacks", _c.c_int32), ("reserved", _c.c_int32)]
 
 
+class cia_tune_report(_c.Structure):
+    _fields_ = [("unit_work", _c.c_int32), ("block", _c.c_int32), ("candidates", _c.c_int32),
+                ("reserved", _c.c_int32), ("best_us", _c.c_double), ("default_us", _c.c_double)]
+
+
 class cia_timing(_c.Structure):
     _fields_ = [("stage_ms", _c.c_double), ("stage_launches", _c.c_int64), ("prep_ms", _c.c_double),
                 ("prep_launches", _c.c_int64), ("aux_ms", _c.c_double), ("aux_launches", _c.c_int64)]
@@ -76,7 +81,8 @@ EXPORTS = ["cia_build", "cia_rhs", "cia_integrate", "cia_destroy", "cia_last_err
            "cia_options_default", "cia_coupling_default", "cia_plan_get_info", "cia_plan_get_timing",
            "cia_fourier_coeffs", "cia_p1_build", "cia_p1_sizes", "cia_p1_export", "cia_p1_free",
            "cia_abi_sizeof", "cia_basis_param_count", "cia_basis_set_params", "cia_basis_get_params",
-           "cia_basis_train", "cia_basis_loss_grad", "cia_basis_features"]
+           "cia_basis_train", "cia_basis_loss_grad", "cia_basis_features", "cia_build_batch",
+           "cia_batch_offsets", "cia_autotune"]
 
 _lib = None
 
@@ -138,6 +144,12 @@ def load():
     lib.cia_basis_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _c.c_int64, _vp, _vp, _vp]
     lib.cia_basis_features.restype = _c.c_int
     lib.cia_basis_features.argtypes = [_vp, _vp, _c.c_int64, _vp, _vp]
+    lib.cia_build_batch.restype = _c.c_int
+    lib.cia_build_batch.argtypes = [_c.c_int32, _vp, _vp, _vp, _vp, P(cia_options), P(_vp)]
+    lib.cia_batch_offsets.restype = _c.c_int
+    lib.cia_batch_offsets.argtypes = [_vp, _vp, _vp]
+    lib.cia_autotune.restype = _c.c_int
+    lib.cia_autotune.argtypes = [_vp, _vp, P(cia_tune_report)]
     _lib = lib
     return lib
 
@@ -276,6 +288,51 @@ def cia_p1(n, row_ptr, col, labels=None, options=None, complete=False):
 # convenience wrapper
 # ---------------------------------------------------------------------------
 
+def cia_build_batch(graphs, labels, couplings, omegas, options: cia_options | None):
+    """graphs: list of cia_graph; labels / omegas: lists of arrays or None."""
+    lib = load()
+    count = len(graphs)
+    G = (cia_graph * count)(*graphs)
+    C = (cia_coupling * count)(*couplings)
+    keep = []
+    lab_arr = None
+    if labels is not None:
+        lab_arr = (_vp * count)()
+        for b, l in enumerate(labels):
+            if l is not None:
+                a = np.ascontiguousarray(l, dtype=np.int32)
+                keep.append(a)
+                lab_arr[b] = a.ctypes.data
+    om_arr = None
+    if omegas is not None:
+        om_arr = (_vp * count)()
+        for b, w in enumerate(omegas):
+            if w is not None:
+                a = np.ascontiguousarray(w, dtype=np.float64)
+                keep.append(a)
+                om_arr[b] = a.ctypes.data
+    out = _vp()
+    o = options if options is not None else cia_options_default()
+    _check(lib.cia_build_batch(count, _c.cast(G, _vp), None if lab_arr is None else _c.cast(lab_arr, _vp),
+                               _c.cast(C, _vp), None if om_arr is None else _c.cast(om_arr, _vp), _c.byref(o),
+                               _c.byref(out)))
+    return out.value
+
+
+def cia_batch_offsets(plan):
+    cnt = _c.c_int32(0)
+    _check(load().cia_batch_offsets(plan, _c.byref(cnt), None))
+    off = np.empty(cnt.value + 1, dtype=np.int64)
+    _check(load().cia_batch_offsets(plan, _c.byref(cnt), _np_ptr(off)))
+    return off
+
+
+def cia_autotune(plan, stream=None) -> cia_tune_report:
+    rep = cia_tune_report()
+    _check(load().cia_autotune(plan, _stream_ptr(stream), _c.byref(rep)))
+    return rep
+
+
 def cia_basis_param_count(rank: int) -> int:
     cnt = _c.c_int64(0)
     _check(load().cia_basis_param_count(int(rank), _c.byref(cnt)))
@@ -374,6 +431,34 @@ class Plan:
         o.unit_work, o.block, o.device = unit_work, block, device
         handle = cia_build(g, labels, c, omega, o)
         return cls(handle, int(n), precision, CIA_MODEL_TRIADIC)
+
+    @classmethod
+    def batch(cls, problems, method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4, flags=0, unit_work=0,
+              block=0, device=-1):
+        """Ensemble of phase-model networks: problems is a list of
+        (n, row_ptr, col, labels, omega, K); h = sin."""
+        load()
+        keep, graphs, coups = [], [], []
+        ds = np.array([0.0, 1.0])
+        dc = np.array([0.0, 0.0])
+        for (n, row_ptr, col, labels, omega, K) in problems:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            keep += [rp, cl]
+            graphs.append(cia_graph(n=int(n), kind=CIA_GRAPH_CSR, reserved=0, row_ptr=_np_ptr(rp), col=_np_ptr(cl)))
+            c = cia_coupling_default()
+            c.model, c.p, c.d_sin, c.d_cos, c.K = CIA_MODEL_PHASE, 1, _np_ptr(ds), _np_ptr(dc), float(K)
+            coups.append(c)
+        o = cia_options_default()
+        o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
+        o.unit_work, o.block, o.device = unit_work, block, device
+        h = cia_build_batch(graphs, [q[3] for q in problems], coups, [q[4] for q in problems], o)
+        plan = cls(h, int(sum(q[0] for q in problems)), precision, CIA_MODEL_PHASE)
+        plan.offsets = cia_batch_offsets(h)
+        return plan
+
+    def autotune(self, stream=None) -> cia_tune_report:
+        return cia_autotune(self.handle, stream)
 
     @classmethod
     def flock(cls, n, row_ptr, col, labels=None, K=1.0, sigma=1.0, beta=0.25, basis=CIA_BASIS_EXACT, rank=32,

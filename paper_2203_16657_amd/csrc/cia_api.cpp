@@ -8,7 +8,7 @@
 
 namespace cia {
 
-cia_status timing_begin(cia_plan *p, hipStream_t s, int kind) {
+cia_status timing_begin(cia_plan *p, hipStream_t s, int kind, int weight) {
     if (!(p->flags & CIA_FLAG_TIMING)) return CIA_OK;
     if (p->ev_used == p->events.size()) {
         cia_plan::EvPair e;
@@ -19,6 +19,7 @@ cia_status timing_begin(cia_plan *p, hipStream_t s, int kind) {
     }
     auto &e = p->events[p->ev_used];
     e.kind = kind;
+    e.weight = weight;
     CIA_HIP(hipEventRecord(e.a, s));
     p->last_stream = s;
     return CIA_OK;
@@ -40,7 +41,7 @@ cia_status timing_collect(cia_plan *p) {
         float ms = 0.f;
         CIA_HIP(hipEventElapsedTime(&ms, p->events[k].a, p->events[k].b));
         p->t_ms[p->events[k].kind] += ms;
-        p->t_count[p->events[k].kind]++;
+        p->t_count[p->events[k].kind] += p->events[k].weight;
     }
     p->ev_used = 0;
     return CIA_OK;
@@ -69,6 +70,59 @@ static void free_plan(cia_plan *p) {
     delete p;
 }
 
+// Checks the options, creates the plan on the selected device and runs
+// `fill`; on failure nothing leaks and *out stays NULL.
+template <typename Fill>
+static cia_status make_plan(const cia_options *o, int64_t n, int32_t model, cia_plan **out, Fill fill) {
+    if (o->method != CIA_METHOD_CIA && o->method != CIA_METHOD_DIRECT)
+        return set_error(CIA_EINVAL, "options.method = %d", o->method);
+    if (o->precision != CIA_F32 && o->precision != CIA_F64)
+        return set_error(CIA_EINVAL, "options.precision = %d", o->precision);
+    if (o->stepper != CIA_RK4 && o->stepper != CIA_EULER)
+        return set_error(CIA_EINVAL, "options.stepper = %d", o->stepper);
+    int ndev = 0;
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return set_error(CIA_EHIP, "no HIP device available (%s)", hipGetErrorString(he));
+    }
+    cia_plan *p = new (std::nothrow) cia_plan();
+    if (!p) return set_error(CIA_ENOMEM, "host allocation failed");
+    p->model = model;
+    p->method = o->method;
+    p->precision = o->precision;
+    p->stepper = o->stepper;
+    p->flags = o->flags;
+    p->n = n;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) cur = 0;
+    p->device = o->device >= 0 ? o->device : cur;
+    if (p->device >= ndev) {
+        delete p;
+        return set_error(CIA_EINVAL, "options.device = %d but only %d devices", o->device, ndev);
+    }
+    cia_status st = select_device(p);
+    if (st == CIA_OK) {
+        try {
+            st = fill(p);
+        } catch (const std::bad_alloc &) {
+            st = set_error(CIA_ENOMEM, "host allocation failed");
+        }
+    }
+    if (st == CIA_OK && (o->flags & CIA_FLAG_AUTOTUNE) && p->phase) {
+        st = phase_autotune(p, nullptr, nullptr);
+        if (st == CIA_EUNSUPPORTED) st = CIA_OK;   // nothing to tune
+    }
+    if (st != CIA_OK) {
+        std::string msg = cia_last_error();
+        free_plan(p);
+        set_error(st, "%s", msg.c_str());
+        return st;
+    }
+    *out = p;
+    return CIA_OK;
+}
+
 }  // namespace cia
 
 using namespace cia;
@@ -85,56 +139,56 @@ cia_status cia_build(const cia_graph *g, const int32_t *labels, const cia_coupli
     cia_options def;
     cia_options_default(&def);
     if (!o) o = &def;
-    if (o->method != CIA_METHOD_CIA && o->method != CIA_METHOD_DIRECT)
-        return set_error(CIA_EINVAL, "options.method = %d", o->method);
-    if (o->precision != CIA_F32 && o->precision != CIA_F64)
-        return set_error(CIA_EINVAL, "options.precision = %d", o->precision);
-    if (o->stepper != CIA_RK4 && o->stepper != CIA_EULER)
-        return set_error(CIA_EINVAL, "options.stepper = %d", o->stepper);
     if (g->n <= 0) return set_error(CIA_EINVAL, "graph: n = %lld, need n >= 1", (long long)g->n);
+    if (c->model != CIA_MODEL_PHASE && c->model != CIA_MODEL_TRIADIC && c->model != CIA_MODEL_FLOCK)
+        return set_error(CIA_EINVAL, "coupling.model = %d", c->model);
+    return make_plan(o, g->n, c->model, out, [&](cia_plan *p) -> cia_status {
+        if (c->model == CIA_MODEL_FLOCK) return flock_build(p, g, labels, c, o);
+        return phase_build(p, g, labels, c, omega, o);
+    });
+}
 
-    int ndev = 0;
-    hipError_t he = hipGetDeviceCount(&ndev);
-    if (he != hipSuccess || ndev == 0) {
-        (void)hipGetLastError();
-        return set_error(CIA_EHIP, "no HIP device available (%s)", hipGetErrorString(he));
-    }
-    cia_plan *p = new (std::nothrow) cia_plan();
-    if (!p) return set_error(CIA_ENOMEM, "host allocation failed");
-    p->model = c->model;
-    p->method = o->method;
-    p->precision = o->precision;
-    p->stepper = o->stepper;
-    p->flags = o->flags;
-    p->n = g->n;
-    int cur = 0;
-    if (hipGetDevice(&cur) != hipSuccess) cur = 0;
-    p->device = o->device >= 0 ? o->device : cur;
-    if (p->device >= ndev) {
-        delete p;
-        return set_error(CIA_EINVAL, "options.device = %d but only %d devices", o->device, ndev);
-    }
-    cia_status st = select_device(p);
-    if (st == CIA_OK) {
-        try {
-            switch (c->model) {
-                case CIA_MODEL_PHASE:
-                case CIA_MODEL_TRIADIC: st = phase_build(p, g, labels, c, omega, o); break;
-                case CIA_MODEL_FLOCK: st = flock_build(p, g, labels, c, o); break;
-                default: st = set_error(CIA_EINVAL, "coupling.model = %d", c->model);
-            }
-        } catch (const std::bad_alloc &) {
-            st = set_error(CIA_ENOMEM, "host allocation failed");
+cia_status cia_build_batch(int32_t count, const cia_graph *graphs, const int32_t *const *labels,
+                           const cia_coupling *couplings, const double *const *omegas, const cia_options *o,
+                           cia_plan **out) {
+    clear_error();
+    if (!out) return set_error(CIA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1) return set_error(CIA_EINVAL, "count = %d", count);
+    if (!graphs || !couplings) return set_error(CIA_EINVAL, "graphs/couplings is NULL");
+    cia_options def;
+    cia_options_default(&def);
+    if (!o) o = &def;
+    int64_t n = 0;
+    for (int32_t b = 0; b < count; b++) n += graphs[b].n > 0 ? graphs[b].n : 0;
+    return make_plan(o, n, CIA_MODEL_PHASE, out, [&](cia_plan *p) -> cia_status {
+        return batch_build(p, count, graphs, labels, couplings, omegas, o);
+    });
+}
+
+cia_status cia_batch_offsets(const cia_plan *p, int32_t *count, int64_t *offsets) {
+    clear_error();
+    if (!p || !count) return set_error(CIA_EINVAL, "NULL pointer");
+    if (p->batch_off.empty()) {
+        *count = 1;
+        if (offsets) {
+            offsets[0] = 0;
+            offsets[1] = p->n;
         }
+        return CIA_OK;
     }
-    if (st != CIA_OK) {
-        std::string msg = cia_last_error();
-        free_plan(p);
-        set_error(st, "%s", msg.c_str());
-        return st;
-    }
-    *out = p;
+    *count = (int32_t)p->batch_off.size() - 1;
+    if (offsets)
+        for (size_t k = 0; k < p->batch_off.size(); k++) offsets[k] = p->batch_off[k];
     return CIA_OK;
+}
+
+cia_status cia_autotune(cia_plan *p, void *stream, cia_tune_report *rep) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    if (!p->phase) return set_error(CIA_EUNSUPPORTED, "only phase-model plans are tuned");
+    CIA_TRY(select_device(p));
+    return phase_autotune(p, static_cast<hipStream_t>(stream), rep);
 }
 
 cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream) {

@@ -407,6 +407,7 @@ size_t cia_abi_sizeof(const char *name) {
     if (!std::strcmp(name, "cia_options")) return sizeof(cia_options);
     if (!std::strcmp(name, "cia_plan_info")) return sizeof(cia_plan_info);
     if (!std::strcmp(name, "cia_timing")) return sizeof(cia_timing);
+    if (!std::strcmp(name, "cia_tune_report")) return sizeof(cia_tune_report);
     return 0;
 }
 

@@ -160,6 +160,7 @@ struct PhaseArgs {
     double2 *r_part;          // [nunits] partial sum of z for the order parameter
     const R *state_in;        // user order (M_PREP)
     R *state_out;             // user order (M_RHS)
+    const R *kn;              // batched ensembles: K_b / N_b per node (community order), else NULL
     R Kn, dt, d0, hzero;
     R K2n;                    // triadic strength K2 / N^2
     R dsin[PMAX + 1], dcos[PMAX + 1];
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
         const bool mine = lane < S.rows;
         const int i = S.row0 + lane;
         // operands of the combine / stage update, loaded before the gather
-        R tn = (R)0, om = (R)0, av = (R)0, thc = (R)0;
+        R tn = (R)0, om = (R)0, av = (R)0, thc = (R)0, knv = a.Kn;
         int cv = 0;
         if (mine) {
             if (mode == M_PREP) {
@@ -399,6 +400,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
             } else {
                 if (mode != M_RHS) tn = a.theta_n[i];
                 if (a.omega) om = a.omega[i];
+                if (a.kn) knv = a.kn[i];
                 if (mode == M_RK4 && a.stage > 0) av = a.acc[i];
                 if (a.d0 != (R)0) cv = a.cnt[i];
                 if (WIDE && wide) thc = a.th_in[i];
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                         s += a.dcos[k + 1] * B.x + a.dsin[k + 1] * B.y;
                         if (k + 1 < P) zk = cmul(zk, z);
                     }
-                    H = om + a.Kn * s;
+                    H = om + knv * s;
                     if (TRI) {
                         // sum over ordered distinct partner pairs of z_j z_k, then
                         // Im(conj(z_m)^2 * .) (App. A.7 with lambda = (1,1,-2))
@@ -490,7 +492,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                         s += (double)a.dcos[k + 1] * B.x + (double)a.dsin[k + 1] * B.y;
                         if (k + 1 < P) zk = cmul(zk, z);
                     }
-                    H = (R)((double)om + (double)a.Kn * s);
+                    H = (R)((double)om + (double)knv * s);
                 }
                 if (mode == M_RHS) {
                     a.state_out[a.perm[i]] = H;
@@ -673,8 +675,9 @@ __global__ __launch_bounds__(256) void triadic_present_kernel(const TriBlock *bl
 }
 
 // r(t) = |(1/N) sum z| from the unit partials, fixed order, one block.
+// With slot_ctr (replayed graphs) the output slot is r_out + *slot_ctr.
 __global__ __launch_bounds__(256) void order_reduce_kernel(const double2 *r_part, int nunits,
-                                                           double invN, double *r_out) {
+                                                           double invN, double *r_out, const int64_t *slot_ctr) {
     __shared__ double sx[256], sy[256];
     double x = 0.0, y = 0.0;
     for (int j = threadIdx.x; j < nunits; j += 256) {
@@ -691,7 +694,45 @@ __global__ __launch_bounds__(256) void order_reduce_kernel(const double2 *r_part
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) r_out[0] = sqrt(sx[0] * sx[0] + sy[0] * sy[0]) * invN;
+    if (threadIdx.x == 0) r_out[slot_ctr ? *slot_ctr : 0] = sqrt(sx[0] * sx[0] + sy[0] * sy[0]) * invN;
+}
+
+// Batched ensembles: r_b(t) = |(1/N_b) sum over the nodes of instance b of z|,
+// one block per instance over its positions (grouped, increasing), FP64,
+// fixed order.  Output r_out[b * stride + slot (+ *slot_ctr)].
+template <typename R>
+__global__ __launch_bounds__(256) void order_grouped_kernel(const cx<R> *cs, const int32_t *grp_idx,
+                                                            const int64_t *grp_off, double *r_out, int64_t stride,
+                                                            int64_t slot, const int64_t *slot_ctr) {
+    __shared__ double sx[256], sy[256];
+    const int b = blockIdx.x;
+    const int64_t e0 = grp_off[b], e1 = grp_off[b + 1];
+    double x = 0.0, y = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const cx<R> z = cs[grp_idx[e]];
+        x += (double)z.x;
+        y += (double)z.y;
+    }
+    sx[threadIdx.x] = x;
+    sy[threadIdx.x] = y;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sx[threadIdx.x] += sx[threadIdx.x + s];
+            sy[threadIdx.x] += sy[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double inv = e1 > e0 ? 1.0 / (double)(e1 - e0) : 0.0;
+        r_out[(int64_t)b * stride + slot + (slot_ctr ? *slot_ctr : 0)] =
+            sqrt(sx[0] * sx[0] + sy[0] * sy[0]) * inv;
+    }
+}
+
+// advances the slot counter of replayed step graphs (one thread; vector store)
+__global__ void counter_kernel(int64_t *ctr, int64_t set, int add) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] = add ? ctr[0] + set : set;
 }
 
 template <typename R>
@@ -836,6 +877,38 @@ struct PhaseState {
     int64_t r_cap = 0;
     void *hbuf = nullptr;
     void *coef = nullptr;   // [2][PMAX+1] device copy of dsin/dcos (all-to-all kernel)
+    // batched ensembles
+    int32_t batch = 0;            // instances (0: a single network)
+    int32_t *grp_idx = nullptr;   // positions grouped by instance
+    int64_t *grp_off = nullptr;   // [batch+1]
+    void *kn = nullptr;           // K_b / N_b per position
+    // capacities of the unit-dependent buffers (the autotuner rebuilds units)
+    size_t units_cap = 0, q_cap = 0, rpart_cap = 0;
+    // host inputs of make_units, kept for the autotuner
+    std::vector<Slice> h_slices;
+    std::vector<int32_t> h_seg_off, h_comm_off;
+    std::vector<char> h_staged;
+    int32_t h_ncomm = 0;
+    uint32_t h_flags = 0;
+    int64_t unit_work = 32768;
+    void *tune_in = nullptr, *tune_out = nullptr;
+    // replayed RK4 step graph
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    double g_dt = 0.0;
+    int64_t g_stride = 0;
+    bool g_want_r = false;
+    double *g_r = nullptr;
+    int64_t *r_ctr = nullptr;
+    ~PhaseState() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto &e : gev)
+            if (e) (void)hipEventDestroy(e);
+        if (gstream) (void)hipStreamDestroy(gstream);
+    }
 };
 
 // Row lists handed to the packer: old-order CSR lists of up to four streams.
@@ -1162,7 +1235,7 @@ static cia_status triadic_lists(const P1 &p1, const cia_hypergraph *h, bool want
 }
 
 cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
-                       const double *omega, const cia_options *o) {
+                       const double *omega, const cia_options *o, const BatchSpec *bs) {
     PhaseState *s = new (std::nothrow) PhaseState();
     if (!s) return set_error(CIA_ENOMEM, "host allocation failed");
     p->phase = s;
@@ -1328,16 +1401,24 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     int32_t nslots = 0;
     if (!s->complete_direct) {
         const int32_t nc = s->direct ? 0 : p1.ncomm;
-        int64_t target = o->unit_work > 0 ? o->unit_work : 32768;
+        s->unit_work = o->unit_work > 0 ? o->unit_work : 32768;
+        s->h_slices = sell.slices;
+        s->h_flags = o->flags;
+        s->h_staged = comm_staged;
         if (s->direct) {
             // the direct path has one segment per community too; treat all as outside rows
-            Sell flat;
-            flat.slices = sell.slices;
-            flat.seg_slice_off = {0, (int32_t)sell.slices.size()};
-            nslots = make_units(flat, std::vector<int32_t>{0}, 0, target, 4, comm_staged, o->flags, units);
+            s->h_seg_off = {0, (int32_t)sell.slices.size()};
+            s->h_comm_off = {0};
+            s->h_ncomm = 0;
         } else {
-            nslots = make_units(sell, p1.comm_off, nc, target, 4, comm_staged, o->flags, units);
+            s->h_seg_off = sell.seg_slice_off;
+            s->h_comm_off = p1.comm_off;
+            s->h_ncomm = nc;
         }
+        Sell view;
+        view.slices = s->h_slices;
+        view.seg_slice_off = s->h_seg_off;
+        nslots = make_units(view, s->h_comm_off, s->h_ncomm, s->unit_work, 4, s->h_staged, s->h_flags, units);
         s->ncomm = nc;
     }
     if (f64)
@@ -1385,6 +1466,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     if (!s->complete_direct) {
         if (units.empty()) units.push_back(Unit{0, 0, 0, 0, 0, 0, 0, 0});
         CIA_TRY(dupload(p, &s->units, units.data(), units.size()));
+        s->units_cap = units.size();
         if (sell.slices.empty()) sell.slices.push_back(Slice{});
         CIA_TRY(dupload(p, &s->slices, sell.slices.data(), sell.slices.size()));
         CIA_TRY(dupload(p, &s->negdata, sell.data[0].data(), sell.data[0].size()));
@@ -1430,7 +1512,38 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         s->th[b] = raw;
         CIA_TRY(dalloc(p, &s->q[b], (size_t)std::max(1, nslots) * s->P));
     }
+    s->q_cap = (size_t)std::max(1, nslots) * s->P;
     CIA_TRY(dalloc(p, &s->r_part, (size_t)std::max(1, s->nunits) + 1024));
+    s->rpart_cap = (size_t)std::max(1, s->nunits) + 1024;
+    if (bs) {
+        // instance of every position, positions grouped by instance, K_b / N_b
+        s->batch = bs->count;
+        std::vector<int64_t> goff(bs->count + 1, 0);
+        std::vector<int32_t> inst(n), gidx(n);
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t u = perm2[i];
+            inst[i] = (int32_t)(std::upper_bound(bs->offsets, bs->offsets + bs->count + 1, u) - bs->offsets - 1);
+            goff[inst[i] + 1]++;
+        }
+        for (int32_t b = 0; b < bs->count; b++) goff[b + 1] += goff[b];
+        std::vector<int64_t> fill(goff.begin(), goff.end() - 1);
+        for (int64_t i = 0; i < n; i++) gidx[fill[inst[i]]++] = (int32_t)i;
+        CIA_TRY(dupload(p, &s->grp_idx, gidx.data(), n));
+        CIA_TRY(dupload(p, &s->grp_off, goff.data(), goff.size()));
+        if (f64) {
+            std::vector<double> k(n);
+            for (int64_t i = 0; i < n; i++) k[i] = bs->kn[perm2[i]];
+            double *d;
+            CIA_TRY(dupload(p, &d, k.data(), n));
+            s->kn = d;
+        } else {
+            std::vector<float> k(n);
+            for (int64_t i = 0; i < n; i++) k[i] = (float)bs->kn[perm2[i]];
+            float *d;
+            CIA_TRY(dupload(p, &d, k.data(), n));
+            s->kn = d;
+        }
+    }
     if (s->tri && s->direct) {
         // present-pair enumeration blocks: 256 centres of one community each
         std::vector<TriBlock> tb;
@@ -1495,6 +1608,7 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
     a.cnt = s->cnt;
     a.perm = s->perm;
     a.omega = static_cast<const R *>(s->omega);
+    a.kn = static_cast<const R *>(s->kn);
     a.theta_n = static_cast<R *>(s->theta_n);
     a.acc = static_cast<R *>(s->acc);
     a.Kn = (R)s->Kn;
@@ -1525,6 +1639,20 @@ static void launch_stage_v(PhaseState *s, const PhaseArgs<R> &a, hipStream_t st)
         hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, true, false>), g, b, s->smem, st, a);
     else
         hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, false, false>), g, b, s->smem, st, a);
+}
+
+template <typename R, int BLOCK>
+static void launch_stage_v_any(PhaseState *s, const PhaseArgs<R> &a, hipStream_t st) {
+    switch (s->P) {
+        case 1: launch_stage_v<R, 1, BLOCK>(s, a, st); break;
+        case 2: launch_stage_v<R, 2, BLOCK>(s, a, st); break;
+        case 3: launch_stage_v<R, 3, BLOCK>(s, a, st); break;
+        case 4: launch_stage_v<R, 4, BLOCK>(s, a, st); break;
+        case 5: launch_stage_v<R, 5, BLOCK>(s, a, st); break;
+        case 6: launch_stage_v<R, 6, BLOCK>(s, a, st); break;
+        case 7: launch_stage_v<R, 7, BLOCK>(s, a, st); break;
+        default: launch_stage_v<R, 8, BLOCK>(s, a, st); break;
+    }
 }
 
 template <typename R, int P>
@@ -1589,7 +1717,7 @@ static cia_status launch_all2all(cia_plan *p, PhaseState *s, hipStream_t st, con
 static cia_status launch_order_reduce(cia_plan *p, PhaseState *s, hipStream_t st, int nparts, double *slot) {
     CIA_TRY(timing_begin(p, st, KK_AUX));
     hipLaunchKernelGGL(order_reduce_kernel, dim3(1), dim3(256), 0, st, s->r_part, nparts,
-                       1.0 / (double)p->n, slot);
+                       1.0 / (double)p->n, slot, (const int64_t *)nullptr);
     CIA_HIP(hipGetLastError());
     return timing_end(p, st);
 }
@@ -1643,24 +1771,64 @@ static cia_status rhs_impl(cia_plan *p, PhaseState *s, const void *state, void *
     return launch_stage<R>(p, s, a, st, KK_STAGE);
 }
 
+// r(t) of the current z: the global order parameter from the unit partials,
+// or per instance for batched ensembles.  slot: index in the trace; ctr:
+// slot counter of replayed graphs (then `slot` is the base).
+template <typename R>
+static cia_status launch_order(cia_plan *p, PhaseState *s, hipStream_t st, const void *cs, int64_t slot,
+                               int64_t stride, const int64_t *ctr, bool timed) {
+    if (timed) CIA_TRY(timing_begin(p, st, KK_AUX));
+    if (s->batch > 0) {
+        hipLaunchKernelGGL((order_grouped_kernel<R>), dim3(s->batch), dim3(256), 0, st,
+                           static_cast<const cx<R> *>(cs), s->grp_idx, s->grp_off, s->r_dev, stride, slot, ctr);
+    } else {
+        hipLaunchKernelGGL(order_reduce_kernel, dim3(1), dim3(256), 0, st, s->r_part, s->nunits,
+                           1.0 / (double)p->n, s->r_dev + slot, ctr);
+    }
+    CIA_HIP(hipGetLastError());
+    return timed ? timing_end(p, st) : CIA_OK;
+}
+
+template <typename R>
+static PhaseArgs<R> stage_args(cia_plan *p, PhaseState *s, bool rk4, int q, double dt, int cur, bool want_r) {
+    PhaseArgs<R> a = base_args<R>(p, s);
+    a.mode = rk4 ? M_RK4 : M_EULER;
+    a.stage = q;
+    a.dt = (R)dt;
+    a.cs_in = static_cast<const cx<R> *>(s->cs[cur]);
+    a.cs_out = static_cast<cx<R> *>(s->cs[cur ^ 1]);
+    a.q_in = s->q[cur];
+    a.q_out = s->q[cur ^ 1];
+    a.th_in = static_cast<const R *>(s->th[cur]);
+    a.th_out = static_cast<R *>(s->th[cur ^ 1]);
+    a.r_part = s->r_part;
+    a.want_r = want_r;
+    return a;
+}
+
 template <typename R>
 static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double dt, int64_t steps,
                                  double *r_trace, hipStream_t st) {
     const int64_t n = p->n;
     const bool want_r = r_trace != nullptr;
-    if (want_r && s->r_cap < steps + 1) {
+    const int64_t nr = s->batch > 0 ? s->batch : 1;   // traces
+    const int64_t stride = steps + 1;
+    if (want_r && s->r_cap < nr * stride) {
         if (s->r_dev) {
             CIA_HIP(hipFree(s->r_dev));
             for (auto &q : p->dev_allocs)
                 if (q == s->r_dev) q = nullptr;
             s->r_dev = nullptr;
         }
-        CIA_TRY(dalloc(p, &s->r_dev, (size_t)steps + 1));
-        s->r_cap = steps + 1;
+        CIA_TRY(dalloc(p, &s->r_dev, (size_t)(nr * stride)));
+        s->r_cap = nr * stride;
     }
     const bool rk4 = p->stepper == CIA_RK4;
     const int64_t grid = (n + 255) / 256;
     int cur = 0;
+    // the unit partials of r are produced by the stage kernel for single
+    // networks; ensembles reduce per instance from z instead
+    const bool part_r = want_r && s->batch == 0;
     if (s->complete_direct) {
         CIA_TRY(timing_begin(p, st, KK_PREP));
         hipLaunchKernelGGL((z_from_theta_kernel<R>), dim3(grid), dim3(256), 0, st, n, s->perm,
@@ -1692,6 +1860,20 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
             }
         }
     } else {
+        // (the direct triadic path launches an extra kernel per stage: no graph)
+        const bool replay = (p->flags & CIA_FLAG_HIPGRAPH) && rk4 && steps > 0 && !(s->tri && s->direct);
+        hipStream_t ws = st;   // stream the steps run on
+        if (replay) {
+            if (!s->gstream) {
+                CIA_HIP(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
+                CIA_HIP(hipEventCreateWithFlags(&s->gev[0], hipEventDisableTiming));
+                CIA_HIP(hipEventCreateWithFlags(&s->gev[1], hipEventDisableTiming));
+                CIA_TRY(dalloc(p, &s->r_ctr, 1));
+            }
+            CIA_HIP(hipEventRecord(s->gev[0], st));
+            CIA_HIP(hipStreamWaitEvent(s->gstream, s->gev[0], 0));
+            ws = s->gstream;
+        }
         PhaseArgs<R> a = base_args<R>(p, s);
         a.mode = M_PREP;
         a.state_in = static_cast<const R *>(state);
@@ -1699,29 +1881,74 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         a.q_out = s->q[0];
         a.th_out = static_cast<R *>(s->th[0]);
         a.r_part = s->r_part;
-        a.want_r = want_r;
-        CIA_TRY(launch_stage<R>(p, s, a, st, KK_PREP));
-        if (want_r) CIA_TRY(launch_order_reduce(p, s, st, s->nunits, s->r_dev));
-        for (int64_t k = 0; k < steps; k++) {
-            const int nst = rk4 ? 4 : 1;
-            for (int q = 0; q < nst; q++) {
-                a = base_args<R>(p, s);
-                a.mode = rk4 ? M_RK4 : M_EULER;
-                a.stage = q;
-                a.dt = (R)dt;
-                a.cs_in = static_cast<const cx<R> *>(s->cs[cur]);
-                a.cs_out = static_cast<cx<R> *>(s->cs[cur ^ 1]);
-                a.q_in = s->q[cur];
-                a.q_out = s->q[cur ^ 1];
-                a.th_in = static_cast<const R *>(s->th[cur]);
-                a.th_out = static_cast<R *>(s->th[cur ^ 1]);
-                a.r_part = s->r_part;
-                a.want_r = want_r && q == nst - 1;
-                CIA_TRY(launch_stage<R>(p, s, a, st, KK_STAGE));
-                cur ^= 1;
+        a.want_r = part_r;
+        CIA_TRY(launch_stage<R>(p, s, a, ws, KK_PREP));
+        if (want_r) CIA_TRY(launch_order<R>(p, s, ws, s->cs[0], 0, stride, nullptr, true));
+        if (replay) {
+            // one RK4 step (four stage launches, r(t) and its slot counter) as a
+            // graph, instantiated once per (dt, trace) and replayed every step
+            if (!s->gexec || s->g_dt != dt || s->g_want_r != want_r || s->g_r != s->r_dev ||
+                s->g_stride != stride) {
+                if (s->gexec) CIA_HIP(hipGraphExecDestroy(s->gexec));
+                if (s->graph) CIA_HIP(hipGraphDestroy(s->graph));
+                s->gexec = nullptr;
+                s->graph = nullptr;
+                CIA_HIP(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
+                for (int q = 0; q < 4; q++) {
+                    PhaseArgs<R> b = stage_args<R>(p, s, true, q, dt, q & 1, part_r && q == 3);
+                    if (s->block == 512) launch_stage_v_any<R, 512>(s, b, ws);
+                    else launch_stage_v_any<R, 256>(s, b, ws);
+                }
+                if (want_r) {
+                    CIA_TRY(launch_order<R>(p, s, ws, s->cs[0], 1, stride, s->r_ctr, false));
+                    hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, ws, s->r_ctr, (int64_t)1, 1);
+                }
+                hipGraph_t gr = nullptr;
+                const hipError_t ec = hipStreamEndCapture(ws, &gr);
+                if (ec != hipSuccess) return set_error(CIA_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+                s->graph = gr;
+                CIA_HIP(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+                s->g_dt = dt;
+                s->g_stride = stride;
+                s->g_want_r = want_r;
+                s->g_r = s->r_dev;
             }
-            if (want_r) CIA_TRY(launch_order_reduce(p, s, st, s->nunits, s->r_dev + k + 1));
+            if (want_r) hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, ws, s->r_ctr, (int64_t)0, 0);
+            CIA_HIP(hipGetLastError());
+            for (int64_t k = 0; k < steps; k++) {
+                CIA_TRY(timing_begin(p, ws, KK_STAGE, 4));
+                CIA_HIP(hipGraphLaunch(s->gexec, ws));
+                CIA_TRY(timing_end(p, ws));
+            }
+        } else {
+            for (int64_t k = 0; k < steps; k++) {
+                const int nst = rk4 ? 4 : 1;
+                for (int q = 0; q < nst; q++) {
+                    a = stage_args<R>(p, s, rk4, q, dt, cur, part_r && q == nst - 1);
+                    CIA_TRY(launch_stage<R>(p, s, a, ws, KK_STAGE));
+                    cur ^= 1;
+                }
+                if (want_r) CIA_TRY(launch_order<R>(p, s, ws, s->cs[cur], k + 1, stride, nullptr, true));
+            }
         }
+        CIA_TRY(timing_begin(p, ws, KK_AUX));
+        hipLaunchKernelGGL((permute_out_kernel<R>), dim3(grid), dim3(256), 0, ws, n, s->perm,
+                           static_cast<const R *>(s->theta_n), static_cast<R *>(state));
+        CIA_HIP(hipGetLastError());
+        CIA_TRY(timing_end(p, ws));
+        if (replay) {
+            CIA_HIP(hipEventRecord(s->gev[1], ws));
+            CIA_HIP(hipStreamWaitEvent(st, s->gev[1], 0));
+        }
+        if (want_r) {
+            CIA_HIP(hipMemcpyAsync(r_trace, s->r_dev, sizeof(double) * nr * stride, hipMemcpyDeviceToHost, st));
+            CIA_HIP(hipStreamSynchronize(st));
+            for (int64_t k = 0; k < nr * stride; k++)
+                if (!std::isfinite(r_trace[k]))
+                    return set_error(CIA_ENONFINITE, "state became non-finite (r trace entry %lld = %g)",
+                                     (long long)k, r_trace[k]);
+        }
+        return CIA_OK;
     }
     CIA_TRY(timing_begin(p, st, KK_AUX));
     hipLaunchKernelGGL((permute_out_kernel<R>), dim3(grid), dim3(256), 0, st, n, s->perm,
@@ -1737,6 +1964,140 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
                                  r_trace[k]);
     }
     return CIA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: unit size and block size, timed on the plan's own data
+// ---------------------------------------------------------------------------
+
+// Make the units for `target` and upload them (growing the unit-dependent
+// buffers when needed).
+static cia_status apply_units(cia_plan *p, PhaseState *s, int64_t target) {
+    Sell view;
+    view.slices = s->h_slices;
+    view.seg_slice_off = s->h_seg_off;
+    std::vector<Unit> units;
+    const int32_t nslots = make_units(view, s->h_comm_off, s->h_ncomm, target, 4, s->h_staged, s->h_flags, units);
+    if (units.empty()) units.push_back(Unit{0, 0, 0, 0, 0, 0, 0, 0});
+    if (units.size() > s->units_cap) {
+        CIA_TRY(dalloc(p, &s->units, units.size()));
+        s->units_cap = units.size();
+    }
+    CIA_HIP(hipMemcpy(s->units, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice));
+    const size_t qneed = (size_t)std::max(1, nslots) * s->P;
+    if (qneed > s->q_cap) {
+        for (int b = 0; b < 2; b++) CIA_TRY(dalloc(p, &s->q[b], qneed));
+        s->q_cap = qneed;
+    }
+    if (units.size() + 1024 > s->rpart_cap) {
+        CIA_TRY(dalloc(p, &s->r_part, units.size() + 1024));
+        s->rpart_cap = units.size() + 1024;
+    }
+    s->nunits = (int32_t)units.size();
+    s->unit_work = target;
+    // a captured step graph holds the old launch shape
+    if (s->gexec) {
+        CIA_HIP(hipGraphExecDestroy(s->gexec));
+        s->gexec = nullptr;
+    }
+    if (s->graph) {
+        CIA_HIP(hipGraphDestroy(s->graph));
+        s->graph = nullptr;
+    }
+    return CIA_OK;
+}
+
+template <typename R>
+static cia_status tune_impl(cia_plan *p, PhaseState *s, hipStream_t st, cia_tune_report *rep) {
+    const int64_t n = p->n;
+    if (!s->tune_in) {
+        unsigned char *raw;
+        CIA_TRY(dalloc(p, &raw, sizeof(R) * n));
+        CIA_HIP(hipMemset(raw, 0, sizeof(R) * n));
+        s->tune_in = raw;
+        CIA_TRY(dalloc(p, &raw, sizeof(R) * n));
+        s->tune_out = raw;
+    }
+    hipEvent_t e0, e1;
+    CIA_HIP(hipEventCreate(&e0));
+    CIA_HIP(hipEventCreate(&e1));
+    // time of one RHS launch (median of 5 after 2 warm-up launches)
+    auto measure = [&](double *us) -> cia_status {
+        PhaseArgs<R> a = base_args<R>(p, s);
+        a.mode = M_PREP;
+        a.state_in = static_cast<const R *>(s->tune_in);
+        a.cs_out = static_cast<cx<R> *>(s->cs[0]);
+        a.q_out = s->q[0];
+        a.th_out = static_cast<R *>(s->th[0]);
+        a.r_part = s->r_part;
+        if (s->block == 512) launch_stage_v_any<R, 512>(s, a, st);
+        else launch_stage_v_any<R, 256>(s, a, st);
+        a = base_args<R>(p, s);
+        a.mode = M_RHS;
+        a.cs_in = static_cast<const cx<R> *>(s->cs[0]);
+        a.q_in = s->q[0];
+        a.th_in = static_cast<const R *>(s->th[0]);
+        a.state_out = static_cast<R *>(s->tune_out);
+        std::vector<float> t;
+        for (int k = 0; k < 7; k++) {
+            CIA_HIP(hipEventRecord(e0, st));
+            if (s->block == 512) launch_stage_v_any<R, 512>(s, a, st);
+            else launch_stage_v_any<R, 256>(s, a, st);
+            CIA_HIP(hipEventRecord(e1, st));
+            CIA_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            CIA_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (k >= 2) t.push_back(ms);
+        }
+        CIA_HIP(hipGetLastError());
+        std::sort(t.begin(), t.end());
+        *us = 1e3 * t[t.size() / 2];
+        return CIA_OK;
+    };
+    const int64_t def_work = s->unit_work;
+    const int def_block = s->block;
+    double def_us = 0.0;
+    CIA_TRY(measure(&def_us));
+    double best_us = def_us;
+    int64_t best_work = def_work;
+    int best_block = def_block;
+    int ncand = 0;
+    static const int64_t works[] = {4096, 8192, 16384, 32768, 65536, 131072};
+    static const int blocks[] = {256, 512};
+    for (int bl : blocks)
+        for (int64_t w : works) {
+            s->block = bl;
+            CIA_TRY(apply_units(p, s, w));
+            double us = 0.0;
+            CIA_TRY(measure(&us));
+            ncand++;
+            if (us < best_us) {
+                best_us = us;
+                best_work = w;
+                best_block = bl;
+            }
+        }
+    s->block = best_block;
+    CIA_TRY(apply_units(p, s, best_work));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->info.nunits = s->nunits;
+    if (rep) {
+        rep->unit_work = (int32_t)best_work;
+        rep->block = best_block;
+        rep->candidates = ncand;
+        rep->reserved = 0;
+        rep->best_us = best_us;
+        rep->default_us = def_us;
+    }
+    return CIA_OK;
+}
+
+cia_status phase_autotune(cia_plan *p, hipStream_t st, cia_tune_report *rep) {
+    PhaseState *s = p->phase;
+    if (s->complete_direct || s->h_slices.empty())
+        return set_error(CIA_EUNSUPPORTED, "nothing to tune on an all-to-all direct plan");
+    return s->f64 ? tune_impl<double>(p, s, st, rep) : tune_impl<float>(p, s, st, rep);
 }
 
 cia_status phase_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t st) {

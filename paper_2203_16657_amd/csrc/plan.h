@@ -28,12 +28,15 @@ struct cia_plan {
     struct EvPair {
         hipEvent_t a, b;
         int kind;
+        int weight;   // launches the bracket stands for
     };
     std::vector<EvPair> events;
     size_t ev_used = 0;
     double t_ms[3] = {0, 0, 0};
     int64_t t_count[3] = {0, 0, 0};
     hipStream_t last_stream = nullptr;
+
+    std::vector<int64_t> batch_off;   // batched ensembles: instance b owns [off[b], off[b+1])
 
     cia::PhaseState *phase = nullptr;
     cia::TriadicState *tri = nullptr;
@@ -66,13 +69,25 @@ cia_status dupload(cia_plan *p, T **ptr, const T *host, size_t count) {
 }
 
 // Event bracketing of kernel launches (only with CIA_FLAG_TIMING).
-cia_status timing_begin(cia_plan *p, hipStream_t s, int kind);
+cia_status timing_begin(cia_plan *p, hipStream_t s, int kind, int weight = 1);
 cia_status timing_end(cia_plan *p, hipStream_t s);
 cia_status timing_collect(cia_plan *p);
 
+// A batched ensemble as one network: the disjoint union of the instances,
+// instance b owning user ids [offsets[b], offsets[b+1]) with coupling scale
+// kn[u] = K_b / N_b for each of its nodes u.
+struct BatchSpec {
+    int32_t count;
+    const int64_t *offsets;   // [count+1]
+    const double *kn;         // [offsets[count]]
+};
+
 // model entry points (phase model: cia_phase.hip)
 cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
-                       const double *omega, const cia_options *o);
+                       const double *omega, const cia_options *o, const BatchSpec *bs = nullptr);
+cia_status phase_autotune(cia_plan *p, hipStream_t s, cia_tune_report *rep);
+cia_status batch_build(cia_plan *p, int32_t count, const cia_graph *graphs, const int32_t *const *labels,
+                       const cia_coupling *couplings, const double *const *omegas, const cia_options *o);
 cia_status phase_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t s);
 cia_status phase_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
                            hipStream_t s);

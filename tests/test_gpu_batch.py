@@ -1,0 +1,219 @@
+"""GPU parity of batched ensembles (many Kuramoto networks in one plan, each
+with its own N_b, K_b, omega and communities), the replayed RK4 step graph
+and the autotuner, against the FP64 oracle run per instance."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2203_16657_amd as cia
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cia.load()
+    return cia, torch
+
+
+def ensemble(count, n_lo, n_hi):
+    return [W.ensemble_member(b, n_lo=n_lo, n_hi=n_hi, count=count) for b in range(count)]
+
+
+def problems(ens, with_omega=True):
+    return [(P.graph.n, P.graph.row_ptr, P.graph.col, P.graph.labels, P.omega if with_omega else None, P.K)
+            for P in ens]
+
+
+def circ(a, b):
+    return np.abs(np.remainder(a - b + np.pi, 2 * np.pi) - np.pi)
+
+
+def test_batch_rhs_per_instance(env):
+    cia, torch = env
+    # frequencies left out: the output is then the coupling part itself, free
+    # of the FP32 rounding of omega + coupling (the FP64 omega path is covered
+    # by the trajectory tests)
+    ens = ensemble(24, 300, 5000)
+    plan = cia.Plan.batch(problems(ens, with_omega=False))
+    off = plan.offsets
+    assert len(off) == 25 and off[-1] == sum(P.graph.n for P in ens)
+    th = torch.as_tensor(np.concatenate([P.theta0 for P in ens]).astype(np.float32), device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    th64 = th.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for b, P in enumerate(ens):
+        g = P.graph
+        sl = slice(off[b], off[b + 1])
+        cw = oracle.phase_rhs(g.n, g.row_ptr, g.col, None, P.K, [0, 1], [0, 0], th64[sl])
+        cg = got[sl]
+        if np.abs(cw).max() == 0.0:
+            assert np.abs(cg).max() < 1e-6, b   # K_0 = 0
+            continue
+        e = np.abs(cg - cw).max() / np.abs(cw).max()
+        worst = max(worst, e)
+    say("batch rhs: instances", len(ens), "worst coupling rel_inf", worst, "units", plan.info().nunits)
+    assert worst < 1e-5
+
+
+@pytest.mark.parametrize("flags", [0, 0x8])
+def test_batch_trajectory_and_order_parameter(env, flags):
+    cia, torch = env
+    ens = ensemble(12, 300, 3000)
+    steps, dt = 40, 0.01
+    plan = cia.Plan.batch(problems(ens), flags=flags)
+    off = plan.offsets
+    th0 = np.concatenate([P.theta0 for P in ens]).astype(np.float32)
+    th = torch.as_tensor(th0, device="cuda")
+    r = np.zeros(len(ens) * (steps + 1))
+    plan.integrate(th, dt, steps, r)
+    got = th.cpu().numpy().astype(np.float64)
+    r = r.reshape(len(ens), steps + 1)
+    we, wr = 0.0, 0.0
+    for b, P in enumerate(ens):
+        g = P.graph
+        sl = slice(off[b], off[b + 1])
+        ref, rref = oracle.phase_integrate(g.n, g.row_ptr, g.col, P.omega, P.K, [0, 1], [0, 0],
+                                           th0[sl].astype(np.float64), dt, steps, trace=True)
+        we = max(we, circ(got[sl], ref).max())
+        wr = max(wr, np.abs(r[b] - rref).max())
+    say("batch trajectory flags", flags, "max circular err", we, "max r err", wr)
+    assert we < 1e-4 and wr < 1e-5
+
+
+def test_batch_equals_sequential_plans(env):
+    cia, torch = env
+    ens = ensemble(8, 500, 4000)
+    steps, dt = 30, 0.01
+    plan = cia.Plan.batch(problems(ens))
+    off = plan.offsets
+    th0 = np.concatenate([P.theta0 for P in ens]).astype(np.float32)
+    th = torch.as_tensor(th0, device="cuda")
+    plan.integrate(th, dt, steps)
+    got = th.cpu().numpy()
+    for b, P in enumerate(ens):
+        g = P.graph
+        single = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K)
+        t1 = torch.as_tensor(P.theta0.astype(np.float32), device="cuda")
+        single.integrate(t1, dt, steps)
+        d = circ(t1.cpu().numpy().astype(np.float64), got[off[b]:off[b + 1]].astype(np.float64)).max()
+        assert d < 2e-5, (b, d)
+
+
+def test_graph_replay_is_bitwise_identical(env):
+    cia, torch = env
+    # single network (config-1 shape) and an ensemble, each integrated twice
+    P = W.kuramoto_small()
+    g = P.graph
+    runs = []
+    for flags in (0, 0x8):
+        plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, flags=flags)
+        th = torch.as_tensor(P.theta0.astype(np.float32), device="cuda")
+        r1, r2 = np.zeros(21), np.zeros(31)
+        plan.integrate(th, 0.01, 20, r1)
+        plan.integrate(th, 0.01, 30, r2)
+        runs.append((th.cpu().numpy(), r1, r2))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+    ens = ensemble(6, 300, 2000)
+    outs = []
+    for flags in (0, 0x8):
+        plan = cia.Plan.batch(problems(ens), flags=flags)
+        th = torch.as_tensor(np.concatenate([Q.theta0 for Q in ens]).astype(np.float32), device="cuda")
+        r = np.zeros(6 * 26)
+        plan.integrate(th, 0.01, 25, r)
+        plan.integrate(th, 0.01, 25, r)
+        outs.append((th.cpu().numpy(), r.copy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_autotune_keeps_results(env):
+    cia, torch = env
+    ens = ensemble(16, 1000, 8000)
+    plan = cia.Plan.batch(problems(ens))
+    th = torch.as_tensor(np.concatenate([P.theta0 for P in ens]).astype(np.float32), device="cuda")
+    a = torch.empty_like(th)
+    plan.rhs(th, a)
+    rep = plan.autotune()
+    say("autotune: unit_work", rep.unit_work, "block", rep.block, "candidates", rep.candidates,
+        "best us", rep.best_us, "default us", rep.default_us)
+    assert rep.candidates == 12 and rep.best_us <= rep.default_us
+    b = torch.empty_like(th)
+    plan.rhs(th, b)
+    torch.cuda.synchronize()
+    assert np.abs(a.cpu().numpy() - b.cpu().numpy()).max() <= 1e-6 * max(1.0, np.abs(a.cpu().numpy()).max())
+    # build-time tuning flag
+    plan2 = cia.Plan.batch(problems(ens), flags=cia.CIA_FLAG_AUTOTUNE)
+    c = torch.empty_like(th)
+    plan2.rhs(th, c)
+    torch.cuda.synchronize()
+    assert np.abs(a.cpu().numpy() - c.cpu().numpy()).max() <= 1e-6 * max(1.0, np.abs(a.cpu().numpy()).max())
+
+
+def test_batch_rejects_mixed_couplings(env):
+    cia, torch = env
+    ens = ensemble(2, 300, 400)
+    g0, g1 = ens[0].graph, ens[1].graph
+    keep = []
+    graphs, coups = [], []
+    for g, ds in ((g0, [0.0, 1.0]), (g1, [0.0, 0.5])):
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(g.col, dtype=np.int32)
+        d_s = np.array(ds)
+        d_c = np.zeros(2)
+        keep += [rp, cl, d_s, d_c]
+        graphs.append(cia.cia_graph(n=g.n, kind=0, reserved=0, row_ptr=cia._np_ptr(rp), col=cia._np_ptr(cl)))
+        c = cia.cia_coupling_default()
+        c.p, c.d_sin, c.d_cos = 1, cia._np_ptr(d_s), cia._np_ptr(d_c)
+        coups.append(c)
+    with pytest.raises(cia.CIAError):
+        cia.cia_build_batch(graphs, None, coups, None, None)
+
+
+def test_ensemble_256_instances(env):
+    """All 256 instances of the ensemble recipe (N log-uniform, 4..500
+    communities, p_in in [0.7, 0.95], p_out log-uniform in [1e-4, 1e-2],
+    K_b = 6b/255) with N scaled to [1e3, 2e4]: one plan, sampled rows of
+    every instance against the oracle, and a short integration."""
+    cia, torch = env
+    ens = ensemble(256, 1e3, 2e4)
+    plan = cia.Plan.batch(problems(ens, with_omega=False), flags=0x8)
+    info = plan.info()
+    off = plan.offsets
+    say("ensemble: N", off[-1], "units", info.nunits, "nnz_neg", info.nnz_neg, "nnz_pos", info.nnz_pos)
+    th = torch.as_tensor(np.concatenate([P.theta0 for P in ens]).astype(np.float32), device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    th64 = th.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(9)
+    worst = 0.0
+    for b, P in enumerate(ens):
+        g = P.graph
+        rows = rng.choice(g.n, min(40, g.n), replace=False)
+        cw = oracle.phase_rhs(g.n, g.row_ptr, g.col, None, P.K, [0, 1], [0, 0], th64[off[b]:off[b + 1]],
+                              rows=rows)
+        cg = got[off[b] + rows]
+        if P.K == 0.0:
+            assert np.abs(cg).max() < 1e-6
+            continue
+        # scale: the largest coupling term of the instance's sampled rows
+        worst = max(worst, np.abs(cg - cw).max() / np.abs(cw).max())
+    say("   worst sampled coupling rel_inf", worst)
+    assert worst < 1e-5
+    r = np.zeros(256 * 11)
+    plan.integrate(th, 0.01, 10, r)
+    r = r.reshape(256, 11)
+    assert np.all(np.isfinite(r)) and np.all((r >= 0) & (r <= 1 + 1e-12))
