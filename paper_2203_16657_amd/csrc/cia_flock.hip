@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "fastmath.h"
 #include "plan.h"
 
 namespace cia {
@@ -163,7 +164,7 @@ __global__ void fourier_features_kernel(const float *__restrict__ X, int64_t n, 
         int4 a = alpha[h];
         float th = pi_over_L * ((float)a.x * x0 + (float)a.y * x1 + (float)a.z * x2);
         float sn, cs;
-        sincosf(th, &sn, &cs);
+        fast_sincosf(th, &sn, &cs);
         f[1 + 2 * h] = cs;
         f[2 + 2 * h] = sn;
     }

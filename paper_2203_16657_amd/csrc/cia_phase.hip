@@ -39,6 +39,7 @@
 #include <cstring>
 #include <numeric>
 
+#include "fastmath.h"
 #include "plan.h"
 
 namespace cia {
@@ -93,7 +94,7 @@ __host__ __device__ static inline uint64_t triple_key(uint32_t a, uint32_t b, ui
     return (uint64_t)a | ((uint64_t)b << 21) | ((uint64_t)c << 42);
 }
 
-__device__ __forceinline__ void dsincos(float t, float *s, float *c) { sincosf(t, s, c); }
+__device__ __forceinline__ void dsincos(float t, float *s, float *c) { fast_sincosf(t, s, c); }
 __device__ __forceinline__ void dsincos(double t, double *s, double *c) { sincos(t, s, c); }
 
 // compensated accumulation (Knuth TwoSum)
@@ -187,8 +188,22 @@ __device__ __forceinline__ void acc_z(cx<R> (&T)[P], cx<R> z, R sign) {
     }
 }
 
+// z of the staged community at a byte offset (local index * sizeof(z)):
+// staged local indices are stored pre-scaled, so the address needs no shift
+template <typename R>
+struct alignas(2 * sizeof(R)) cx_aligned {
+    R x, y;
+};
+template <typename R>
+__device__ __forceinline__ cx<R> zat(const cx<R> *zsh, uint32_t byte_off) {
+    // the aligned type keeps the access a single 8- (16-) byte LDS read
+    const cx_aligned<R> v =
+        *reinterpret_cast<const cx_aligned<R> *>(reinterpret_cast<const unsigned char *>(zsh) + byte_off);
+    return cx<R>{v.x, v.y};
+}
+
 // Stream `w` chunks of one lane's row (stride 64 chunks, U per batch).
-// STAGED: 8 uint16 LDS indices per chunk, one batch in flight (the LDS
+// STAGED: 8 uint16 LDS byte offsets per chunk, one batch in flight (the LDS
 // gathers of a batch give enough independent work).  Otherwise 4 int32
 // global positions per chunk, double-buffered: batch j+1's loads are in
 // flight while batch j's partners are gathered, as z (GATHER_Z) or as theta
@@ -209,8 +224,8 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
                 const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    z[u][2 * q] = zsh[q4[q] & 0xffffu];
-                    z[u][2 * q + 1] = zsh[q4[q] >> 16];
+                    z[u][2 * q] = zat(zsh, q4[q] & 0xffffu);
+                    z[u][2 * q + 1] = zat(zsh, q4[q] >> 16);
                 }
             }
 #pragma unroll
@@ -269,8 +284,8 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
 }
 
 // Stream a lane's list of partner pairs (j, k) and return sum z_j z_k.
-// STAGED: 4 pairs of uint16 local indices per chunk (LDS gathers, pad
-// lambda holds 0); otherwise 2 pairs of int32 positions per chunk, gathered
+// STAGED: 4 pairs of uint16 LDS byte offsets per chunk (LDS gathers, the
+// padding offset lambda * sizeof(z) holds 0); otherwise 2 pairs of int32 positions per chunk, gathered
 // as z (GATHER_Z) or as theta with z recomputed; pad position contributes 0.
 template <typename R, int U, bool STAGED, bool GATHER_Z>
 __device__ __forceinline__ cx<R> gather_pairs(const uint4 *__restrict__ col, int w, const cx<R> *zsh,
@@ -293,7 +308,7 @@ __device__ __forceinline__ cx<R> gather_pairs(const uint4 *__restrict__ col, int
                 const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const cx<R> p = cmul(zsh[q4[q] & 0xffffu], zsh[q4[q] >> 16]);
+                    const cx<R> p = cmul(zat(zsh, q4[q] & 0xffffu), zat(zsh, q4[q] >> 16));
                     M.x += p.x;
                     M.y += p.y;
                 }
@@ -382,7 +397,8 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     for (int k = 0; k < 2 * P; k++) ps[k] = pc[k] = 0.f, pd[k] = 0.0;
     double rx = 0.0, ry = 0.0;
 
-    const uint32_t pad16 = (uint32_t)lam | ((uint32_t)lam << 16);
+    const uint32_t padb = (uint32_t)lam * (uint32_t)sizeof(cx<R>);
+    const uint32_t pad16 = padb | (padb << 16);
     const uint4 padl = make_uint4(pad16, pad16, pad16, pad16);
     const uint4 padp = make_uint4(a.pad_pos, a.pad_pos, a.pad_pos, a.pad_pos);
 
@@ -928,15 +944,18 @@ struct Sell {
     std::vector<uint4> data[4];
 };
 
-// Order rows inside every segment by decreasing remainder work, cut the
+// Order rows inside every segment by decreasing remainder work (globally
+// gathered chunks first, then LDS-gathered chunks), cut the
 // segments into 64-row slices and pack the sliced blocks of every stream.
 // Segments are the communities [comm_off[c], comm_off[c+1]) and the tail of
 // rows outside every community.  In segments with seg_staged[c], local
 // entries are stored as uint16 indices (8 per chunk, pairs 4 per chunk, pad
-// lambda); everything else as int32 new positions (4 per chunk, pairs 2 per
+// lambda), pre-multiplied by zscale = sizeof(z) so they are LDS byte
+// offsets; everything else as int32 new positions (4 per chunk, pairs 2 per
 // chunk, pad n).
 static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, int32_t ncomm,
-                             const std::vector<char> &seg_staged, const StreamIn (&S)[4], Sell &out) {
+                             const std::vector<char> &seg_staged, const StreamIn (&S)[4], uint32_t zscale,
+                             Sell &out) {
     const int32_t nseg = ncomm + 1;
     std::vector<int64_t> sb(nseg + 1);
     for (int32_t c = 0; c <= ncomm; c++) sb[c] = c < ncomm ? comm_off[c] : (ncomm ? comm_off[ncomm] : 0);
@@ -955,10 +974,11 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
     for (int32_t c = 0; c < nseg; c++) {
         const int64_t b = sb[c], e = sb[c + 1];
         std::vector<int64_t> key(e - b);
-        for (int64_t k = 0; k < e - b; k++) {
-            key[k] = 0;
-            for (int q = 0; q < 4; q++) key[k] += chunks(q, c, b + k);
-        }
+        // globally gathered streams (1, 3: a partner phase and its sincos per
+        // slot) first, LDS-gathered streams (0, 2) second, so every slice is
+        // nearly uniform in both and few padded slots are evaluated
+        for (int64_t k = 0; k < e - b; k++)
+            key[k] = ((chunks(1, c, b + k) + chunks(3, c, b + k)) << 32) + chunks(0, c, b + k) + chunks(2, c, b + k);
         std::vector<int32_t> idx(e - b);
         for (int64_t k = 0; k < e - b; k++) idx[k] = (int32_t)k;
         std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return key[x] > key[y]; });
@@ -1019,8 +1039,8 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
                     for (int t = 0; t < ne; t++) {
                         const int64_t word = ((chunk * SLICE + l) * pc + slot) * ne + t;
                         if (st16) {
-                            uint16_t v = (uint16_t)lam;
-                            if (e < nn) v = (uint16_t)(out.newpos[off + src[e * ne + t]] - off);
+                            uint16_t v = (uint16_t)(lam * zscale);
+                            if (e < nn) v = (uint16_t)((out.newpos[off + src[e * ne + t]] - off) * zscale);
                             w16[word] = v;
                         } else {
                             uint32_t v = (uint32_t)n;
@@ -1333,7 +1353,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
                 S[3].val = xval.data();
                 S[3].pair = true;
             }
-            CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, S, sell));
+            CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, S, (uint32_t)zbytes, sell));
             if (s->d0 != 0.0) {
                 // |S+| - |S-| per row (all zero for a complete graph)
                 cnt_old.resize(n);
@@ -1364,7 +1384,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
                     S[3].pair = true;
                 }
                 std::vector<char> none(p1.ncomm, 0);
-                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, none, S, sell));
+                CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, none, S, (uint32_t)zbytes, sell));
                 if (s->d0 != 0.0) {
                     cnt_old.resize(n);
                     for (int64_t i = 0; i < n; i++) cnt_old[i] = (int32_t)(arp[i + 1] - arp[i]);
