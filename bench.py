@@ -34,7 +34,7 @@ def profiled_traffic():
     summary, valid only while the kernel sources are the ones profiled."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "phase_stage_kernel_kuramoto_n1e6.md")
-    srcs = [os.path.join(ROOT, "paper_2203_16657_amd", "csrc", f) for f in ("cia_phase.hip", "plan.h")]
+    srcs = [os.path.join(ROOT, "paper_2203_16657_amd", "csrc", f) for f in ("cia_phase.hip", "plan.h", "fastmath.h")]
     try:
         text = open(prof).read()
         h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
@@ -46,7 +46,7 @@ def profiled_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True):
+def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True, timing_every=0):
     import numpy as np
     th = torch.as_tensor(theta0, dtype=torch.float32, device="cuda")
     if warmup:
@@ -55,6 +55,9 @@ def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True):
     th = torch.as_tensor(theta0, dtype=torch.float32, device="cuda")
     r = np.zeros(steps + 1) if with_r else None
     stream = torch.cuda.current_stream()
+    # kernel durations: HIP events around one stage launch in `timing_every`,
+    # on the launch stream, inside the timed region
+    plan.set_timing(timing_every)
     plan.timing(reset=True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -78,6 +81,10 @@ def main():
                     help="RK4 steps timed for the direct method")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
+    ap.add_argument("--timing-every", type=int, default=16,
+                    help="HIP events around one stage launch in this many (1 = every launch)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner pick the unit and block size before timing")
     ap.add_argument("--unit-work", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -118,15 +125,22 @@ def main():
     g = P.graph
     log("workload %s: n=%d nnz=%d communities=%d (%.1fs)" % (P.name, g.n, g.nnz, g.ncomm, time.time() - t0))
 
-    flags = 0 if args.no_timing else cia.CIA_FLAG_TIMING
+    every = 0 if args.no_timing else max(1, args.timing_every)
     t0 = time.time()
-    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, flags=flags,
+    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K,
                           unit_work=args.unit_work, block=args.block)
+    tune = None
+    if args.autotune and not args.unit_work and not args.block:
+        rep = plan.autotune()
+        tune = {"unit_work": rep.unit_work, "block": rep.block, "candidates": rep.candidates,
+                "best_us": round(rep.best_us, 2), "default_us": round(rep.default_us, 2)}
+        log("autotune: unit_work %d block %d (%.2f us vs %.2f us default, %d candidates)" % (
+            rep.unit_work, rep.block, rep.best_us, rep.default_us, rep.candidates))
     info = plan.info()
     log("cia plan: units=%d ncomm=%d nnz_neg=%d nnz_pos=%d unassigned=%d bytes/stage=%.3e (%.1fs)" % (
         info.nunits, info.ncomm, info.nnz_neg, info.nnz_pos, info.n_unassigned, info.bytes_per_stage,
         time.time() - t0))
-    ms, tim, r = time_integrate(plan, torch, P.theta0, P.dt, args.steps, args.warmup)
+    ms, tim, r = time_integrate(plan, torch, P.theta0, P.dt, args.steps, args.warmup, timing_every=every)
     n = g.n
     rhs_per_step = 4
     value = n * rhs_per_step * args.steps / (ms / 1e3)
@@ -138,19 +152,19 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(),
                 "kernel": "phase_stage_kernel", "avg_launch_us": round(stage_avg_ms * 1e3, 2),
-                "algorithmic_bytes_per_launch": info.bytes_per_stage}
+                "algorithmic_bytes_per_launch": info.bytes_per_stage, "timed_launches": tim.stage_launches}
         log("stage kernel avg %.2f us, %.1f GB/s algorithmic (%.1f%% of 8 TB/s)" % (
             stage_avg_ms * 1e3, achieved, 100 * achieved / HBM_PEAK_GBS))
     plan.close()
 
     # direct method, same data layout and stepper
     t0 = time.time()
-    dplan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, flags=flags,
-                           method=cia.CIA_METHOD_DIRECT)
+    dplan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, method=cia.CIA_METHOD_DIRECT)
     dinfo = dplan.info()
     log("direct plan: units=%d nnz=%d (%.1fs)" % (dinfo.nunits, dinfo.nnz_pos, time.time() - t0))
     dsteps = min(args.direct_steps, args.steps)
-    dms, dtim, _ = time_integrate(dplan, torch, P.theta0, P.dt, dsteps, min(args.warmup, 5))
+    dms, dtim, _ = time_integrate(dplan, torch, P.theta0, P.dt, dsteps, min(args.warmup, 5),
+                                  timing_every=0 if args.no_timing else 1)
     dvalue = n * rhs_per_step * dsteps / (dms / 1e3)
     d_stage_ms = dtim.stage_ms / max(dtim.stage_launches, 1) if dtim.stage_launches else None
     log("direct: %.3f ms/step, %.3e RHS node-updates/s" % (dms / dsteps, dvalue))
@@ -191,7 +205,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": P.name, "n": n, "communities": info.ncomm, "nnz_graph": info.nnz_graph,
                    "nnz_neg": info.nnz_neg, "nnz_pos": info.nnz_pos, "stepper": "rk4", "dt": P.dt,
-                   "rhs_per_step": rhs_per_step, "parallelism": "single-gpu"},
+                   "rhs_per_step": rhs_per_step, "parallelism": "single-gpu", "units": info.nunits,
+                   "autotune": tune},
         "direct": direct,
         "speedup_vs_direct": value / dvalue,
         "roofline": roof,

@@ -87,7 +87,8 @@ typedef enum cia_status {
 #define CIA_FLAG_KEEP_LABELS 0x1u  /* skip the P1 cost rule (App. A.1): every labelled
                                       community is treated as a dense block */
 #define CIA_FLAG_TIMING 0x2u       /* record HIP events around every kernel launch;
-                                      read them with cia_plan_get_timing */
+                                      read them with cia_plan_get_timing (see also
+                                      cia_plan_set_timing) */
 #define CIA_FLAG_NO_VALIDATE 0x4u  /* skip the symmetry / sortedness checks of cia_build */
 #define CIA_FLAG_HIPGRAPH 0x8u     /* phase models, RK4: capture one step (its four stage
                                       launches and the order parameter) as a HIP graph once
@@ -346,6 +347,12 @@ typedef struct cia_timing {
 } cia_timing;
 
 cia_status cia_plan_get_timing(cia_plan *p, cia_timing *t, int reset);
+
+/* Sample the kernel timing: HIP events around one launch in `every` of each
+   kind (stage / prep / aux), so long runs are timed with little disturbance.
+   0 = off, 1 = every launch (what CIA_FLAG_TIMING sets at build).  Collects
+   and keeps what was recorded so far; restarts the launch counters. */
+cia_status cia_plan_set_timing(cia_plan *p, int32_t every);
 
 /* --------------------------------------------------------------------- */
 /* Host-only helpers (no device needed)                                   */

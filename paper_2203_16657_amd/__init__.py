@@ -82,7 +82,7 @@ EXPORTS = ["cia_build", "cia_rhs", "cia_integrate", "cia_destroy", "cia_last_err
            "cia_fourier_coeffs", "cia_p1_build", "cia_p1_sizes", "cia_p1_export", "cia_p1_free",
            "cia_abi_sizeof", "cia_basis_param_count", "cia_basis_set_params", "cia_basis_get_params",
            "cia_basis_train", "cia_basis_loss_grad", "cia_basis_features", "cia_build_batch",
-           "cia_batch_offsets", "cia_autotune"]
+           "cia_batch_offsets", "cia_autotune", "cia_plan_set_timing"]
 
 _lib = None
 
@@ -148,6 +148,8 @@ def load():
     lib.cia_build_batch.argtypes = [_c.c_int32, _vp, _vp, _vp, _vp, P(cia_options), P(_vp)]
     lib.cia_batch_offsets.restype = _c.c_int
     lib.cia_batch_offsets.argtypes = [_vp, _vp, _vp]
+    lib.cia_plan_set_timing.restype = _c.c_int
+    lib.cia_plan_set_timing.argtypes = [_vp, _c.c_int32]
     lib.cia_autotune.restype = _c.c_int
     lib.cia_autotune.argtypes = [_vp, _vp, P(cia_tune_report)]
     _lib = lib
@@ -327,6 +329,10 @@ def cia_batch_offsets(plan):
     return off
 
 
+def cia_plan_set_timing(plan, every: int) -> None:
+    _check(load().cia_plan_set_timing(plan, int(every)))
+
+
 def cia_autotune(plan, stream=None) -> cia_tune_report:
     rep = cia_tune_report()
     _check(load().cia_autotune(plan, _stream_ptr(stream), _c.byref(rep)))
@@ -456,6 +462,9 @@ class Plan:
         plan = cls(h, int(sum(q[0] for q in problems)), precision, CIA_MODEL_PHASE)
         plan.offsets = cia_batch_offsets(h)
         return plan
+
+    def set_timing(self, every: int):
+        cia_plan_set_timing(self.handle, every)
 
     def autotune(self, stream=None) -> cia_tune_report:
         return cia_autotune(self.handle, stream)

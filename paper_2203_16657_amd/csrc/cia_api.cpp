@@ -9,12 +9,15 @@
 namespace cia {
 
 cia_status timing_begin(cia_plan *p, hipStream_t s, int kind, int weight) {
-    if (!(p->flags & CIA_FLAG_TIMING)) return CIA_OK;
+    p->ev_open = false;
+    if (p->timing_every <= 0) return CIA_OK;
+    if (p->tick[kind]++ % p->timing_every != 0) return CIA_OK;
     if (p->ev_used == p->events.size()) {
         cia_plan::EvPair e;
         CIA_HIP(hipEventCreate(&e.a));
         CIA_HIP(hipEventCreate(&e.b));
         e.kind = kind;
+        e.weight = weight;
         p->events.push_back(e);
     }
     auto &e = p->events[p->ev_used];
@@ -22,11 +25,13 @@ cia_status timing_begin(cia_plan *p, hipStream_t s, int kind, int weight) {
     e.weight = weight;
     CIA_HIP(hipEventRecord(e.a, s));
     p->last_stream = s;
+    p->ev_open = true;
     return CIA_OK;
 }
 
 cia_status timing_end(cia_plan *p, hipStream_t s) {
-    if (!(p->flags & CIA_FLAG_TIMING)) return CIA_OK;
+    if (!p->ev_open) return CIA_OK;
+    p->ev_open = false;
     CIA_HIP(hipEventRecord(p->events[p->ev_used].b, s));
     p->ev_used++;
     // bound the number of events in flight
@@ -93,6 +98,7 @@ static cia_status make_plan(const cia_options *o, int64_t n, int32_t model, cia_
     p->precision = o->precision;
     p->stepper = o->stepper;
     p->flags = o->flags;
+    p->timing_every = (o->flags & CIA_FLAG_TIMING) ? 1 : 0;
     p->n = n;
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess) cur = 0;
@@ -205,7 +211,7 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream) {
         case CIA_MODEL_FLOCK: st = flock_rhs(p, state, dstate, s); break;
         default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
     }
-    if (st == CIA_OK && (p->flags & CIA_FLAG_TIMING)) st = timing_collect(p);
+    if (st == CIA_OK && p->timing_every > 0) st = timing_collect(p);
     return st;
 }
 
@@ -228,7 +234,7 @@ cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, dou
             break;
         default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
     }
-    if (st == CIA_OK && (p->flags & CIA_FLAG_TIMING)) st = timing_collect(p);
+    if (st == CIA_OK && p->timing_every > 0) st = timing_collect(p);
     return st;
 }
 
@@ -247,6 +253,17 @@ cia_status cia_plan_get_info(const cia_plan *p, cia_plan_info *info) {
         CIA_TRY(select_device(q));
         CIA_TRY(flock_judge_count(q, &info->judge_fallbacks));
     }
+    return CIA_OK;
+}
+
+cia_status cia_plan_set_timing(cia_plan *p, int32_t every) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    if (every < 0) return set_error(CIA_EINVAL, "every = %d", every);
+    CIA_TRY(select_device(p));
+    CIA_TRY(timing_collect(p));
+    p->timing_every = every;
+    for (auto &k : p->tick) k = 0;
     return CIA_OK;
 }
 

@@ -32,6 +32,9 @@ struct cia_plan {
     };
     std::vector<EvPair> events;
     size_t ev_used = 0;
+    int32_t timing_every = 0;      // events around one launch in this many per kind (0 = off)
+    int64_t tick[3] = {0, 0, 0};   // launches seen per kind
+    bool ev_open = false;          // the last timing_begin recorded an event
     double t_ms[3] = {0, 0, 0};
     int64_t t_count[3] = {0, 0, 0};
     hipStream_t last_stream = nullptr;
