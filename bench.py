@@ -55,8 +55,9 @@ def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True, timing_e
     th = torch.as_tensor(theta0, dtype=torch.float32, device="cuda")
     r = np.zeros(steps + 1) if with_r else None
     stream = torch.cuda.current_stream()
-    # kernel durations: HIP events around one stage launch in `timing_every`,
-    # on the launch stream, inside the timed region
+    # kernel durations: HIP events around one stage launch in `timing_every`
+    # (17: coprime with the 4 stages, so every stage is sampled), on the
+    # launch stream, inside the timed region
     plan.set_timing(timing_every)
     plan.timing(reset=True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -81,7 +82,7 @@ def main():
                     help="RK4 steps timed for the direct method")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events")
-    ap.add_argument("--timing-every", type=int, default=16,
+    ap.add_argument("--timing-every", type=int, default=17,
                     help="HIP events around one stage launch in this many (1 = every launch)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library's autotuner pick the unit and block size before timing")

@@ -159,6 +159,13 @@ struct PhaseArgs {
     const double2 *q_in;      // [slots][P] partial observables of the current stage
     double2 *q_out;
     double2 *r_part;          // [nunits] partial sum of z for the order parameter
+    // the previous launch's order-parameter partials, summed at kernel start by
+    // one wavefront of the last block into r_prev_out (+ *r_prev_slot)
+    const double2 *r_prev_part;
+    double *r_prev_out;
+    const int64_t *r_prev_slot;
+    int32_t r_prev_n;
+    double invN;
     const R *state_in;        // user order (M_PREP)
     R *state_out;             // user order (M_RHS)
     const R *kn;              // batched ensembles: K_b / N_b per node (community order), else NULL
@@ -190,6 +197,25 @@ __device__ __forceinline__ void acc_z(cx<R> (&T)[P], cx<R> z, R sign) {
 
 // z of the staged community at a byte offset (local index * sizeof(z)):
 // staged local indices are stored pre-scaled, so the address needs no shift
+// r(t) = |(1/N) sum z| from the unit partials: one wavefront, lane-strided
+// FP64 sums then an xor-butterfly, so the order is fixed.  Used by the
+// stage kernel (folded into the next launch) and by order_reduce_kernel.
+__device__ __forceinline__ void reduce_r_wave(const double2 *part, int n, double invN, double *out) {
+    const int lane = threadIdx.x & 63;
+    double x = 0.0, y = 0.0;
+#pragma unroll 8
+    for (int j = lane; j < n; j += 64) {
+        const double2 v = part[j];
+        x += v.x;
+        y += v.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o);
+        y += __shfl_xor(y, o);
+    }
+    if (lane == 0) *out = sqrt(x * x + y * y) * invN;
+}
+
 template <typename R>
 struct alignas(2 * sizeof(R)) cx_aligned {
     R x, y;
@@ -218,20 +244,18 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
             uint4 v[U];
 #pragma unroll
             for (int u = 0; u < U; u++) v[u] = k + u < w ? ld_stream(col + (size_t)(k + u) * SLICE) : padv;
-            cx<R> z[U][8];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                cx<R> z[8];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    z[u][2 * q] = zat(zsh, q4[q] & 0xffffu);
-                    z[u][2 * q + 1] = zat(zsh, q4[q] >> 16);
+                    z[2 * q] = zat(zsh, q4[q] & 0xffffu);
+                    z[2 * q + 1] = zat(zsh, q4[q] >> 16);
                 }
+#pragma unroll
+                for (int q = 0; q < 8; q++) acc_z<R, P>(T, z[q], sign);
             }
-#pragma unroll
-            for (int u = 0; u < U; u++)
-#pragma unroll
-                for (int q = 0; q < 8; q++) acc_z<R, P>(T, z[u][q], sign);
         }
         return;
     }
@@ -331,7 +355,7 @@ __device__ __forceinline__ cx<R> gather_pairs(const uint4 *__restrict__ col, int
 template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE, bool TRI>
 __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     constexpr int NW = BLOCK / 64;
-    constexpr int UL = P >= 4 ? 1 : 4 / P;  // chunks per batch, LDS-gathered rows
+    constexpr int UL = P >= 4 ? 2 : 8 / P;  // chunks per batch, LDS-gathered rows
     constexpr int UG = P >= 2 ? 1 : 2;      // chunks per batch, global-gathered rows (two in flight)
     extern __shared__ __align__(16) unsigned char smem[];
     cx<R> *zsh = reinterpret_cast<cx<R> *>(smem);   // [lds_cap + 1]
@@ -343,6 +367,10 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     const Unit Un = a.units[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
+    // r(t) of the previous step from its partials (the kernel boundary makes
+    // them visible), by the first block, which starts before all others
+    if (a.r_prev_out && blockIdx.x == 0 && wid == 0)
+        reduce_r_wave(a.r_prev_part, a.r_prev_n, a.invN, a.r_prev_out + (a.r_prev_slot ? *a.r_prev_slot : 0));
     const bool assigned = !DIRECT && (Un.flags & UF_ASSIGNED) != 0;
     const bool staged = !DIRECT && (Un.flags & UF_STAGED) != 0;
     const bool wide = WIDE && (Un.flags & UF_WIDE) != 0;
@@ -471,7 +499,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                         if (k + 1 < P) zk = cmul(zk, z);
                     }
                     H = om + knv * s;
-                    if (TRI) {
+                    if constexpr (TRI && P >= 2) {
                         // sum over ordered distinct partner pairs of z_j z_k, then
                         // Im(conj(z_m)^2 * .) (App. A.7 with lambda = (1,1,-2))
                         const cx<R> z2 = cmul(z, z);
@@ -690,27 +718,11 @@ __global__ __launch_bounds__(256) void triadic_present_kernel(const TriBlock *bl
     out[i] = E;
 }
 
-// r(t) = |(1/N) sum z| from the unit partials, fixed order, one block.
-// With slot_ctr (replayed graphs) the output slot is r_out + *slot_ctr.
-__global__ __launch_bounds__(256) void order_reduce_kernel(const double2 *r_part, int nunits,
-                                                           double invN, double *r_out, const int64_t *slot_ctr) {
-    __shared__ double sx[256], sy[256];
-    double x = 0.0, y = 0.0;
-    for (int j = threadIdx.x; j < nunits; j += 256) {
-        x += r_part[j].x;
-        y += r_part[j].y;
-    }
-    sx[threadIdx.x] = x;
-    sy[threadIdx.x] = y;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            sx[threadIdx.x] += sx[threadIdx.x + s];
-            sy[threadIdx.x] += sy[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) r_out[slot_ctr ? *slot_ctr : 0] = sqrt(sx[0] * sx[0] + sy[0] * sy[0]) * invN;
+// standalone reduction (one wavefront); with slot_ctr (replayed graphs) the
+// output slot is r_out + *slot_ctr
+__global__ __launch_bounds__(64) void order_reduce_kernel(const double2 *r_part, int nunits, double invN,
+                                                          double *r_out, const int64_t *slot_ctr) {
+    reduce_r_wave(r_part, nunits, invN, r_out + (slot_ctr ? *slot_ctr : 0));
 }
 
 // Batched ensembles: r_b(t) = |(1/N_b) sum over the nodes of instance b of z|,
@@ -1629,6 +1641,7 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
     a.perm = s->perm;
     a.omega = static_cast<const R *>(s->omega);
     a.kn = static_cast<const R *>(s->kn);
+    a.invN = 1.0 / (double)p->n;
     a.theta_n = static_cast<R *>(s->theta_n);
     a.acc = static_cast<R *>(s->acc);
     a.Kn = (R)s->Kn;
@@ -1736,7 +1749,7 @@ static cia_status launch_all2all(cia_plan *p, PhaseState *s, hipStream_t st, con
 
 static cia_status launch_order_reduce(cia_plan *p, PhaseState *s, hipStream_t st, int nparts, double *slot) {
     CIA_TRY(timing_begin(p, st, KK_AUX));
-    hipLaunchKernelGGL(order_reduce_kernel, dim3(1), dim3(256), 0, st, s->r_part, nparts,
+    hipLaunchKernelGGL(order_reduce_kernel, dim3(1), dim3(64), 0, st, s->r_part, nparts,
                        1.0 / (double)p->n, slot, (const int64_t *)nullptr);
     CIA_HIP(hipGetLastError());
     return timing_end(p, st);
@@ -1802,7 +1815,7 @@ static cia_status launch_order(cia_plan *p, PhaseState *s, hipStream_t st, const
         hipLaunchKernelGGL((order_grouped_kernel<R>), dim3(s->batch), dim3(256), 0, st,
                            static_cast<const cx<R> *>(cs), s->grp_idx, s->grp_off, s->r_dev, stride, slot, ctr);
     } else {
-        hipLaunchKernelGGL(order_reduce_kernel, dim3(1), dim3(256), 0, st, s->r_part, s->nunits,
+        hipLaunchKernelGGL(order_reduce_kernel, dim3(1), dim3(64), 0, st, s->r_part, s->nunits,
                            1.0 / (double)p->n, s->r_dev + slot, ctr);
     }
     CIA_HIP(hipGetLastError());
@@ -1824,6 +1837,17 @@ static PhaseArgs<R> stage_args(cia_plan *p, PhaseState *s, bool rk4, int q, doub
     a.r_part = s->r_part;
     a.want_r = want_r;
     return a;
+}
+
+// single networks, RK4: the first stage of a step sums the order-parameter
+// partials that the previous launch (prep pass or last stage) left, into
+// `slot` (+ *ctr)
+template <typename R>
+static void fold_order(PhaseState *s, PhaseArgs<R> &a, double *slot, const int64_t *ctr) {
+    a.r_prev_part = s->r_part;
+    a.r_prev_out = slot;
+    a.r_prev_slot = ctr;
+    a.r_prev_n = s->nunits;
 }
 
 template <typename R>
@@ -1903,7 +1927,10 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         a.r_part = s->r_part;
         a.want_r = part_r;
         CIA_TRY(launch_stage<R>(p, s, a, ws, KK_PREP));
-        if (want_r) CIA_TRY(launch_order<R>(p, s, ws, s->cs[0], 0, stride, nullptr, true));
+        // r(t_0): with RK4 on single networks it is folded into the first
+        // stage of the first step (or reduced below when steps == 0)
+        const bool fold = part_r && rk4;
+        if (want_r && !fold) CIA_TRY(launch_order<R>(p, s, ws, s->cs[0], 0, stride, nullptr, true));
         if (replay) {
             // one RK4 step (four stage launches, r(t) and its slot counter) as a
             // graph, instantiated once per (dt, trace) and replayed every step
@@ -1916,11 +1943,12 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
                 CIA_HIP(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
                 for (int q = 0; q < 4; q++) {
                     PhaseArgs<R> b = stage_args<R>(p, s, true, q, dt, q & 1, part_r && q == 3);
+                    if (fold && q == 0) fold_order<R>(s, b, s->r_dev, s->r_ctr);
                     if (s->block == 512) launch_stage_v_any<R, 512>(s, b, ws);
                     else launch_stage_v_any<R, 256>(s, b, ws);
                 }
                 if (want_r) {
-                    CIA_TRY(launch_order<R>(p, s, ws, s->cs[0], 1, stride, s->r_ctr, false));
+                    if (!fold) CIA_TRY(launch_order<R>(p, s, ws, s->cs[0], 1, stride, s->r_ctr, false));
                     hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, ws, s->r_ctr, (int64_t)1, 1);
                 }
                 hipGraph_t gr = nullptr;
@@ -1945,12 +1973,15 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
                 const int nst = rk4 ? 4 : 1;
                 for (int q = 0; q < nst; q++) {
                     a = stage_args<R>(p, s, rk4, q, dt, cur, part_r && q == nst - 1);
+                    if (fold && q == 0) fold_order<R>(s, a, s->r_dev + k, nullptr);
                     CIA_TRY(launch_stage<R>(p, s, a, ws, KK_STAGE));
                     cur ^= 1;
                 }
-                if (want_r) CIA_TRY(launch_order<R>(p, s, ws, s->cs[cur], k + 1, stride, nullptr, true));
+                if (want_r && !fold) CIA_TRY(launch_order<R>(p, s, ws, s->cs[cur], k + 1, stride, nullptr, true));
             }
         }
+        // the last step's r(t) (its partials were left by the final stage)
+        if (fold) CIA_TRY(launch_order<R>(p, s, ws, nullptr, steps, stride, nullptr, true));
         CIA_TRY(timing_begin(p, ws, KK_AUX));
         hipLaunchKernelGGL((permute_out_kernel<R>), dim3(grid), dim3(256), 0, ws, n, s->perm,
                            static_cast<const R *>(s->theta_n), static_cast<R *>(state));
