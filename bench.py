@@ -77,7 +77,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="large", choices=["large", "small"])
+    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble"],
+                    help="large: the N = 1e6 Kuramoto bench line; flock and ensemble: the Cucker-Smale "
+                         "and batched-ensemble workloads (measurement modes, not the bench line)")
+    ap.add_argument("--train-iters", type=int, default=3000, help="flock: optimiser steps of the basis")
+    ap.add_argument("--ensemble-nmax", type=float, default=2e4, help="ensemble: largest instance size")
     ap.add_argument("--direct-steps", type=int, default=100,
                     help="RK4 steps timed for the direct method")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -120,6 +124,11 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 5 x %d bytes" % (src.numel() * 4))
         del src, dst
+
+    if args.workload == "flock":
+        return bench_flock(args, cia, W, torch, np)
+    if args.workload == "ensemble":
+        return bench_ensemble(args, cia, W, torch, np)
 
     t0 = time.time()
     P = W.kuramoto_large() if args.workload == "large" else W.kuramoto_small()
@@ -215,6 +224,134 @@ def main():
         "r_final": float(r[-1]) if r is not None else None,
     }
     print(json.dumps(res), flush=True)
+
+
+def timed(torch, fn):
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    fn(s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def bench_flock(args, cia, W, torch, np):
+    """Cucker-Smale on 400 communities of 500 (N = 2e5): the learned rank-32
+    basis (trained on the GPU, judged per community), the exact community
+    path, the Fourier basis and the direct method; single-RHS errors against
+    the FP64 oracle on sampled rows and RK4 throughput."""
+    import oracle
+    F = W.flock()
+    g = F.graph
+    n = g.n
+    log("flock workload: n=%d nnz=%d communities=%d" % (n, g.nnz, g.ncomm))
+    st = torch.as_tensor(np.concatenate([F.x0, F.v0]).astype(np.float32), device="cuda").contiguous()
+    s64 = st.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(1).choice(n, 2000, replace=False)
+    _, vref = oracle.cs_rhs(n, g.row_ptr, g.col, F.K, F.sigma, F.beta, s64[:3], s64[3:], rows=rows)
+
+    def rhs_err(plan):
+        out = torch.empty_like(st)
+        plan.rhs(st, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64)[3:, rows]
+        return float(np.abs(got - vref).max() / np.abs(vref).max())
+
+    def make(basis, **kw):
+        return cia.Plan.flock(n, g.row_ptr, g.col, g.labels, K=F.K, sigma=F.sigma, beta=F.beta, basis=basis, **kw)
+
+    steps = min(args.steps, 50)
+    res = {}
+    # learned basis: train, then time steps with the judge
+    learned = make(cia.CIA_BASIS_LEARNED, rank=32)
+    lt = np.zeros(args.train_iters)
+    train_ms = timed(torch, lambda s: learned.basis_train(st, args.train_iters, seed=11, loss_trace=lt, stream=s))
+    params, lo, hi = learned.basis_get_params(cia.cia_basis_param_count(32))
+    free = make(cia.CIA_BASIS_LEARNED, rank=32, flags=cia.CIA_FLAG_NO_JUDGE)
+    free.basis_set_params(params, lo, hi)
+    fourier = make(cia.CIA_BASIS_FOURIER, p=1, flags=cia.CIA_FLAG_NO_JUDGE)
+    exact = make(cia.CIA_BASIS_EXACT)
+    direct = make(cia.CIA_BASIS_EXACT, method=cia.CIA_METHOD_DIRECT)
+    errs = {"learned_no_judge": rhs_err(free), "learned_judged": rhs_err(learned), "fourier_p1": rhs_err(fourier),
+            "exact": rhs_err(exact), "direct": rhs_err(direct)}
+    fallbacks = learned.info().judge_fallbacks
+    for name, plan in (("learned_judged", learned), ("learned_no_judge", free), ("exact", exact),
+                       ("direct", direct)):
+        y = st.clone()
+        plan.integrate(y, F.dt, 2)
+        y = st.clone()
+        plan.set_timing(17)
+        plan.timing(reset=True)
+        ms = timed(torch, lambda s: plan.integrate(y, F.dt, steps, stream=s))
+        t = plan.timing(reset=True)
+        res[name] = {"value": n * 4 * steps / (ms / 1e3), "ms_per_step": ms / steps,
+                     "stage_us": round(1e3 * t.stage_ms / max(t.stage_launches, 1), 2),
+                     "prep_us": round(1e3 * t.prep_ms / max(t.prep_launches, 1), 2)}
+        log("%-17s %.3f ms/step, %.3e node-updates/s" % (name, ms / steps, res[name]["value"]))
+    out = {
+        "metric": "flock RHS node-updates/s (learned rank-32 basis, judged), 1 MI355X, N=2e5",
+        "value": res["learned_judged"]["value"], "unit": "RHS node-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": 2, "ms_per_step": res["learned_judged"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": "flock_n200000", "n": n, "communities": g.ncomm, "rank": 32, "judge_tol": 1e-3,
+                   "stepper": "rk4", "dt": F.dt},
+        "methods": res, "rhs_rel_err": errs, "judge_fallbacks": fallbacks,
+        "train": {"iters": args.train_iters, "ms": train_ms, "loss_first": float(lt[:10].mean()),
+                  "loss_last": float(lt[-100:].mean())},
+        "gain_vs_fourier": errs["fourier_p1"] / errs["learned_no_judge"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args, cia, W, torch, np):
+    """The 256-instance ensemble (N log-uniform up to --ensemble-nmax, 4..500
+    communities, K swept over [0, 6]): one batched plan (plain and with the
+    replayed step graph) against 256 sequential single-network integrations."""
+    count = 256
+    ens = [W.ensemble_member(b, n_hi=args.ensemble_nmax, count=count) for b in range(count)]
+    probs = [(P.graph.n, P.graph.row_ptr, P.graph.col, P.graph.labels, P.omega, P.K) for P in ens]
+    ntot = sum(P.graph.n for P in ens)
+    th0 = np.concatenate([P.theta0 for P in ens]).astype(np.float32)
+    steps = min(args.steps, 100)
+    log("ensemble: %d instances, N total %d" % (count, ntot))
+    res = {}
+    for name, flags in (("batched", cia.CIA_FLAG_AUTOTUNE), ("batched_graph", cia.CIA_FLAG_AUTOTUNE | cia.CIA_FLAG_HIPGRAPH)):
+        plan = cia.Plan.batch(probs, flags=flags)
+        th = torch.as_tensor(th0, device="cuda")
+        plan.integrate(th, 0.01, 2, np.zeros(count * 3))
+        th = torch.as_tensor(th0, device="cuda")
+        r = np.zeros(count * (steps + 1))
+        ms = timed(torch, lambda s: plan.integrate(th, 0.01, steps, r, stream=s))
+        res[name] = {"value": ntot * 4 * steps / (ms / 1e3), "ms_per_step": ms / steps, "units": plan.info().nunits}
+        log("%-14s %.3f ms/step" % (name, ms / steps))
+        plan.close()
+    plans = [cia.Plan.phase(*q[:5], K=q[5]) for q in probs]
+    ths = [torch.as_tensor(P.theta0.astype(np.float32), device="cuda") for P in ens]
+    rs = [np.zeros(steps + 1) for _ in ens]
+    for pl, t in zip(plans, ths):
+        pl.integrate(t, 0.01, 2, np.zeros(3))
+    ths = [torch.as_tensor(P.theta0.astype(np.float32), device="cuda") for P in ens]
+
+    def seq(s):
+        for pl, t, r in zip(plans, ths, rs):
+            pl.integrate(t, 0.01, steps, r, stream=s)
+
+    ms = timed(torch, seq)
+    res["sequential"] = {"value": ntot * 4 * steps / (ms / 1e3), "ms_per_step": ms / steps}
+    log("%-14s %.3f ms/step" % ("sequential", ms / steps))
+    out = {
+        "metric": "ensemble RHS node-updates/s (256 instances, one batched plan), 1 MI355X",
+        "value": res["batched"]["value"], "unit": "RHS node-updates/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+        "ms_per_step": res["batched"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ensemble_256", "n_total": ntot, "n_max": args.ensemble_nmax, "stepper": "rk4",
+                   "dt": 0.01},
+        "methods": res, "speedup_vs_sequential": res["batched"]["value"] / res["sequential"]["value"],
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

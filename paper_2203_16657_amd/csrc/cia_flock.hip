@@ -37,8 +37,9 @@ namespace cia {
 namespace {
 
 constexpr int HID = 64;            // hidden width of the learned basis
-constexpr int FBLOCK = 256;        // threads of the row kernels (one row per thread)
+constexpr int TPR = 4;             // threads per row in the stage kernel
 constexpr int CHUNK_ROWS = 256;    // rows per chunk of the stage kernel
+constexpr int FBLOCK = CHUNK_ROWS * TPR;
 constexpr int JUDGE_SAMPLES = 16;  // sampled members per community and step
 constexpr int TRAIN_PAIRS = 4096;  // pairs per optimiser step
 constexpr int TILE_PTS = 64;       // points per MFMA tile (32 pairs in training)
@@ -244,19 +245,48 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const float *__restri
 // E1: per-community sums P_cr = sum f_r, V_cr = sum f_r v (FP64 accumulation)
 // --------------------------------------------------------------------------
 
-__global__ void flock_e1_kernel(const float *__restrict__ F, const float *__restrict__ Y, int64_t n,
-                                const int32_t *__restrict__ comm_off, int Rp, float *__restrict__ Q) {
-    const int c = blockIdx.x;
+__global__ __launch_bounds__(256) void flock_e1_kernel(const float *__restrict__ F, const float *__restrict__ Y,
+                                                       int64_t n, const int32_t *__restrict__ comm_off, int Rp,
+                                                       float *__restrict__ Q) {
+    __shared__ double part[256];
+    const int c = blockIdx.x, t = threadIdx.x;
     const int c0 = comm_off[c], c1 = comm_off[c + 1];
-    for (int item = threadIdx.x; item < Rp * 4; item += blockDim.x) {
-        const int r = item >> 2, q = item & 3;
-        const float *vq = Y + (int64_t)(2 + q) * n;  // q = 1..3 -> v planes 3..5
-        double s = 0.0;
-        for (int j = c0; j < c1; j++) {
-            float f = F[(int64_t)j * Rp + r];
-            s += q == 0 ? (double)f : (double)f * (double)vq[j];
+    const int items = Rp * 4;
+    // G threads share an item and take every G-th row; four independent
+    // accumulators keep several loads in flight
+    const int G = items >= 256 ? 1 : 256 / items;
+    for (int base = 0; base < items; base += 256 / G) {
+        const int item = base + t % (256 / G), ph = t / (256 / G);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (item < items && ph < G) {
+            const int r = item >> 2, q = item & 3;
+            const float *vq = Y + (int64_t)(2 + q) * n;  // q = 1..3 -> v planes 3..5
+            int j = c0 + ph;
+            for (; j + 3 * G < c1; j += 4 * G) {
+                const float f0 = F[(int64_t)j * Rp + r], f1 = F[(int64_t)(j + G) * Rp + r];
+                const float f2 = F[(int64_t)(j + 2 * G) * Rp + r], f3 = F[(int64_t)(j + 3 * G) * Rp + r];
+                if (q == 0) {
+                    s0 += f0; s1 += f1; s2 += f2; s3 += f3;
+                } else {
+                    s0 += (double)f0 * vq[j];
+                    s1 += (double)f1 * vq[j + G];
+                    s2 += (double)f2 * vq[j + 2 * G];
+                    s3 += (double)f3 * vq[j + 3 * G];
+                }
+            }
+            for (; j < c1; j += G) {
+                const float f = F[(int64_t)j * Rp + r];
+                s0 += q == 0 ? (double)f : (double)f * vq[j];
+            }
         }
-        Q[((int64_t)c * Rp + r) * 4 + q] = (float)s;
+        part[t] = (s0 + s1) + (s2 + s3);
+        __syncthreads();
+        if (ph == 0 && item < items) {
+            double v = part[t];
+            for (int g = 1; g < G; g++) v += part[t + g * (256 / G)];
+            Q[((int64_t)c * Rp + (item >> 2)) * 4 + (item & 3)] = (float)v;
+        }
+        __syncthreads();
     }
 }
 
@@ -319,8 +349,9 @@ __device__ inline void flock_emit(const FlockArgs &a, int64_t i, const float k[6
     }
 }
 
-// One thread per row; the block covers up to 256 rows of one community (or
-// of the unassigned tail).  Staged chunks copy the community's state planes
+// Four lanes per row (each takes every fourth partner, then the row's sums
+// are combined across the group); the block covers up to 256 rows of one
+// community (or of the unassigned tail).  Staged chunks copy the community's state planes
 // and features into LDS first.  RP > 0 fixes the feature stride at compile
 // time (own features held in registers); RP == 0 reads it from the arguments.
 template <int RP>
@@ -350,9 +381,12 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
             for (int q = threadIdx.x; q < lam * Rp; q += blockDim.x) sF[q] = a.F[c0 * Rp + q];
     }
     __syncthreads();
-    if ((int)threadIdx.x >= ch.rows) return;  // no barrier below
+    // TPR consecutive lanes share a row (a row's group never straddles a
+    // wavefront); whole groups past the chunk leave together
+    const int rloc = (int)threadIdx.x / TPR, sub = (int)threadIdx.x % TPR;
+    if (rloc >= ch.rows) return;  // no barrier below
 
-    const int64_t i = ch.row0 + threadIdx.x;
+    const int64_t i = ch.row0 + rloc;
     float xi[3], vi[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
@@ -379,7 +413,8 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
     if (c >= 0) {
         const int64_t e0 = a.negptr[i], e1 = a.negptr[i + 1];
         if (!fb) {
-            // E1 broadcast: sum_r sgn_r f_r(s_i) (V_cr - v_i P_cr)
+            // E1 broadcast: sum_r sgn_r f_r(s_i) (V_cr - v_i P_cr), by the
+            // first lane of the row's group
             const float *fi = staged ? sF + (i - c0) * Rp : a.F + i * Rp;
             const float4 *Qc = reinterpret_cast<const float4 *>(a.Q) + (int64_t)c * Rp;
             float g[RP > 0 ? RP : 1];
@@ -387,17 +422,19 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
             for (int r = 0; r < Rp; r++) {
                 const float gr = a.sgn[r] * fi[r];
                 if (RP > 0) g[RP > 0 ? r : 0] = gr;
-                const float4 q = Qc[r];
-                sP += gr * q.x;
-                sV0 += gr * q.y;
-                sV1 += gr * q.z;
-                sV2 += gr * q.w;
+                if (sub == 0) {
+                    const float4 q = Qc[r];
+                    sP += gr * q.x;
+                    sV0 += gr * q.y;
+                    sV1 += gr * q.z;
+                    sV2 += gr * q.w;
+                }
             }
             acc[0] = sV0 - vi[0] * sP;
             acc[1] = sV1 - vi[1] * sP;
             acc[2] = sV2 - vi[2] * sP;
             // E2, S-neg: subtract the expanded weight of the missing intra pairs
-            for (int64_t e = e0; e < e1; e++) {
+            for (int64_t e = e0 + sub; e < e1; e += TPR) {
                 const int jl = a.neg[e];
                 const float *fj = staged ? sF + (int64_t)jl * Rp : a.F + (c0 + jl) * Rp;
                 float wt = 0.f;
@@ -417,7 +454,7 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
             }
         } else {
             // exact fallback: all pairs of the community minus S-neg
-            for (int jl = 0; jl < lam; jl++) {
+            for (int jl = sub; jl < lam; jl += TPR) {
                 if (c0 + jl == i) continue;
                 float xj[3], vj[3];
                 member(jl, xj, vj);
@@ -426,7 +463,7 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
 #pragma unroll
                 for (int d = 0; d < 3; d++) acc[d] += w * (vj[d] - vi[d]);
             }
-            for (int64_t e = e0; e < e1; e++) {
+            for (int64_t e = e0 + sub; e < e1; e += TPR) {
                 float xj[3], vj[3];
                 member(a.neg[e], xj, vj);
                 const float d0 = xj[0] - xi[0], d1 = xj[1] - xi[1], d2 = xj[2] - xi[2];
@@ -437,15 +474,21 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
         }
     }
     // E2, S-pos: exact weight on the pairs leaving the community
-    for (int64_t e = a.posptr[i], e1 = a.posptr[i + 1]; e < e1; e++) {
+    for (int64_t e = a.posptr[i] + sub, e1 = a.posptr[i + 1]; e < e1; e += TPR) {
         const int64_t j = a.pos[e];
         const float d0 = a.Ys[j] - xi[0], d1 = a.Ys[n + j] - xi[1], d2 = a.Ys[2 * n + j] - xi[2];
         const float w = cs_weight(d0 * d0 + d1 * d1 + d2 * d2, a.K, a.s2, a.beta);
 #pragma unroll
         for (int d = 0; d < 3; d++) acc[d] += w * (a.Ys[(3 + d) * n + j] - vi[d]);
     }
-    const float k[6] = {vi[0], vi[1], vi[2], acc[0] * a.invN, acc[1] * a.invN, acc[2] * a.invN};
-    flock_emit(a, i, k);
+    // the row's partial sums, combined in a fixed order across its group
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+        for (int o = 1; o < TPR; o <<= 1) acc[d] += __shfl_xor(acc[d], o);
+    if (sub == 0) {
+        const float k[6] = {vi[0], vi[1], vi[2], acc[0] * a.invN, acc[1] * a.invN, acc[2] * a.invN};
+        flock_emit(a, i, k);
+    }
 }
 
 // Direct method: one wavefront per row of the adjacency in community order.
@@ -1069,7 +1112,7 @@ cia_status launch_stage(cia_plan *p, const FlockArgs &a, hipStream_t s) {
             case 28: flock_stage_kernel<28><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
             case 32: flock_stage_kernel<32><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
             case 48: flock_stage_kernel<48><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
-            case 64: flock_stage_kernel<64><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
+            // 64 cached features would spill registers at 1024 threads per block
             default: flock_stage_kernel<0><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
         }
     }
@@ -1341,7 +1384,6 @@ cia_status flock_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
             case 28: e = hipFuncSetAttribute((const void *)flock_stage_kernel<28>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
             case 32: e = hipFuncSetAttribute((const void *)flock_stage_kernel<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
             case 48: e = hipFuncSetAttribute((const void *)flock_stage_kernel<48>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
-            case 64: e = hipFuncSetAttribute((const void *)flock_stage_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
             default: e = hipFuncSetAttribute((const void *)flock_stage_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
         }
         if (e != hipSuccess) {
