@@ -248,6 +248,20 @@ def test_flock_training_gain_and_judge(env):
     say("learned rank 32 err", err_l, "fourier p=1 err", err_f, "gain", err_f / err_l)
     assert err_l < 2e-2
     assert err_f > 5 * err_l
+    # Eckart-Young: no rank-32 symmetric separable weight beats the truncated
+    # eigendecomposition of a community's weight matrix
+    members = np.flatnonzero(g.labels == 0)
+    xm = s64[:3, members]
+    Wc = (1.0 + ((xm[:, :, None] - xm[:, None, :]) ** 2).sum(0)) ** -0.25
+    ev = np.linalg.eigvalsh(Wc)
+    floor = np.sqrt(np.sort(ev ** 2)[:-32].sum())
+    Fm = torch.empty((len(members), 32), dtype=torch.float32, device="cuda")
+    plan.basis_features(torch.as_tensor(xm.astype(np.float32), device="cuda").contiguous(), Fm)
+    torch.cuda.synchronize()
+    Fh = Fm.cpu().numpy().astype(np.float64)
+    learned_fro = np.linalg.norm(Fh @ Fh.T - Wc)
+    say("community 0: rank-32 Eckart-Young floor", floor, "learned", learned_fro, "ratio", learned_fro / floor)
+    assert learned_fro >= floor * (1 - 1e-9)
     # judge: an untrained basis fails everywhere, so every community takes the
     # exact path; the trained one fails a tight bound (rank 32 cannot reach
     # 1e-3 here) and passes a loose one

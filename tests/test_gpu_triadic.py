@@ -111,3 +111,51 @@ def test_triadic_rejects_intra_listed_triangle(env):
         cia.Plan.triadic(g.n, g.row_ptr, g.col, g.labels, None, K1=1, K2=1, tri_seed=T.tri_seed, p_tri=T.p_tri,
                          cross_tri=bad)
     assert "inside one community" in cia.cia_last_error()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_triadic_config3_community_sizes(env, precision):
+    """The config-3 recipe (sizes U[200, 2000], pairwise p_in 0.9 and inter
+    degree 3, intra triples with p = 0.9, 3 cross triples per node on
+    average) at N = 6000; CIA against the oracle on sampled rows."""
+    cia, torch = env
+    T = W.triadic(seed=3, n=6000)
+    g = T.graph
+    say("config-3 sizes: n", g.n, "communities", g.ncomm, "precision", precision)
+    plan = plan_for(cia, T, 0, precision)
+    dt = torch.float64 if precision else torch.float32
+    th = torch.as_tensor(T.theta0, dtype=dt, device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(0).choice(g.n, 150, replace=False)
+    want = oracle.triadic_rhs(g.n, g.row_ptr, g.col, g.labels, T.tri_seed, T.p_tri, T.cross_tri, None, T.K1,
+                              T.K2, th.cpu().numpy().astype(np.float64), rows=rows)
+    err = rel_inf(got[rows], want)
+    say("   missing pairs", plan.info().nnz_extra, "rel_inf", err)
+    assert err < (1e-12 if precision else 1e-5)
+    plan.close()
+
+
+def test_triadic_full_size_direct(env):
+    """Config 3 at full size (N = 1e5, 91 communities of U[200, 2000]): the
+    direct method (present hyperedges enumerated on the GPU with the
+    predicate) against the oracle on sampled rows."""
+    cia, torch = env
+    T = W.triadic(seed=3, n=100_000)
+    g = T.graph
+    say("config 3: n", g.n, "communities", g.ncomm, "pairwise nnz", g.nnz, "cross triples", len(T.cross_tri))
+    plan = plan_for(cia, T, 1, 0)
+    th = torch.as_tensor(T.theta0, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(1).choice(g.n, 60, replace=False)
+    want = oracle.triadic_rhs(g.n, g.row_ptr, g.col, g.labels, T.tri_seed, T.p_tri, T.cross_tri, None, T.K1,
+                              T.K2, th.cpu().numpy().astype(np.float64), rows=rows)
+    err = rel_inf(got[rows], want)
+    say("   rel_inf", err)
+    assert err < 1e-5
+    plan.close()
