@@ -48,11 +48,12 @@ def profiled_traffic():
 
 def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True, timing_every=0):
     import numpy as np
-    th = torch.as_tensor(theta0, dtype=torch.float32, device="cuda")
+    tdt = torch.float64 if plan.precision == 1 else torch.float32
+    th = torch.as_tensor(theta0, dtype=tdt, device="cuda")
     if warmup:
         plan.integrate(th, dt, warmup, np.zeros(warmup + 1) if with_r else None)
     torch.cuda.synchronize()
-    th = torch.as_tensor(theta0, dtype=torch.float32, device="cuda")
+    th = torch.as_tensor(theta0, dtype=tdt, device="cuda")
     r = np.zeros(steps + 1) if with_r else None
     stream = torch.cuda.current_stream()
     # kernel durations: HIP events around one stage launch in `timing_every`
@@ -136,8 +137,10 @@ def main():
     log("workload %s: n=%d nnz=%d communities=%d (%.1fs)" % (P.name, g.n, g.nnz, g.ncomm, time.time() - t0))
 
     every = 0 if args.no_timing else max(1, args.timing_every)
+    # the N = 1000 network is run in FP64, as specified for it
+    prec = cia.CIA_F64 if args.workload == "small" else cia.CIA_F32
     t0 = time.time()
-    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K,
+    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, precision=prec,
                           unit_work=args.unit_work, block=args.block)
     tune = None
     if args.autotune and not args.unit_work and not args.block:
@@ -169,7 +172,8 @@ def main():
 
     # direct method, same data layout and stepper
     t0 = time.time()
-    dplan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, method=cia.CIA_METHOD_DIRECT)
+    dplan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, method=cia.CIA_METHOD_DIRECT,
+                           precision=prec)
     dinfo = dplan.info()
     log("direct plan: units=%d nnz=%d (%.1fs)" % (dinfo.nunits, dinfo.nnz_pos, time.time() - t0))
     dsteps = min(args.direct_steps, args.steps)
@@ -211,7 +215,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if prec == cia.CIA_F64 else "f32",
         "data": "synthetic",
         "config": {"workload": P.name, "n": n, "communities": info.ncomm, "nnz_graph": info.nnz_graph,
                    "nnz_neg": info.nnz_neg, "nnz_pos": info.nnz_pos, "stepper": "rk4", "dt": P.dt,
