@@ -198,9 +198,12 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream);
  *            wrapped into [0, 2 pi).
  *  r_trace : optional host [steps+1]; receives the global order parameter
  *            r(t_n) = |(1/N) sum_m exp(i theta_m)| (App. A.4) accumulated in
- *            FP64 (phase models only; NULL = not computed).  When non-NULL the
- *            call synchronises the stream and returns CIA_ENONFINITE if the
- *            final state holds a NaN or an Inf.
+ *            FP64 (phase models only; NULL = not computed; plans of
+ *            cia_build_batch fill [count][steps+1], one trace per instance).
+ *            When non-NULL the call synchronises the stream and returns
+ *            CIA_ENONFINITE if the state became NaN or Inf.
+ *  The flock model integrates positions and velocities (six planes); it
+ *  takes no r_trace (CIA_EINVAL if given).
  */
 cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
                          void *stream);

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(cia):
 
 def test_struct_layouts_match(cia):
     for cls in (cia.cia_graph, cia.cia_hypergraph, cia.cia_coupling, cia.cia_options,
-                cia.cia_plan_info, cia.cia_timing):
+                cia.cia_plan_info, cia.cia_timing, cia.cia_tune_report):
         assert cia.cia_abi_sizeof(cls.__name__) == ctypes.sizeof(cls), cls.__name__
     assert cia.cia_abi_sizeof("nope") == 0
 
