@@ -78,9 +78,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble"],
-                    help="large: the N = 1e6 Kuramoto bench line; flock and ensemble: the Cucker-Smale "
-                         "and batched-ensemble workloads (measurement modes, not the bench line)")
+    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble", "triadic"],
+                    help="large: the N = 1e6 Kuramoto bench line; flock, ensemble and triadic: the "
+                         "Cucker-Smale, batched-ensemble and higher-order workloads (measurement modes, "
+                         "not the bench line)")
+    ap.add_argument("--triadic-n", type=int, default=6000, help="triadic: network size (sizes U[200, 2000])")
     ap.add_argument("--train-iters", type=int, default=3000, help="flock: optimiser steps of the basis")
     ap.add_argument("--ensemble-nmax", type=float, default=2e4, help="ensemble: largest instance size")
     ap.add_argument("--direct-steps", type=int, default=100,
@@ -130,6 +132,8 @@ def main():
         return bench_flock(args, cia, W, torch, np)
     if args.workload == "ensemble":
         return bench_ensemble(args, cia, W, torch, np)
+    if args.workload == "triadic":
+        return bench_triadic(args, cia, W, torch, np)
 
     t0 = time.time()
     P = W.kuramoto_large() if args.workload == "large" else W.kuramoto_small()
@@ -354,6 +358,49 @@ def bench_ensemble(args, cia, W, torch, np):
         "config": {"workload": "ensemble_256", "n_total": ntot, "n_max": args.ensemble_nmax, "stepper": "rk4",
                    "dt": 0.01},
         "methods": res, "speedup_vs_sequential": res["batched"]["value"] / res["sequential"]["value"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_triadic(args, cia, W, torch, np):
+    """Higher-order Kuramoto with the config-3 community sizes (U[200, 2000],
+    pairwise p_in 0.9, intra triples with p = 0.9, 3 cross triples per node):
+    CIA (stored missing pairs) against the direct method (present triples
+    enumerated on the GPU), FP32, RK4."""
+    T = W.triadic(seed=3, n=args.triadic_n)
+    g = T.graph
+    n = g.n
+    log("triadic workload: n=%d communities=%d pairwise nnz=%d cross triples=%d" % (
+        n, g.ncomm, g.nnz, len(T.cross_tri)))
+    steps = min(args.steps, 20)
+    res = {}
+    for name, method in (("cia", cia.CIA_METHOD_CIA), ("direct", cia.CIA_METHOD_DIRECT)):
+        t0 = time.time()
+        plan = cia.Plan.triadic(n, g.row_ptr, g.col, g.labels, T.omega, K1=T.K1, K2=T.K2, tri_seed=T.tri_seed,
+                                p_tri=T.p_tri, cross_tri=T.cross_tri, method=method)
+        build_s = time.time() - t0
+        info = plan.info()
+        th = torch.as_tensor(T.theta0.astype(np.float32), device="cuda")
+        plan.integrate(th, T.dt, 1)
+        th = torch.as_tensor(T.theta0.astype(np.float32), device="cuda")
+        plan.set_timing(1)
+        plan.timing(reset=True)
+        ms = timed(torch, lambda s: plan.integrate(th, T.dt, steps, stream=s))
+        t = plan.timing(reset=True)
+        res[name] = {"value": n * 4 * steps / (ms / 1e3), "ms_per_step": ms / steps,
+                     "stage_us": round(1e3 * t.stage_ms / max(t.stage_launches, 1), 2),
+                     "aux_us": round(1e3 * t.aux_ms / max(t.aux_launches, 1), 2),
+                     "build_s": round(build_s, 2), "pair_entries": info.nnz_extra,
+                     "bytes_per_stage": info.bytes_per_stage}
+        log("%-7s %.3f ms/step (build %.1f s, %d stored pairs)" % (name, ms / steps, build_s, info.nnz_extra))
+        plan.close()
+    out = {
+        "metric": "triadic RHS node-updates/s (CIA), 1 MI355X, config-3 community sizes",
+        "value": res["cia"]["value"], "unit": "RHS node-updates/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": res["cia"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "triadic_n%d" % n, "n": n, "communities": g.ncomm, "stepper": "rk4", "dt": T.dt},
+        "methods": res, "speedup_vs_direct": res["cia"]["value"] / res["direct"]["value"],
     }
     print(json.dumps(out), flush=True)
 

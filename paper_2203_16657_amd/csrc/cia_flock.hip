@@ -155,9 +155,14 @@ __global__ void flock_permute_out(const float *__restrict__ Y, const int32_t *__
 // Fourier features of every point (one thread per point): F[i][0] = 1,
 // F[i][1+2h] = cos(pi <alpha_h, s_i> / L), F[i][2+2h] = sin(...), zero padding.
 __global__ void fourier_features_kernel(const float *__restrict__ X, int64_t n, const int4 *__restrict__ alpha,
-                                        int nh, float pi_over_L, int Rp, float *__restrict__ F) {
+                                        int nh, float pi_over_L, int Rp, const int32_t *__restrict__ comm_of,
+                                        const int32_t *__restrict__ fb, float *__restrict__ F) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (comm_of) {  // only members of communities on the separable path need features
+        const int c = comm_of[i];
+        if (c < 0 || (fb && fb[c])) return;
+    }
     float x0 = X[i], x1 = X[n + i], x2 = X[2 * n + i];
     float *f = F + i * Rp;
     f[0] = 1.0f;
@@ -173,6 +178,8 @@ __global__ void fourier_features_kernel(const float *__restrict__ X, int64_t n, 
 }
 
 struct MlpArgs {
+    const int32_t *comm_of;   // optional: skip tiles without a member of a separable-path community
+    const int32_t *fb;        //   (with fb: communities on the exact fallback count as not needing)
     const float *params;   // FP32 master parameters (W1, b1, b2, b3 read from here)
     const uint16_t *w2b;   // bf16 W2 [64][64]
     const uint16_t *w3b;   // bf16 W3 [R][64]
@@ -198,6 +205,15 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const float *__restri
     }
     if (t < R) sb3[t] = m.params[po.b3 + t];
     const int64_t p0 = (int64_t)blockIdx.x * TILE_PTS;
+    if (m.comm_of) {
+        const int64_t p = p0 + (t >> 2);
+        int need = 0;
+        if (p < n) {
+            const int c = m.comm_of[p];
+            need = c >= 0 && !(m.fb && m.fb[c]);
+        }
+        if (!__syncthreads_or(need)) return;  // the whole block leaves together
+    }
     {
         // layer 1: thread t -> point t/4, hidden units 16*(t%4) .. +15
         const int pl = t >> 2, g = (t & 3) * 16;
@@ -247,9 +263,10 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const float *__restri
 
 __global__ __launch_bounds__(256) void flock_e1_kernel(const float *__restrict__ F, const float *__restrict__ Y,
                                                        int64_t n, const int32_t *__restrict__ comm_off, int Rp,
-                                                       float *__restrict__ Q) {
+                                                       const int32_t *__restrict__ fb, float *__restrict__ Q) {
     __shared__ double part[256];
     const int c = blockIdx.x, t = threadIdx.x;
+    if (fb && fb[c]) return;  // exact fallback: no observables needed (whole block)
     const int c0 = comm_off[c], c1 = comm_off[c + 1];
     const int items = Rp * 4;
     // G threads share an item and take every G-th row; four independent
@@ -1056,13 +1073,20 @@ void set_box(FlockState *f, const double lo[3], const double hi[3]) {
 }
 
 // features of the stage state X (community order) into f->F
-cia_status run_features(cia_plan *p, const float *X, int64_t n, float *F, hipStream_t s) {
+// features of the points X into F; with comm_of (a stage state in community
+// order) only members of communities that need them are computed: every
+// separable-path community, or with fb those not on the exact fallback
+cia_status run_features(cia_plan *p, const float *X, int64_t n, float *F, hipStream_t s,
+                        const int32_t *comm_of = nullptr, const int32_t *fb = nullptr) {
     FlockState *f = p->flock;
     if (f->basis == CIA_BASIS_FOURIER) {
         fourier_features_kernel<<<grid_for(n, 256), 256, 0, s>>>(X, n, f->alpha, f->nh, (float)(M_PI / f->L),
-                                                                 f->Rp, F);
+                                                                 f->Rp, comm_of, fb, F);
     } else if (f->basis == CIA_BASIS_LEARNED) {
-        mlp_features_kernel<<<grid_for(n, TILE_PTS), 256, 0, s>>>(X, n, mlp_args(f), F);
+        MlpArgs m = mlp_args(f);
+        m.comm_of = comm_of;
+        m.fb = fb;
+        mlp_features_kernel<<<grid_for(n, TILE_PTS), 256, 0, s>>>(X, n, m, F);
     }
     CIA_HIP(hipGetLastError());
     return CIA_OK;
@@ -1073,8 +1097,11 @@ cia_status run_observables(cia_plan *p, const float *Ys, bool judge, hipStream_t
     FlockState *f = p->flock;
     if (p->method != CIA_METHOD_CIA || f->basis == CIA_BASIS_EXACT || f->ncomm == 0) return CIA_OK;
     CIA_TRY(timing_begin(p, s, KK_PREP));
-    CIA_TRY(run_features(p, Ys, p->n, f->F, s));
-    flock_e1_kernel<<<f->ncomm, 256, 0, s>>>(f->F, Ys, p->n, f->comm_off, f->Rp, f->Q);
+    // the judged stage needs every community's features and observables; the
+    // other stages skip communities held on the exact fallback
+    const int32_t *skip = (judge && f->judge) ? nullptr : f->fb;
+    CIA_TRY(run_features(p, Ys, p->n, f->F, s, f->comm_of, skip));
+    flock_e1_kernel<<<f->ncomm, 256, 0, s>>>(f->F, Ys, p->n, f->comm_off, f->Rp, skip, f->Q);
     CIA_HIP(hipGetLastError());
     if (judge && f->judge) {
         JudgeArgs j{};
