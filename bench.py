@@ -391,7 +391,7 @@ def bench_triadic(args, cia, W, torch, np):
                      "stage_us": round(1e3 * t.stage_ms / max(t.stage_launches, 1), 2),
                      "aux_us": round(1e3 * t.aux_ms / max(t.aux_launches, 1), 2),
                      "build_s": round(build_s, 2), "pair_entries": info.nnz_extra,
-                     "bytes_per_stage": info.bytes_per_stage}
+                     "bytes_per_stage": info.bytes_per_stage, "bytes_aux": info.bytes_aux}
         log("%-7s %.3f ms/step (build %.1f s, %d stored pairs)" % (name, ms / steps, build_s, info.nnz_extra))
         plan.close()
     out = {
@@ -402,6 +402,13 @@ def bench_triadic(args, cia, W, torch, np):
         "config": {"workload": "triadic_n%d" % n, "n": n, "communities": g.ncomm, "stepper": "rk4", "dt": T.dt},
         "methods": res, "speedup_vs_direct": res["cia"]["value"] / res["direct"]["value"],
     }
+    aux_us = res["cia"]["aux_us"]
+    if aux_us > 0 and res["cia"]["bytes_aux"] > 0:
+        # the missing-pair sum launch streams the stored lists once per stage
+        achieved = res["cia"]["bytes_aux"] / (aux_us * 1e-6) / 1e9
+        out["roofline"] = {"kernel": "tri_missing_kernel", "bound": "hbm", "achieved": round(achieved, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": None}
     print(json.dumps(out), flush=True)
 
 

@@ -333,6 +333,9 @@ typedef struct cia_plan_info {
     int32_t judge_fallbacks;  /* flock: communities currently on the exact fallback (read
                                  from the device; synchronises it) */
     int32_t reserved;
+    double bytes_aux;         /* algorithmic HBM bytes of the auxiliary launch before each
+                                 stage (triadic pair sums: the missing-pair lists, 16 B per
+                                 chunk, and the sums written), 0 if there is none */
 } cia_plan_info;
 
 cia_status cia_plan_get_info(const cia_plan *p, cia_plan_info *info);

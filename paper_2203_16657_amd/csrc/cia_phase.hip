@@ -144,7 +144,7 @@ struct PhaseArgs {
     const Slice *slices;
     const uint4 *negdata;     // S-neg slice blocks
     const uint4 *posdata;     // S-pos slice blocks
-    const uint4 *tnegdata;    // missing intra-community hyperedges (triadic)
+    const void *tri_m;        // triadic CIA: per row, sum over missing intra pairs of z_j z_k (cx<R>)
     const uint4 *tposdata;    // hyperedges across communities (triadic)
     const cx<R> *h_extra;     // direct triadic: sum over present intra pairs of z_j z_k
     const int32_t *cnt;       // [n] |S+| - |S-| per row (only when d_0 != 0)
@@ -307,14 +307,12 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
     }
 }
 
-// Stream a lane's list of partner pairs (j, k) and return sum z_j z_k.
-// STAGED: 4 pairs of uint16 LDS byte offsets per chunk (LDS gathers, the
-// padding offset lambda * sizeof(z) holds 0); otherwise 2 pairs of int32 positions per chunk, gathered
-// as z (GATHER_Z) or as theta with z recomputed; pad position contributes 0.
-template <typename R, int U, bool STAGED, bool GATHER_Z>
-__device__ __forceinline__ cx<R> gather_pairs(const uint4 *__restrict__ col, int w, const cx<R> *zsh,
-                                              const cx<R> *__restrict__ cs, const R *__restrict__ th,
-                                              uint32_t pad, uint4 padv) {
+// Stream a lane's list of partner pairs (j, k) and return sum z_j z_k:
+// 2 pairs of int32 positions per chunk, gathered as z (GATHER_Z) or as
+// theta with z recomputed; the pad position contributes 0.
+template <typename R, int U, bool GATHER_Z>
+__device__ __forceinline__ cx<R> gather_pairs(const uint4 *__restrict__ col, int w, const cx<R> *__restrict__ cs,
+                                              const R *__restrict__ th, uint32_t pad, uint4 padv) {
     cx<R> M = {(R)0, (R)0};
     auto zof = [&](uint32_t j) -> cx<R> {
         if (GATHER_Z) return cs[j];
@@ -328,20 +326,10 @@ __device__ __forceinline__ cx<R> gather_pairs(const uint4 *__restrict__ col, int
         for (int u = 0; u < U; u++) v[u] = k + u < w ? ld_stream(col + (size_t)(k + u) * SLICE) : padv;
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if (STAGED) {
-                const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const cx<R> p = cmul(zat(zsh, q4[q] & 0xffffu), zat(zsh, q4[q] >> 16));
-                    M.x += p.x;
-                    M.y += p.y;
-                }
-            } else {
-                const cx<R> p0 = cmul(zof(v[u].x), zof(v[u].y));
-                const cx<R> p1 = cmul(zof(v[u].z), zof(v[u].w));
-                M.x += p0.x + p1.x;
-                M.y += p0.y + p1.y;
-            }
+            const cx<R> p0 = cmul(zof(v[u].x), zof(v[u].y));
+            const cx<R> p1 = cmul(zof(v[u].z), zof(v[u].w));
+            M.x += p0.x + p1.x;
+            M.y += p0.y + p1.y;
         }
     }
     return M;
@@ -464,16 +452,8 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
         }
         cx<R> Mt = {(R)0, (R)0}, Xt = {(R)0, (R)0};   // missing intra / cross hyperedge pair sums
         if (TRI && gather) {
-            if (!DIRECT) {
-                if (staged)
-                    Mt = gather_pairs<R, 2, true, false>(a.tnegdata + S.beg[2] + lane, S.w[2], zsh, a.cs_in, a.th_in,
-                                                          a.pad_pos, padl);
-                else
-                    Mt = gather_pairs<R, 2, false, false>(a.tnegdata + S.beg[2] + lane, S.w[2], zsh, a.cs_in, a.th_in,
-                                                           a.pad_pos, padp);
-            }
-            Xt = gather_pairs<R, 2, false, DIRECT>(a.tposdata + S.beg[3] + lane, S.w[3], zsh, a.cs_in, a.th_in,
-                                                   a.pad_pos, padp);
+            if (!DIRECT && assigned && mine && a.tri_m) Mt = static_cast<const cx<R> *>(a.tri_m)[i];
+            Xt = gather_pairs<R, 2, DIRECT>(a.tposdata + S.beg[3] + lane, S.w[3], a.cs_in, a.th_in, a.pad_pos, padp);
         }
 
         // ---- combine (eq. FastHdense + E2), stage update, next z ----
@@ -671,14 +651,188 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     }
 }
 
-// Direct triadic baseline: for every centre, the sum of z_j z_k over the
-// present intra-community hyperedges {m, j, k}, j < k, found by evaluating
-// the hyperedge predicate for every pair of the community (O(lambda^2) per
-// centre).  One block per (community, 256 centres); z and user ids staged.
+// ---------------------------------------------------------------------------
+// triadic model: intra-community hyperedges (App. A.7 on a hypergraph)
+// ---------------------------------------------------------------------------
+// A triple {m, j, k} of one community is a hyperedge iff
+// splitmix64(seed ^ key(m, j, k)) < thr.  The kernels below take a block of
+// up to TRI_ROWS centres of one community, stage the community's user ids
+// (and z) in LDS and give each wavefront one centre at a time; the centre's
+// partner pairs (x, y), x < y, are walked x-major with the 64 lanes over y.
+
+// splitmix64 output for state x (Steele, Lea, Flood, OOPSLA 2014)
+__host__ __device__ static inline uint64_t splitmix64_out(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+constexpr int TRI_ROWS = 16;   // centres per enumeration block (4 wavefronts)
+constexpr int TRI_RUN = 7;     // partners per chunk of a missing-pair list
+
 struct alignas(16) TriBlock {
     int32_t off, lam, row0, rows;
 };
 
+// lanes below the calling lane whose bit is set in m
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Pairs (x, y), x < y < lam, x != me != y, of centre `me`: group(x, y, ok,
+// miss) for every 64 consecutive y of an x (ok: y is a partner; miss: the
+// triple is not a hyperedge), then run_end(x).  Wave-uniform control flow.
+template <typename G, typename E>
+__device__ __forceinline__ void tri_walk(const uint32_t *us, int lam, int me, uint64_t seed, uint64_t thr,
+                                         G &&group, E &&run_end) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t ui = us[me];
+    for (int x = 0; x < lam - 1; x++) {
+        if (x == me) continue;
+        const uint32_t ux = us[x];
+        for (int y0 = x + 1; y0 < lam; y0 += 64) {
+            const int y = y0 + lane;
+            const bool ok = y < lam && y != me;
+            bool miss = false;
+            if (ok) miss = splitmix64_out(seed ^ triple_key(ui, ux, us[y])) >= thr;
+            group(x, y, ok, miss);
+        }
+        run_end(x);
+    }
+}
+
+// Missing-pair lists, pass 1: per centre, the number of missing partner
+// pairs and of list chunks (a chunk holds one x and up to TRI_RUN of its y).
+__global__ __launch_bounds__(256) void tri_count_kernel(const TriBlock *blocks, const int32_t *perm, uint64_t seed,
+                                                        uint64_t thr, int32_t *nchunk, int32_t *npair) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *us = reinterpret_cast<uint32_t *>(smem);
+    const TriBlock B = blocks[blockIdx.x];
+    for (int j = threadIdx.x; j < B.lam; j += 256) us[j] = (uint32_t)perm[B.off + j];
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int r = wid; r < B.rows; r += 4) {
+        const int i = B.row0 + r;
+        int c = 0, chunks = 0, pairs = 0;
+        tri_walk(
+            us, B.lam, i - B.off, seed, thr,
+            [&](int, int, bool ok, bool miss) { c += __popcll(__ballot(ok && miss)); },
+            [&](int) {
+                chunks += (c + TRI_RUN - 1) / TRI_RUN;
+                pairs += c;
+                c = 0;
+            });
+        if (lane == 0) {
+            nchunk[i] = chunks;
+            npair[i] = pairs;
+        }
+    }
+}
+
+// Pass 2: write the lists.  Centre i owns chunks [cptr[i], cptr[i+1]); a
+// chunk is 8 uint16 LDS byte offsets (x, then y_1..y_7, unused slots at the
+// zero slot lam).  Writes past the centre's range are dropped; written[i]
+// (chunks produced) lets the host check the two passes agree.
+__global__ __launch_bounds__(256) void tri_fill_kernel(const TriBlock *blocks, const int32_t *perm, uint64_t seed,
+                                                       uint64_t thr, uint32_t zb, const int64_t *cptr, uint16_t *out,
+                                                       int32_t *written) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *us = reinterpret_cast<uint32_t *>(smem);
+    const TriBlock B = blocks[blockIdx.x];
+    for (int j = threadIdx.x; j < B.lam; j += 256) us[j] = (uint32_t)perm[B.off + j];
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint16_t pad = (uint16_t)((uint32_t)B.lam * zb);
+    for (int r = wid; r < B.rows; r += 4) {
+        const int i = B.row0 + r;
+        const int64_t lim = cptr[i + 1];
+        int64_t base = cptr[i];
+        int c = 0;
+        tri_walk(
+            us, B.lam, i - B.off, seed, thr,
+            [&](int, int y, bool ok, bool miss) {
+                const bool m = ok && miss;
+                const uint64_t mask = __ballot(m);
+                if (m) {
+                    const int pos = c + lanes_below(mask);
+                    const int64_t ch = base + pos / TRI_RUN;
+                    if (ch < lim) out[ch * 8 + 1 + pos % TRI_RUN] = (uint16_t)((uint32_t)y * zb);
+                }
+                c += __popcll(mask);
+            },
+            [&](int x) {
+                const int nch = (c + TRI_RUN - 1) / TRI_RUN;
+                for (int q = lane; q < nch * 8; q += 64) {
+                    const int j = q >> 3, sl = q & 7;
+                    if (base + j >= lim) break;
+                    if (sl == 0) out[(base + j) * 8] = (uint16_t)((uint32_t)x * zb);
+                    else if (j * TRI_RUN + sl - 1 >= c) out[(base + j) * 8 + sl] = pad;
+                }
+                base += nch;
+                c = 0;
+            });
+        if (lane == 0) written[i] = (int32_t)(base - cptr[i]);
+    }
+}
+
+// CIA: per centre, M = sum over its missing partner pairs of z_x z_y, one
+// wavefront per centre streaming its chunks (x z_x times the sum of the
+// run's z_y).  Units: centres [c0, c1) of one community, z staged in LDS.
+struct alignas(16) TriUnit {
+    int32_t off, lam, c0, c1;
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void tri_missing_kernel(const TriUnit *units, const cx<R> *cs, const int64_t *cptr,
+                                                          const uint4 *chunks, cx<R> *M) {
+    constexpr int U = 4;   // chunks in flight per lane
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<R> *zsh = reinterpret_cast<cx<R> *>(smem);
+    const TriUnit T = units[blockIdx.x];
+    for (int j = threadIdx.x; j < T.lam; j += 256) zsh[j] = cs[T.off + j];
+    if (threadIdx.x == 0) zsh[T.lam] = cx<R>{(R)0, (R)0};
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t padb = (uint32_t)T.lam * (uint32_t)sizeof(cx<R>);
+    const uint32_t pad16 = padb | (padb << 16);
+    const uint4 padv = make_uint4(pad16, pad16, pad16, pad16);
+    for (int i = T.c0 + wid; i < T.c1; i += 4) {
+        const int64_t e = cptr[i + 1];
+        cx<R> acc = {(R)0, (R)0};
+        for (int64_t k = cptr[i] + lane; k < e; k += 64 * U) {
+            uint4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) v[u] = k + 64 * u < e ? ld_stream(chunks + k + 64 * u) : padv;
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const cx<R> zx = zat(zsh, v[u].x & 0xffffu);
+                const uint32_t ys[7] = {v[u].x >> 16, v[u].y & 0xffffu, v[u].y >> 16, v[u].z & 0xffffu,
+                                        v[u].z >> 16, v[u].w & 0xffffu, v[u].w >> 16};
+                cx<R> S = zat(zsh, ys[0]);
+#pragma unroll
+                for (int q = 1; q < 7; q++) {
+                    const cx<R> zy = zat(zsh, ys[q]);
+                    S.x += zy.x;
+                    S.y += zy.y;
+                }
+                const cx<R> p = cmul(zx, S);
+                acc.x += p.x;
+                acc.y += p.y;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o);
+            acc.y += __shfl_xor(acc.y, o);
+        }
+        if (lane == 0) M[i] = acc;
+    }
+}
+
+// Direct triadic baseline: per centre, the sum of z_x z_y over the PRESENT
+// intra-community hyperedges {m, x, y}, x < y, found by evaluating the
+// hyperedge predicate for every pair of the community (O(lambda^2) per
+// centre); one wavefront per centre, lanes over y.
 template <typename R>
 __global__ __launch_bounds__(256) void triadic_present_kernel(const TriBlock *blocks, const int32_t *perm,
                                                               const cx<R> *cs, uint64_t seed, uint64_t thr,
@@ -692,30 +846,31 @@ __global__ __launch_bounds__(256) void triadic_present_kernel(const TriBlock *bl
         us[j] = (uint32_t)perm[B.off + j];
     }
     __syncthreads();
-    if ((int)threadIdx.x >= B.rows) return;
-    const int i = B.row0 + threadIdx.x;
-    const int me = i - B.off;
-    const uint32_t ui = us[me];
-    cx<R> E = {(R)0, (R)0};
-    for (int x = 0; x < B.lam; x++) {
-        if (x == me) continue;
-        const uint32_t ux = us[x];
-        const cx<R> zx = zs[x];
-        for (int y = x + 1; y < B.lam; y++) {
-            if (y == me) continue;
-            const uint64_t key = triple_key(ui, ux, us[y]);
-            uint64_t z = (seed ^ key) + 0x9E3779B97F4A7C15ULL;
-            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-            z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-            z ^= z >> 31;
-            if (z < thr) {
-                const cx<R> p = cmul(zx, zs[y]);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int r = wid; r < B.rows; r += 4) {
+        const int i = B.row0 + r;
+        cx<R> E = {(R)0, (R)0}, S = {(R)0, (R)0};
+        tri_walk(
+            us, B.lam, i - B.off, seed, thr,
+            [&](int, int y, bool ok, bool miss) {
+                if (ok && !miss) {
+                    const cx<R> zy = zs[y];
+                    S.x += zy.x;
+                    S.y += zy.y;
+                }
+            },
+            [&](int x) {
+                const cx<R> p = cmul(zs[x], S);
                 E.x += p.x;
                 E.y += p.y;
-            }
+                S = cx<R>{(R)0, (R)0};
+            });
+        for (int o = 32; o > 0; o >>= 1) {
+            E.x += __shfl_xor(E.x, o);
+            E.y += __shfl_xor(E.y, o);
         }
+        if (lane == 0) out[i] = E;
     }
-    out[i] = E;
 }
 
 // standalone reduction (one wavefront); with slot_ctr (replayed graphs) the
@@ -886,6 +1041,12 @@ struct PhaseState {
     TriBlock *tri_blocks = nullptr;   // direct triadic: (community, centres) blocks
     int32_t ntri_blocks = 0;
     size_t tri_smem = 0;
+    TriUnit *tri_units = nullptr;     // CIA triadic: missing-pair sum units
+    int32_t tri_nunits = 0;
+    size_t tri_msmem = 0;
+    int64_t *tri_cptr = nullptr;      // [n+1] chunk offsets of the missing-pair lists
+    uint4 *tri_chunks = nullptr;
+    void *tri_m = nullptr;            // [n] missing-pair sums (cx<R>)
     void *h_extra = nullptr;
     int32_t nunits = 0, ncomm = 0;
     int lds_cap = 0;
@@ -895,7 +1056,7 @@ struct PhaseState {
     // device
     Unit *units = nullptr;
     Slice *slices = nullptr;
-    uint4 *negdata = nullptr, *posdata = nullptr, *tnegdata = nullptr, *tposdata = nullptr;
+    uint4 *negdata = nullptr, *posdata = nullptr, *tposdata = nullptr;
     int32_t *cnt = nullptr, *perm = nullptr;
     void *omega = nullptr, *theta_n = nullptr, *acc = nullptr, *th[2] = {nullptr, nullptr};
     void *cs[2] = {nullptr, nullptr};
@@ -1169,73 +1330,18 @@ static int32_t make_units(const Sell &sell, const std::vector<int32_t> &comm_off
 // triadic model: hyperedge lists per centre (App. A.7 on a hypergraph)
 // ---------------------------------------------------------------------------
 
-// splitmix64 output for state x (Steele, Lea, Flood, OOPSLA 2014)
-static inline uint64_t splitmix64_out(uint64_t x) {
-    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
-
 static uint64_t triple_threshold(double p) {
     if (p <= 0.0) return 0;
     if (p >= 1.0) return UINT64_MAX;
     return (uint64_t)std::ldexp(p, 64);
 }
 
-// For every centre of every community: the partner pairs (j, k), j < k, of
-// intra-community triples that are NOT hyperedges (local indices packed as
-// two int32 per entry), and, for every centre, the partner pairs of the
-// explicit cross-community hyperedges (old positions).  Lists are in P1's
-// (old) position order.
-static cia_status triadic_lists(const P1 &p1, const cia_hypergraph *h, bool want_missing,
-                                std::vector<int64_t> &mptr, std::vector<int32_t> &mval,
-                                std::vector<int64_t> &xptr, std::vector<int32_t> &xval, int64_t &n_missing) {
+// For every centre, the partner pairs of the explicit cross-community
+// hyperedges (old positions), in P1's (old) position order.  The
+// intra-community triples are given by the predicate and listed on the GPU.
+static cia_status triadic_cross_lists(const P1 &p1, const cia_hypergraph *h, std::vector<int64_t> &xptr,
+                                      std::vector<int32_t> &xval) {
     const int64_t n = p1.n;
-    const uint64_t thr = triple_threshold(h->p_intra);
-    const uint64_t seed = h->seed;
-    mptr.assign(n + 1, 0);
-    n_missing = 0;
-    if (want_missing && thr != UINT64_MAX) {
-        // count, then fill (the predicate is evaluated twice; no extra memory)
-        for (int pass = 0; pass < 2; pass++) {
-#pragma omp parallel for schedule(dynamic, 16)
-            for (int64_t i = 0; i < (p1.ncomm ? p1.comm_off[p1.ncomm] : 0); i++) {
-                const int32_t c = p1.comm_of_pos[i];
-                const int64_t off = p1.comm_off[c], lam = p1.comm_off[c + 1] - off;
-                const uint32_t ui = (uint32_t)p1.perm[i];
-                const int64_t me = i - off;
-                int64_t cnt = 0;
-                int32_t *w = pass ? mval.data() + 2 * mptr[i] : nullptr;
-                for (int64_t a = 0; a < lam; a++) {
-                    if (a == me) continue;
-                    const uint32_t ua = (uint32_t)p1.perm[off + a];
-                    for (int64_t b = a + 1; b < lam; b++) {
-                        if (b == me) continue;
-                        const uint32_t ub = (uint32_t)p1.perm[off + b];
-                        if (splitmix64_out(seed ^ triple_key(ui, ua, ub)) >= thr) {
-                            if (pass) {
-                                w[2 * cnt] = (int32_t)a;
-                                w[2 * cnt + 1] = (int32_t)b;
-                            }
-                            cnt++;
-                        }
-                    }
-                }
-                if (!pass) mptr[i + 1] = cnt;
-            }
-            if (!pass) {
-                for (int64_t i = 0; i < n; i++) mptr[i + 1] += mptr[i];
-                n_missing = mptr[n];
-                try {
-                    mval.resize(2 * std::max<int64_t>(n_missing, 1));
-                } catch (const std::bad_alloc &) {
-                    return set_error(CIA_ENOMEM, "host allocation of %lld missing hyperedge pairs failed",
-                                     (long long)n_missing);
-                }
-            }
-        }
-    }
     // explicit hyperedges, three centres each
     xptr.assign(n + 1, 0);
     const int32_t *t = h->tri;
@@ -1263,6 +1369,129 @@ static cia_status triadic_lists(const P1 &p1, const cia_hypergraph *h, bool want
             xval[2 * at + 1] = v[(r + 2) % 3];
         }
     }
+    return CIA_OK;
+}
+
+// Device scratch of one build step, freed on every exit path.
+struct DevTmp {
+    void *p = nullptr;
+    DevTmp() = default;
+    DevTmp(const DevTmp &) = delete;
+    DevTmp &operator=(const DevTmp &) = delete;
+    ~DevTmp() {
+        if (p) (void)hipFree(p);
+    }
+    cia_status alloc(size_t bytes) {
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return set_error(e == hipErrorOutOfMemory ? CIA_ENOMEM : CIA_EHIP, "hipMalloc of %zu bytes failed: %s",
+                             bytes, hipGetErrorString(e));
+        }
+        return CIA_OK;
+    }
+};
+
+// Enumeration blocks (community, up to TRI_ROWS centres) of every community
+// with at least three members.
+static std::vector<TriBlock> tri_blocks(const std::vector<int32_t> &comm_off, int32_t ncomm, int32_t &maxl) {
+    std::vector<TriBlock> tb;
+    maxl = 0;
+    for (int32_t cc = 0; cc < ncomm; cc++) {
+        const int32_t off = comm_off[cc], lam = comm_off[cc + 1] - off;
+        if (lam < 3) continue;
+        maxl = std::max(maxl, lam);
+        for (int32_t r = 0; r < lam; r += TRI_ROWS) tb.push_back(TriBlock{off, lam, off + r, std::min(TRI_ROWS, lam - r)});
+    }
+    return tb;
+}
+
+// CIA triadic: the missing-pair lists of every centre, built on the device
+// (count pass, offsets on the host, fill pass), and the units of the
+// per-stage missing-pair sum, centres of one community with about equal
+// list length.  npairs: missing partner pairs over all centres (three per
+// missing triple); nchunks: list chunks of 16 bytes.
+static cia_status tri_build_missing(cia_plan *p, PhaseState *s, const std::vector<int32_t> &comm_off, int32_t ncomm,
+                                    int64_t n, uint32_t zb, int64_t &npairs, int64_t &nchunks) {
+    npairs = nchunks = 0;
+    if (s->tri_thr == UINT64_MAX) return CIA_OK;   // every intra triple is a hyperedge
+    int32_t maxl = 0;
+    const std::vector<TriBlock> tb = tri_blocks(comm_off, ncomm, maxl);
+    if (tb.empty()) return CIA_OK;
+    if ((int64_t)maxl * zb > 65535)
+        return set_error(CIA_EUNSUPPORTED,
+                         "triadic model: community of %d nodes; missing-pair lists cover communities of up to %d nodes",
+                         maxl, (int)(65535 / zb));
+    DevTmp dblk, dcnt, dpair;
+    CIA_TRY(dblk.alloc(sizeof(TriBlock) * tb.size()));
+    CIA_TRY(dcnt.alloc(sizeof(int32_t) * n));
+    CIA_TRY(dpair.alloc(sizeof(int32_t) * n));
+    CIA_HIP(hipMemcpy(dblk.p, tb.data(), sizeof(TriBlock) * tb.size(), hipMemcpyHostToDevice));
+    CIA_HIP(hipMemset(dcnt.p, 0, sizeof(int32_t) * n));
+    CIA_HIP(hipMemset(dpair.p, 0, sizeof(int32_t) * n));
+    const auto *blk = static_cast<const TriBlock *>(dblk.p);
+    hipLaunchKernelGGL(tri_count_kernel, dim3((unsigned)tb.size()), dim3(256), (size_t)maxl * 4, nullptr, blk, s->perm,
+                       (uint64_t)s->tri_seed, (uint64_t)s->tri_thr, static_cast<int32_t *>(dcnt.p),
+                       static_cast<int32_t *>(dpair.p));
+    CIA_HIP(hipGetLastError());
+    std::vector<int32_t> cnt(n), pairs(n);
+    CIA_HIP(hipMemcpy(cnt.data(), dcnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    CIA_HIP(hipMemcpy(pairs.data(), dpair.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    std::vector<int64_t> cptr(n + 1, 0);
+    for (int64_t i = 0; i < n; i++) {
+        cptr[i + 1] = cptr[i] + cnt[i];
+        npairs += pairs[i];
+    }
+    nchunks = cptr[n];
+    CIA_TRY(dupload(p, &s->tri_cptr, cptr.data(), cptr.size()));
+    CIA_TRY(dalloc(p, &s->tri_chunks, (size_t)std::max<int64_t>(nchunks, 1)));
+    hipLaunchKernelGGL(tri_fill_kernel, dim3((unsigned)tb.size()), dim3(256), (size_t)maxl * 4, nullptr, blk, s->perm,
+                       (uint64_t)s->tri_seed, (uint64_t)s->tri_thr, zb, s->tri_cptr,
+                       reinterpret_cast<uint16_t *>(s->tri_chunks), static_cast<int32_t *>(dpair.p));
+    CIA_HIP(hipGetLastError());
+    std::vector<int32_t> wrote(n);
+    CIA_HIP(hipMemcpy(wrote.data(), dpair.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    for (const TriBlock &b : tb)
+        for (int32_t r = 0; r < b.rows; r++)
+            if (wrote[b.row0 + r] != cnt[b.row0 + r])
+                return set_error(CIA_EHIP, "triadic lists: fill pass wrote %d chunks for centre %d, count pass %d",
+                                 wrote[b.row0 + r], b.row0 + r, cnt[b.row0 + r]);
+
+    // units: cut a community's centres every TRI_ROWS / 4 * 4 centres once
+    // the unit holds `target` chunks (four wavefronts share a unit)
+    const int64_t target = std::max<int64_t>(nchunks / 2048, 1024);
+    std::vector<TriUnit> units;
+    std::vector<int64_t> work;
+    for (int32_t cc = 0; cc < ncomm; cc++) {
+        const int32_t off = comm_off[cc], lam = comm_off[cc + 1] - off;
+        if (lam < 3) continue;
+        int32_t c0 = off;
+        int64_t w = 0;
+        for (int32_t i = off; i < off + lam; i++) {
+            w += cnt[i];
+            if ((w >= target && (i + 1 - c0) % 4 == 0) || i + 1 == off + lam) {
+                units.push_back(TriUnit{off, lam, c0, i + 1});
+                work.push_back(w);
+                c0 = i + 1;
+                w = 0;
+            }
+        }
+    }
+    // longest units first
+    std::vector<int32_t> ord(units.size());
+    for (size_t k = 0; k < ord.size(); k++) ord[k] = (int32_t)k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+    std::vector<TriUnit> sorted(units.size());
+    for (size_t k = 0; k < ord.size(); k++) sorted[k] = units[ord[k]];
+    s->tri_nunits = (int32_t)sorted.size();
+    CIA_TRY(dupload(p, &s->tri_units, sorted.data(), sorted.size()));
+    s->tri_msmem = (size_t)(maxl + 1) * zb;
+    if (s->tri_msmem > LDS_BYTES) return set_error(CIA_EUNSUPPORTED, "triadic model: LDS request too large");
+    unsigned char *raw;
+    CIA_TRY(dalloc(p, &raw, (size_t)zb * n));
+    CIA_HIP(hipMemset(raw, 0, (size_t)zb * n));
+    s->tri_m = raw;
     return CIA_OK;
 }
 
@@ -1334,8 +1563,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     std::vector<char> comm_staged;
     int64_t nnz_neg = 0, nnz_pos = 0, nnz_neg_staged = 0, nnz_tri = 0;
     try {
-        std::vector<int64_t> mptr, xptr;
-        std::vector<int32_t> mval, xval;
+        std::vector<int64_t> xptr;
+        std::vector<int32_t> xval;
         if (!s->direct) {
             // triadic hyperedges are defined on the given communities: keep them all
             CIA_TRY(p1_build(g, labels, o->dense_alpha, keep || s->tri, validate, true, p1));
@@ -1356,11 +1585,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
             S[1].ptr = &p1.posptr;
             S[1].val = p1.pos.data();
             if (s->tri) {
-                CIA_TRY(triadic_lists(p1, c->hyper, true, mptr, mval, xptr, xval, nnz_tri));
-                S[2].ptr = &mptr;
-                S[2].val = mval.data();
-                S[2].local = true;
-                S[2].pair = true;
+                CIA_TRY(triadic_cross_lists(p1, c->hyper, xptr, xval));
                 S[3].ptr = &xptr;
                 S[3].val = xval.data();
                 S[3].pair = true;
@@ -1390,7 +1615,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
                 S[1].ptr = &arp;
                 S[1].val = acol.data();
                 if (s->tri) {
-                    CIA_TRY(triadic_lists(p1, c->hyper, false, mptr, mval, xptr, xval, nnz_tri));
+                    CIA_TRY(triadic_cross_lists(p1, c->hyper, xptr, xval));
                     S[3].ptr = &xptr;
                     S[3].val = xval.data();
                     S[3].pair = true;
@@ -1503,7 +1728,6 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         CIA_TRY(dupload(p, &s->slices, sell.slices.data(), sell.slices.size()));
         CIA_TRY(dupload(p, &s->negdata, sell.data[0].data(), sell.data[0].size()));
         CIA_TRY(dupload(p, &s->posdata, sell.data[1].data(), sell.data[1].size()));
-        CIA_TRY(dupload(p, &s->tnegdata, sell.data[2].data(), sell.data[2].size()));
         CIA_TRY(dupload(p, &s->tposdata, sell.data[3].data(), sell.data[3].size()));
         // the kernels read cnt[i] only when d_0 != 0, and then it holds n entries
         if (s->d0 != 0.0 && (int64_t)cnt.size() != n)
@@ -1577,23 +1801,29 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         }
     }
     if (s->tri && s->direct) {
-        // present-pair enumeration blocks: 256 centres of one community each
-        std::vector<TriBlock> tb;
-        size_t maxl = 0;
-        for (int32_t cc = 0; cc < p1.ncomm; cc++) {
-            const int32_t off = p1.comm_off[cc], lam = p1.comm_off[cc + 1] - off;
-            maxl = std::max<size_t>(maxl, (size_t)lam);
-            for (int32_t r = 0; r < lam; r += 256) tb.push_back(TriBlock{off, lam, off + r, std::min(256, lam - r)});
-        }
-        s->tri_smem = maxl * (2 * rs + 4);
+        // present-pair enumeration blocks: up to TRI_ROWS centres of one community each
+        int32_t maxl = 0;
+        std::vector<TriBlock> tb = tri_blocks(p1.comm_off, p1.ncomm, maxl);
+        s->tri_smem = (size_t)maxl * (2 * rs + 4);
         if (s->tri_smem > LDS_BYTES)
-            return set_error(CIA_EUNSUPPORTED, "direct triadic: community of %zu nodes does not fit in LDS", maxl);
+            return set_error(CIA_EUNSUPPORTED, "direct triadic: community of %d nodes does not fit in LDS", maxl);
         s->ntri_blocks = (int32_t)tb.size();
         if (tb.empty()) tb.push_back(TriBlock{0, 0, 0, 0});
         CIA_TRY(dupload(p, &s->tri_blocks, tb.data(), tb.size()));
         CIA_TRY(dalloc(p, &raw, 2 * rs * n));
         CIA_HIP(hipMemset(raw, 0, 2 * rs * n));
         s->h_extra = raw;
+    }
+    if (s->tri && !s->direct) {
+        int64_t npairs = 0, nchunks = 0;
+        CIA_TRY(tri_build_missing(p, s, p1.comm_off, p1.ncomm, n, (uint32_t)zbytes, npairs, nchunks));
+        inf.nnz_extra = npairs;
+        // per stage: the pair-sum launch reads every chunk once and writes one
+        // sum per community row, which the stage launch reads
+        const double rows = (double)(p1.ncomm ? p1.comm_off[p1.ncomm] : 0);
+        inf.bytes_aux = 16.0 * (double)nchunks + (double)zbytes * rows;
+        inf.bytes_per_stage += (double)zbytes * rows;
+        inf.bytes_per_rhs += inf.bytes_aux + (double)zbytes * rows;
     }
     if (s->complete_direct) {
         CIA_TRY(dalloc(p, &raw, rs * n));
@@ -1633,7 +1863,7 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
     a.slices = s->slices;
     a.negdata = s->negdata;
     a.posdata = s->posdata;
-    a.tnegdata = s->tnegdata;
+    a.tri_m = s->tri_m;
     a.tposdata = s->tposdata;
     a.h_extra = static_cast<const cx<R> *>(s->h_extra);
     a.K2n = (R)s->K2n;
@@ -1696,6 +1926,13 @@ static cia_status launch_stage_p(cia_plan *p, PhaseState *s, const PhaseArgs<R> 
         hipLaunchKernelGGL((triadic_present_kernel<R>), dim3(s->ntri_blocks), dim3(256), s->tri_smem, st,
                            s->tri_blocks, s->perm, a.cs_in, (uint64_t)s->tri_seed, (uint64_t)s->tri_thr,
                            static_cast<cx<R> *>(s->h_extra));
+        CIA_HIP(hipGetLastError());
+        CIA_TRY(timing_end(p, st));
+    }
+    if (s->tri && !s->direct && a.mode != M_PREP && s->tri_nunits > 0) {
+        CIA_TRY(timing_begin(p, st, KK_AUX));
+        hipLaunchKernelGGL((tri_missing_kernel<R>), dim3(s->tri_nunits), dim3(256), s->tri_msmem, st, s->tri_units,
+                           a.cs_in, s->tri_cptr, s->tri_chunks, static_cast<cx<R> *>(s->tri_m));
         CIA_HIP(hipGetLastError());
         CIA_TRY(timing_end(p, st));
     }

@@ -114,6 +114,27 @@ def test_triadic_rejects_intra_listed_triangle(env):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_triadic_missing_pair_count(env, precision):
+    """The missing-pair lists built on the device hold exactly three partner
+    pairs per intra-community triple that is not a hyperedge (counted here
+    with the oracle's predicate over every triple of every community)."""
+    cia, torch = env
+    T = W.triadic(seed=5, n=300, lo=40, hi=100, tri_per_node=0.2)
+    g = T.graph
+    plan = plan_for(cia, T, 0, precision)
+    missing = 0
+    for c in np.unique(g.labels[g.labels >= 0]):
+        mem = [int(u) for u in np.flatnonzero(g.labels == c)]
+        for a in range(len(mem)):
+            for b in range(a + 1, len(mem)):
+                for d in range(b + 1, len(mem)):
+                    missing += not oracle.triple_present(T.tri_seed, T.p_tri, mem[a], mem[b], mem[d])
+    say("missing triples", missing, "stored pairs", plan.info().nnz_extra)
+    assert missing > 0 and plan.info().nnz_extra == 3 * missing
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_triadic_config3_community_sizes(env, precision):
     """The config-3 recipe (sizes U[200, 2000], pairwise p_in 0.9 and inter
     degree 3, intra triples with p = 0.9, 3 cross triples per node on
@@ -158,4 +179,30 @@ def test_triadic_full_size_direct(env):
     err = rel_inf(got[rows], want)
     say("   rel_inf", err)
     assert err < 1e-5
+    plan.close()
+
+
+def test_triadic_full_size_cia(env):
+    """Config 3 at full size (N = 1e5, 91 communities of U[200, 2000], about
+    1e10 stored missing pairs built on the device): CIA against the oracle on
+    sampled rows, then RK4 steps stay finite."""
+    cia, torch = env
+    T = W.triadic(seed=3, n=100_000)
+    g = T.graph
+    plan = plan_for(cia, T, 0, 0)
+    info = plan.info()
+    say("config 3 CIA: n", g.n, "missing pairs", info.nnz_extra, "list GB", info.bytes_aux / 1e9)
+    th = torch.as_tensor(T.theta0, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(2).choice(g.n, 60, replace=False)
+    want = oracle.triadic_rhs(g.n, g.row_ptr, g.col, g.labels, T.tri_seed, T.p_tri, T.cross_tri, None, T.K1,
+                              T.K2, th.cpu().numpy().astype(np.float64), rows=rows)
+    err = rel_inf(got[rows], want)
+    say("   rel_inf", err)
+    assert err < 1e-5
+    plan.integrate(th, T.dt, 2)
+    assert torch.isfinite(th).all().item()
     plan.close()
