@@ -113,7 +113,12 @@ typedef struct cia_graph {
 /* Hypergraph of the triadic model.  A triple of distinct nodes inside one
    community is a hyperedge iff splitmix64(seed ^ key) < floor(p_intra * 2^64),
    key = a | b << 21 | c << 42 for the sorted user ids a < b < c (N < 2^21);
-   every other hyperedge is listed explicitly in `tri`. */
+   every other hyperedge is listed explicitly in `tri`.  The CIA method builds
+   the lists of missing intra-community triples on the device during
+   cia_build (16 bytes per up to seven partner pairs of a centre; about 23 GB
+   at N = 1e5 with communities of U[200, 2000] and p_intra = 0.9); a
+   community with missing triples may hold at most 8191 nodes (FP32) or 4095
+   (FP64), else cia_build returns CIA_EUNSUPPORTED. */
 typedef struct cia_hypergraph {
     uint64_t seed;
     double p_intra;            /* in [0, 1] */
@@ -329,7 +334,8 @@ typedef struct cia_plan_info {
     int32_t p;                /* phase: Fourier order; flock: Fourier order or learned rank */
     double bytes_per_rhs;     /* algorithmic HBM bytes of one RHS evaluation */
     double bytes_per_stage;   /* algorithmic HBM bytes of one fused RK stage launch */
-    int64_t nnz_extra;        /* model-specific remainder entries (triadic pair lists) */
+    int64_t nnz_extra;        /* model-specific remainder entries (triadic CIA: partner pairs of
+                                 missing intra-community triples, three per triple) */
     int32_t judge_fallbacks;  /* flock: communities currently on the exact fallback (read
                                  from the device; synchronises it) */
     int32_t reserved;
