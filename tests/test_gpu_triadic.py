@@ -206,3 +206,39 @@ def test_triadic_full_size_cia(env):
     plan.integrate(th, T.dt, 2)
     assert torch.isfinite(th).all().item()
     plan.close()
+
+
+@pytest.mark.parametrize("precision,lam", [(0, 8191), (1, 4095)])
+def test_triadic_largest_listed_community(env, precision, lam):
+    """One community of the largest size whose missing-pair lists fit 16-bit
+    LDS offsets (8191 nodes in FP32, 4095 in FP64), few missing triples:
+    CIA against the oracle on sampled rows."""
+    cia, torch = env
+    T = W.triadic(seed=9, n=lam, lo=lam, hi=lam, p_tri=0.999, tri_per_node=0.0)
+    g = T.graph
+    assert g.ncomm == 1
+    plan = plan_for(cia, T, 0, precision)
+    info = plan.info()
+    dt = torch.float64 if precision else torch.float32
+    th = torch.as_tensor(T.theta0, dtype=dt, device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(3).choice(g.n, 6, replace=False)
+    want = oracle.triadic_rhs(g.n, g.row_ptr, g.col, g.labels, T.tri_seed, T.p_tri, T.cross_tri, None, T.K1,
+                              T.K2, th.cpu().numpy().astype(np.float64), rows=rows)
+    err = rel_inf(got[rows], want)
+    say("community", lam, "precision", precision, "missing pairs", info.nnz_extra, "rel_inf", err)
+    assert info.nnz_extra > 0
+    assert err < (1e-12 if precision else 1e-5)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision,lam", [(0, 8192), (1, 4096)])
+def test_triadic_community_above_list_limit(env, precision, lam):
+    cia, torch = env
+    T = W.triadic(seed=9, n=lam, lo=lam, hi=lam, p_tri=0.999, tri_per_node=0.0)
+    with pytest.raises(cia.CIAError):
+        plan_for(cia, T, 0, precision)
+    assert "communities of up to %d nodes" % (lam - 1) in cia.cia_last_error()
