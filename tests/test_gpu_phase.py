@@ -230,6 +230,27 @@ def test_trajectory_fp32_scaled_large_config(env):
         plan.close()
 
 
+@pytest.mark.parametrize("recipe", ["config1", "config2_scaled"])
+def test_order_parameter_ten_time_units(env, recipe):
+    """FP32 on the GPU, RK4 dt 0.01 for 1000 steps (10 time units): r(t)
+    within 1e-3 of the FP64 oracle at every step, for CIA and direct."""
+    cia, torch = env
+    P = W.kuramoto_small() if recipe == "config1" else W.scaled_kuramoto(3000, seed=21, hi=300)
+    g = P.graph
+    steps = 1000
+    _, want_r = oracle.phase_integrate(g.n, g.row_ptr, g.col, P.omega, P.K, [0, 1], [0, 0], P.theta0, P.dt,
+                                       steps)
+    for method in (0, 1):
+        plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, method=method)
+        th = torch.as_tensor(P.theta0, dtype=torch.float32, device="cuda")
+        r = np.zeros(steps + 1)
+        plan.integrate(th, P.dt, steps, r)
+        dr = np.abs(r - want_r).max()
+        say("r(t) over 10 time units:", recipe, "n", g.n, "method", method, "max |dr|", dr)
+        assert dr < 1e-3
+        plan.close()
+
+
 def test_full_size_sampled_rows(env):
     """N = 1e6 power-law workload, the plans bench.py times: sampled rows of
     one RHS against the oracle computed row by row."""

@@ -242,3 +242,23 @@ def test_triadic_community_above_list_limit(env, precision, lam):
     with pytest.raises(cia.CIAError):
         plan_for(cia, T, 0, precision)
     assert "communities of up to %d nodes" % (lam - 1) in cia.cia_last_error()
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_triadic_graph_replay_matches_eager(env, method):
+    """The replayed RK4 step graph (pair-sum and stage launches captured
+    once) gives bitwise the eager result, over two integrate calls."""
+    cia, torch = env
+    T = W.triadic(seed=14, n=2500, lo=200, hi=600, tri_per_node=1.0)
+    g = T.graph
+    outs = []
+    for flags in (0, cia.CIA_FLAG_HIPGRAPH):
+        plan = cia.Plan.triadic(g.n, g.row_ptr, g.col, g.labels, T.omega, K1=T.K1, K2=T.K2, tri_seed=T.tri_seed,
+                                p_tri=T.p_tri, cross_tri=T.cross_tri, method=method, flags=flags)
+        th = torch.as_tensor(T.theta0, dtype=torch.float32, device="cuda")
+        r = np.zeros(2 * 21)
+        plan.integrate(th, T.dt, 20, r[:21])
+        plan.integrate(th, T.dt, 20, r[21:])
+        outs.append((th.cpu().numpy(), r))
+        plan.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
