@@ -228,37 +228,15 @@ __device__ __forceinline__ cx<R> zat(const cx<R> *zsh, uint32_t byte_off) {
     return cx<R>{v.x, v.y};
 }
 
-// Stream `w` chunks of one lane's row (stride 64 chunks, U per batch).
-// STAGED: 8 uint16 LDS byte offsets per chunk, one batch in flight (the LDS
-// gathers of a batch give enough independent work).  Otherwise 4 int32
-// global positions per chunk, double-buffered: batch j+1's loads are in
-// flight while batch j's partners are gathered, as z (GATHER_Z) or as theta
-// with z recomputed.
-template <typename R, int P, int U, bool STAGED, bool GATHER_Z>
+// Stream `w` chunks of one lane's row (stride 64 chunks, U per batch): 4
+// int32 global positions per chunk, double-buffered (batch j+1's loads are
+// in flight while batch j's partners are gathered), as z (GATHER_Z) or as
+// theta with z recomputed.
+template <typename R, int P, int U, bool GATHER_Z>
 __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restrict__ col, int w,
-                                            const cx<R> *zsh, const cx<R> *__restrict__ cs,
-                                            const R *__restrict__ th, uint32_t pad, R sign, uint4 padv) {
+                                            const cx<R> *__restrict__ cs, const R *__restrict__ th, uint32_t pad,
+                                            R sign, uint4 padv) {
     if (w <= 0) return;
-    if (STAGED) {
-        for (int k = 0; k < w; k += U) {
-            uint4 v[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) v[u] = k + u < w ? ld_stream(col + (size_t)(k + u) * SLICE) : padv;
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-                cx<R> z[8];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    z[2 * q] = zat(zsh, q4[q] & 0xffffu);
-                    z[2 * q + 1] = zat(zsh, q4[q] >> 16);
-                }
-#pragma unroll
-                for (int q = 0; q < 8; q++) acc_z<R, P>(T, z[q], sign);
-            }
-        }
-        return;
-    }
     uint4 v[U];
 #pragma unroll
     for (int u = 0; u < U; u++) v[u] = u < w ? ld_stream(col + (size_t)u * SLICE) : padv;
@@ -305,6 +283,60 @@ __device__ __forceinline__ void gather_rows(cx<R> (&T)[P], const uint4 *__restri
 #pragma unroll
         for (int u = 0; u < U; u++) v[u] = vn[u];
     }
+}
+
+// Staged rows: the S-neg chunks gathered from LDS and the S-pos chunks by
+// theta gathers, with the first S-pos batch's index loads issued beside the
+// S-neg loads and its theta gathers in flight while the LDS gathers run.
+template <typename R, int P, int UL, int UG>
+__device__ __forceinline__ void gather_staged_rows(cx<R> (&T)[P], const uint4 *__restrict__ neg, int wn,
+                                                   const uint4 *__restrict__ pos, int wp, const cx<R> *zsh,
+                                                   const cx<R> *__restrict__ cs, const R *__restrict__ th,
+                                                   uint32_t pad, uint4 padl, uint4 padp) {
+    uint4 nv[UL], pv[UG];
+#pragma unroll
+    for (int u = 0; u < UL; u++) nv[u] = u < wn ? ld_stream(neg + (size_t)u * SLICE) : padl;
+#pragma unroll
+    for (int u = 0; u < UG; u++) pv[u] = u < wp ? ld_stream(pos + (size_t)u * SLICE) : padp;
+    R t[UG][4];
+#pragma unroll
+    for (int u = 0; u < UG; u++) {
+        t[u][0] = th[pv[u].x];
+        t[u][1] = th[pv[u].y];
+        t[u][2] = th[pv[u].z];
+        t[u][3] = th[pv[u].w];
+    }
+    for (int k = 0; k < wn; k += UL) {
+        if (k > 0) {
+#pragma unroll
+            for (int u = 0; u < UL; u++) nv[u] = k + u < wn ? ld_stream(neg + (size_t)(k + u) * SLICE) : padl;
+        }
+#pragma unroll
+        for (int u = 0; u < UL; u++) {
+            const uint32_t q4[4] = {nv[u].x, nv[u].y, nv[u].z, nv[u].w};
+            cx<R> z[8];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                z[2 * q] = zat(zsh, q4[q] & 0xffffu);
+                z[2 * q + 1] = zat(zsh, q4[q] >> 16);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) acc_z<R, P>(T, z[q], (R)-1);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UG; u++) {
+        const uint32_t q4[4] = {pv[u].x, pv[u].y, pv[u].z, pv[u].w};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            R sn, c0;
+            dsincos(t[u][q], &sn, &c0);
+            const bool ok = q4[q] != pad;
+            acc_z<R, P>(T, cx<R>{ok ? c0 : (R)0, ok ? sn : (R)0}, (R)1);
+        }
+    }
+    if (wp > UG)
+        gather_rows<R, P, UG, false>(T, pos + (size_t)UG * SLICE, wp - UG, cs, th, pad, (R)1, padp);
 }
 
 // Stream a lane's list of partner pairs (j, k) and return sum z_j z_k:
@@ -442,13 +474,14 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
 #pragma unroll
         for (int k = 0; k < P; k++) T[k].x = T[k].y = (R)0;
         if (gather) {
-            if (!DIRECT) {
-                if (staged)
-                    gather_rows<R, P, UL, true, false>(T, a.negdata + S.beg[0] + lane, S.w[0], zsh, a.cs_in, a.th_in, a.pad_pos, (R)-1, padl);
-                else
-                    gather_rows<R, P, UG, false, false>(T, a.negdata + S.beg[0] + lane, S.w[0], zsh, a.cs_in, a.th_in, a.pad_pos, (R)-1, padp);
+            if (!DIRECT && staged) {
+                gather_staged_rows<R, P, UL, UG>(T, a.negdata + S.beg[0] + lane, S.w[0], a.posdata + S.beg[1] + lane,
+                                                 S.w[1], zsh, a.cs_in, a.th_in, a.pad_pos, padl, padp);
+            } else {
+                if (!DIRECT)
+                    gather_rows<R, P, UG, false>(T, a.negdata + S.beg[0] + lane, S.w[0], a.cs_in, a.th_in, a.pad_pos, (R)-1, padp);
+                gather_rows<R, P, UG, DIRECT>(T, a.posdata + S.beg[1] + lane, S.w[1], a.cs_in, a.th_in, a.pad_pos, (R)1, padp);
             }
-            gather_rows<R, P, UG, false, DIRECT>(T, a.posdata + S.beg[1] + lane, S.w[1], zsh, a.cs_in, a.th_in, a.pad_pos, (R)1, padp);
         }
         cx<R> Mt = {(R)0, (R)0}, Xt = {(R)0, (R)0};   // missing intra / cross hyperedge pair sums
         if (TRI && gather) {
