@@ -33,7 +33,7 @@ _vp = ctypes.c_void_p
 
 def build(force: bool = False) -> str:
     """Compile the oracle: gcc -O2, no fast-math (libm sin/cos, IEEE FP64)."""
-    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "basis.c")]
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "basis.c", "structured.c")]
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in srcs):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
@@ -91,6 +91,12 @@ def _load():
         lib.oracle_cs_rhs_separable.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, _vp, d, d, d,
                                                 ctypes.c_int, _vp, ctypes.c_int, d, _vp, ctypes.c_int,
                                                 _vp, _vp, _vp, _vp, _vp, i64, _vp, _vp]
+        lib.oracle_structured_rhs.restype = None
+        lib.oracle_structured_rhs.argtypes = [ctypes.c_int, i64, i64, _vp, _vp, _vp, d, ctypes.c_int, _vp,
+                                              _vp, _vp, _vp, i64, _vp]
+        lib.oracle_structured_integrate.restype = ctypes.c_int
+        lib.oracle_structured_integrate.argtypes = [ctypes.c_int, i64, i64, _vp, _vp, _vp, d, ctypes.c_int,
+                                                    _vp, _vp, _vp, d, i64, ctypes.c_int, _vp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -158,6 +164,51 @@ def phase_integrate(n, row_ptr, col, omega, K, d_sin, d_cos, theta0, dt, steps,
                                     1 if stepper == "euler" else 0, _p(r))
     if rc != 0:
         raise MemoryError("oracle_phase_integrate")
+    return th, r
+
+
+# ---------------------------------------------------------------------------
+# structured adjacency (App. B): rank one and the k-nearest-neighbour ring
+# ---------------------------------------------------------------------------
+
+def _structured_args(kind, n, k, alpha, beta):
+    if kind == "rank1":
+        alpha, beta = _f64(alpha), _f64(beta)
+        assert len(alpha) == n and len(beta) == n
+        return 0, 0, alpha, beta
+    assert kind == "ring" and k >= 0
+    return 1, int(k), None, None
+
+
+def structured_rhs(kind, n, omega, K, d_sin, d_cos, theta, k=0, alpha=None, beta=None, rows=None):
+    """H_m = omega_m + (K/N) sum_l a_ml h(theta_l - theta_m) with a_ml =
+    alpha_m beta_l ("rank1", App. B.1) or a_ml = [c_N(m, l) <= k] ("ring",
+    App. B.2); l = m included in both."""
+    lib = _load()
+    kd, kk, alpha, beta = _structured_args(kind, n, k, alpha, beta)
+    d_sin, d_cos = _f64(d_sin), _f64(d_cos)
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    out = np.empty(cnt, dtype=np.float64)
+    lib.oracle_structured_rhs(kd, int(n), kk, _p(alpha), _p(beta), _p(_f64(omega)), float(K), len(d_sin) - 1,
+                              _p(d_sin), _p(d_cos), _p(_f64(theta)), _p(rws), 0 if rws is None else len(rws),
+                              _p(out))
+    return out
+
+
+def structured_integrate(kind, n, omega, K, d_sin, d_cos, theta0, dt, steps, k=0, alpha=None, beta=None,
+                         stepper="rk4"):
+    """Returns (theta_final, r_trace).  No phase wrapping."""
+    lib = _load()
+    kd, kk, alpha, beta = _structured_args(kind, n, k, alpha, beta)
+    d_sin, d_cos = _f64(d_sin), _f64(d_cos)
+    th = np.array(theta0, dtype=np.float64, copy=True)
+    r = np.empty(steps + 1, dtype=np.float64)
+    rc = lib.oracle_structured_integrate(kd, int(n), kk, _p(alpha), _p(beta), _p(_f64(omega)), float(K),
+                                         len(d_sin) - 1, _p(d_sin), _p(d_cos), _p(th), float(dt), int(steps),
+                                         1 if stepper == "euler" else 0, _p(r))
+    if rc != 0:
+        raise MemoryError("oracle_structured_integrate")
     return th, r
 
 
