@@ -53,6 +53,10 @@ typedef enum cia_status {
 /* graph kinds */
 #define CIA_GRAPH_CSR 0       /* explicit symmetric adjacency in CSR form */
 #define CIA_GRAPH_COMPLETE 1  /* all-to-all: a_ml = 1 for l != m; nothing stored */
+#define CIA_GRAPH_RANK1 2     /* rank one (App. B.1): a_ml = alpha_m beta_l for every pair,
+                                 l = m included; nothing stored but alpha and beta */
+#define CIA_GRAPH_RING 3      /* k-nearest-neighbour ring (App. B.2): a_ml = 1 iff
+                                 min(|m-l|, N-|m-l|) <= ring_k, l = m included */
 
 /* models */
 #define CIA_MODEL_PHASE 0    /* theta_m' = omega_m + (K/N) sum_l a_ml h(theta_l - theta_m),
@@ -103,11 +107,15 @@ typedef enum cia_status {
 
 typedef struct cia_graph {
     int64_t n;                 /* number of nodes N >= 1 */
-    int32_t kind;              /* CIA_GRAPH_CSR or CIA_GRAPH_COMPLETE */
+    int32_t kind;              /* CIA_GRAPH_* */
     int32_t reserved;
     const int64_t *row_ptr;    /* host [n+1]; CSR only */
     const int32_t *col;        /* host [row_ptr[n]]; symmetric, rows strictly increasing,
                                   no self-loops; CSR only */
+    const double *alpha;       /* host [n], finite; CIA_GRAPH_RANK1 only (output weights) */
+    const double *beta;        /* host [n], finite; CIA_GRAPH_RANK1 only (input weights) */
+    int64_t ring_k;            /* CIA_GRAPH_RING only: half-width k >= 0 (k >= N/2 couples
+                                  every pair) */
 } cia_graph;
 
 /* Hypergraph of the triadic model.  A triple of distinct nodes inside one

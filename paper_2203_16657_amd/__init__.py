@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcia.so")
 
 # ---- constants (mirror of cia.h) ----
 CIA_OK, CIA_EINVAL, CIA_ENOMEM, CIA_EHIP, CIA_EUNSUPPORTED, CIA_ENONFINITE = 0, -1, -2, -3, -4, -5
-CIA_GRAPH_CSR, CIA_GRAPH_COMPLETE = 0, 1
+CIA_GRAPH_CSR, CIA_GRAPH_COMPLETE, CIA_GRAPH_RANK1, CIA_GRAPH_RING = 0, 1, 2, 3
 CIA_MODEL_PHASE, CIA_MODEL_TRIADIC, CIA_MODEL_FLOCK = 0, 1, 2
 CIA_METHOD_CIA, CIA_METHOD_DIRECT = 0, 1
 CIA_F32, CIA_F64 = 0, 1
@@ -36,7 +36,7 @@ _vp = ctypes.c_void_p
 
 class cia_graph(_c.Structure):
     _fields_ = [("n", _c.c_int64), ("kind", _c.c_int32), ("reserved", _c.c_int32),
-                ("row_ptr", _vp), ("col", _vp)]
+                ("row_ptr", _vp), ("col", _vp), ("alpha", _vp), ("beta", _vp), ("ring_k", _c.c_int64)]
 
 
 class cia_hypergraph(_c.Structure):
@@ -412,6 +412,37 @@ class Plan:
         o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
         o.unit_work, o.block, o.dense_alpha, o.device = unit_work, block, dense_alpha, device
         h = cia_build(g, labels, c, omega, o)
+        return cls(h, int(n), precision, CIA_MODEL_PHASE)
+
+    @classmethod
+    def structured(cls, n, kind, omega=None, K=1.0, d_sin=(0.0, 1.0), d_cos=(0.0, 0.0), alpha=None, beta=None,
+                   ring_k=0, method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4, flags=0, device=-1):
+        """Phase model on a structured adjacency (App. B): kind "rank1"
+        (a_ml = alpha_m beta_l) or "ring" (a_ml = 1 iff the circular distance
+        of m and l is at most ring_k); l = m is coupled in both."""
+        load()
+        al = be = None
+        if kind == "rank1":
+            al = np.ascontiguousarray(alpha, dtype=np.float64)
+            be = np.ascontiguousarray(beta, dtype=np.float64)
+            gk = CIA_GRAPH_RANK1
+        elif kind == "ring":
+            gk = CIA_GRAPH_RING
+        else:
+            raise ValueError("kind must be 'rank1' or 'ring'")
+        g = cia_graph(n=int(n), kind=gk, reserved=0, row_ptr=None, col=None, alpha=_np_ptr(al), beta=_np_ptr(be),
+                      ring_k=int(ring_k))
+        ds = np.ascontiguousarray(d_sin, dtype=np.float64)
+        dc = np.ascontiguousarray(d_cos, dtype=np.float64)
+        c = cia_coupling_default()
+        c.model = CIA_MODEL_PHASE
+        c.p = len(ds) - 1
+        c.d_sin = _np_ptr(ds)
+        c.d_cos = _np_ptr(dc)
+        c.K = float(K)
+        o = cia_options_default()
+        o.method, o.precision, o.stepper, o.flags, o.device = method, precision, stepper, flags, device
+        h = cia_build(g, None, c, omega, o)
         return cls(h, int(n), precision, CIA_MODEL_PHASE)
 
     @classmethod

@@ -71,6 +71,7 @@ static void free_plan(cia_plan *p) {
         if (q) (void)hipFree(q);
     phase_free(p);
     flock_free(p);
+    struct_free(p);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
     delete p;
 }
@@ -149,6 +150,7 @@ cia_status cia_build(const cia_graph *g, const int32_t *labels, const cia_coupli
     if (c->model != CIA_MODEL_PHASE && c->model != CIA_MODEL_TRIADIC && c->model != CIA_MODEL_FLOCK)
         return set_error(CIA_EINVAL, "coupling.model = %d", c->model);
     return make_plan(o, g->n, c->model, out, [&](cia_plan *p) -> cia_status {
+        if (g->kind == CIA_GRAPH_RANK1 || g->kind == CIA_GRAPH_RING) return struct_build(p, g, labels, c, omega, o);
         if (c->model == CIA_MODEL_FLOCK) return flock_build(p, g, labels, c, o);
         return phase_build(p, g, labels, c, omega, o);
     });
@@ -205,7 +207,8 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream) {
     CIA_TRY(select_device(p));
     hipStream_t s = static_cast<hipStream_t>(stream);
     cia_status st;
-    switch (p->model) {
+    switch (p->structd ? -1 : p->model) {
+        case -1: st = struct_rhs(p, state, dstate, s); break;
         case CIA_MODEL_PHASE:
         case CIA_MODEL_TRIADIC: st = phase_rhs(p, state, dstate, s); break;
         case CIA_MODEL_FLOCK: st = flock_rhs(p, state, dstate, s); break;
@@ -225,7 +228,8 @@ cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, dou
     CIA_TRY(select_device(p));
     hipStream_t s = static_cast<hipStream_t>(stream);
     cia_status st;
-    switch (p->model) {
+    switch (p->structd ? -1 : p->model) {
+        case -1: st = struct_integrate(p, state, dt, steps, r_trace, s); break;
         case CIA_MODEL_PHASE:
         case CIA_MODEL_TRIADIC: st = phase_integrate(p, state, dt, steps, r_trace, s); break;
         case CIA_MODEL_FLOCK:

@@ -1,0 +1,710 @@
+// Phase model on the structured adjacencies of App. B (extensions of step
+// E1): rank-one coupling a_ml = alpha_m beta_l (App. B.1) and the
+// k-nearest-neighbour ring a_ml = [min(|m-l|, N-|m-l|) <= k] (App. B.2), both
+// with l = m included, and h as its real Fourier series (App. A.2):
+//
+//   theta_m' = omega_m + (K/N) sum_l a_ml h(theta_l - theta_m).
+//
+// Each harmonic is treated on its own, as the paper suggests for h with
+// several modes.  Nodes stay in user order; a block owns a tile of STILE
+// consecutive nodes and writes FP64 tile sums of the next stage's z^k; a
+// one-block launch between stages turns them into totals (and, for the
+// ring, exclusive tile offsets), in a fixed order.
+//
+//  * rank one: R_k = sum_l beta_l z_l^k, then s_m = d0 sum beta +
+//    sum_k (dsin_k Im + dcos_k Re)(R_k conj(z_m^k)) and H_m = omega_m +
+//    (K/N) alpha_m s_m (eq. rank1fast);
+//  * ring: the window sum F_{m,k} = sum_{l=m-k}^{m+k} z_l^k (indices mod N)
+//    is Pc(m+k+1) - Pc(m-k) for the circular prefix sum Pc(x) =
+//    floor(x/N) Tot_k + sum_{l < x mod N} z_l^k.  The paper's serial window
+//    recurrence becomes, per block, two block scans over the block's two
+//    shifted windows started from the tile offsets.
+//
+// The direct variants sum h over every coupled pair (O(N^2) for rank one,
+// O(N k) for the ring) and share the stage update.
+#include <cmath>
+#include <cstring>
+
+#include "fastmath.h"
+#include "plan.h"
+
+namespace cia {
+
+namespace {
+
+constexpr int SB = 256;            // threads per stage block
+constexpr int SNPT = 4;            // consecutive nodes per thread
+constexpr int STILE = SB * SNPT;   // nodes per block
+constexpr int SPMAX = 8;           // harmonics
+constexpr int SCAN_T = 1024;       // threads of the scan launch
+
+enum SKind { SK_RANK1 = 0, SK_RING = 1, SK_RANK1_DIRECT = 2, SK_RING_DIRECT = 3 };
+enum SMode { SM_PREP = 0, SM_RHS = 1, SM_RK4 = 2, SM_EULER = 3 };
+
+template <typename R>
+struct zc {
+    R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ zc<R> zmul(zc<R> a, zc<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ zc<R> zpow(zc<R> z, int k) {
+    zc<R> r = z;
+    for (int i = 1; i < k; i++) r = zmul(r, z);
+    return r;
+}
+__device__ __forceinline__ void zsincos(float t, float *s, float *c) { fast_sincosf(t, s, c); }
+__device__ __forceinline__ void zsincos(double t, double *s, double *c) { sincos(t, s, c); }
+
+template <typename R>
+__device__ __forceinline__ R wrap_phase(R t);
+template <>
+__device__ __forceinline__ float wrap_phase<float>(float t) {
+    const float hi = 6.28318548202514648f;      // float(2 pi)
+    const float lo = -1.7484555314695172e-7f;   // 2 pi - float(2 pi)
+    const float k = floorf(t * 0.15915494309189535f);
+    float r = fmaf(-k, lo, fmaf(-k, hi, t));
+    if (r < 0.f) r += hi;
+    if (r >= hi) r -= hi;
+    return r;
+}
+template <>
+__device__ __forceinline__ double wrap_phase<double>(double t) {
+    const double twopi = 6.283185307179586;
+    double r = t - twopi * floor(t / twopi);
+    if (r < 0.0) r += twopi;
+    if (r >= twopi) r -= twopi;
+    return r;
+}
+
+__device__ __forceinline__ double2 d2add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Block sum of one double2 per thread (fixed order), broadcast to all threads.
+template <int NT>
+__device__ __forceinline__ double2 block_sum(double2 v, double2 *sh) {
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o);
+        v.y += __shfl_xor(v.y, o);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double2 r = sh[0];
+    for (int w = 1; w < NT / 64; w++) r = d2add(r, sh[w]);
+    return r;
+}
+
+// Exclusive scan of one double2 per thread in thread order (fixed order);
+// *total receives the block total.
+template <int NT>
+__device__ __forceinline__ double2 block_excl_scan(double2 v, double2 *sh, double2 *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double2 inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        double2 u;
+        u.x = __shfl_up(inc.x, o);
+        u.y = __shfl_up(inc.y, o);
+        if (lane >= o) inc = d2add(inc, u);
+    }
+    double2 ex;
+    ex.x = __shfl_up(inc.x, 1);
+    ex.y = __shfl_up(inc.y, 1);
+    if (lane == 0) ex = make_double2(0.0, 0.0);
+    __syncthreads();
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    double2 off = make_double2(0.0, 0.0), tot = make_double2(0.0, 0.0);
+    for (int w = 0; w < NT / 64; w++) {
+        if (w < wid) off = d2add(off, sh[w]);
+        tot = d2add(tot, sh[w]);
+    }
+    *total = tot;
+    return d2add(off, ex);
+}
+
+template <typename R>
+struct SArgs {
+    int64_t n, kw;                      // nodes; ring half-width
+    int32_t ntiles, mode, stage;
+    R dt, Kn, d0w;                      // d0w: dcos[0] times the row weight (sum beta, or 2 kw + 1)
+    R dsin[SPMAX + 1], dcos[SPMAX + 1];
+    const R *omega, *alpha, *beta;      // [n]; alpha, beta for rank one only
+    const R *state_in;                  // prep: theta in user order
+    R *state_out;                       // rhs: H
+    R *theta_n, *acc;                   // theta at the step start; RK4 accumulator
+    const zc<R> *z_in;                  // z of the current stage
+    zc<R> *z_out;                       // z of the next stage
+    const double2 *tot;                 // scan output: [P+1] totals, then ring tile offsets [(ntiles+1)][P]
+    double2 *part;                      // [ntiles][P+1]: tile sums of w z^k, k = 1..P, then of z
+};
+
+// Ring window sums for this thread's nodes j = a0 + SNPT t + e, harmonic by
+// harmonic, added into s as (dsin_k Im + dcos_k Re)(F_{j,k} conj(z_j^k)).
+template <typename R, int P>
+__device__ __forceinline__ void ring_windows(const SArgs<R> &a, int64_t a0, const zc<R> (&zj)[SNPT], R (&s)[SNPT],
+                                             double2 *sh) {
+    const int t = threadIdx.x;
+    const int64_t n = a.n, kw = a.kw;
+    const double2 *off = a.tot + (P + 1);
+    zc<R> zjk[SNPT];
+#pragma unroll
+    for (int e = 0; e < SNPT; e++) zjk[e] = zj[e];
+    for (int k = 1; k <= P; k++) {
+        const double2 Tot = off[(int64_t)a.ntiles * P + (k - 1)];
+        double2 pc[2][SNPT];
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int64_t st = r == 0 ? a0 - kw : a0 + kw + 1;
+            int64_t q = st / n;
+            if (st - q * n < 0) q -= 1;
+            const int64_t sp = st - q * n;   // in [0, n)
+            const int64_t tl = sp / STILE;
+            // sum of z^k over the start tile up to sp
+            double2 pt = make_double2(0.0, 0.0);
+            for (int64_t i = tl * STILE + t; i < sp; i += SB) {
+                const zc<R> z = zpow(a.z_in[i], k);
+                pt.x += (double)z.x;
+                pt.y += (double)z.y;
+            }
+            pt = block_sum<SB>(pt, sh);
+            const double2 o = off[tl * P + (k - 1)];
+            const double2 base = make_double2((double)q * Tot.x + o.x + pt.x, (double)q * Tot.y + o.y + pt.y);
+            // this thread's positions st + SNPT t + e, then a block scan
+            zc<R> v[SNPT];
+            double2 ts = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int e = 0; e < SNPT; e++) {
+                int64_t x = (st + (int64_t)SNPT * t + e) % n;
+                if (x < 0) x += n;
+                v[e] = zpow(a.z_in[x], k);
+                ts.x += (double)v[e].x;
+                ts.y += (double)v[e].y;
+            }
+            double2 btot;
+            double2 run = d2add(base, block_excl_scan<SB>(ts, sh, &btot));
+#pragma unroll
+            for (int e = 0; e < SNPT; e++) {
+                pc[r][e] = run;
+                run.x += (double)v[e].x;
+                run.y += (double)v[e].y;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < SNPT; e++) {
+            const R fx = (R)(pc[1][e].x - pc[0][e].x), fy = (R)(pc[1][e].y - pc[0][e].y);
+            // F conj(z_j^k)
+            const R wr = fx * zjk[e].x + fy * zjk[e].y, wi = fy * zjk[e].x - fx * zjk[e].y;
+            s[e] += a.dsin[k] * wi + a.dcos[k] * wr;
+            zjk[e] = zmul(zjk[e], zj[e]);
+        }
+    }
+}
+
+// h(theta_l - theta_j) from z_l and z_j (powers by recurrence)
+template <typename R, int P>
+__device__ __forceinline__ R h_pair(const SArgs<R> &a, zc<R> zl, zc<R> zj) {
+    // e^{i(theta_l - theta_j)} = z_l conj(z_j)
+    const zc<R> d = {zl.x * zj.x + zl.y * zj.y, zl.y * zj.x - zl.x * zj.y};
+    R v = a.dcos[0];
+    zc<R> dk = d;
+#pragma unroll
+    for (int k = 1; k <= P; k++) {
+        v += a.dsin[k] * dk.y + a.dcos[k] * dk.x;
+        if (k < P) dk = zmul(dk, d);
+    }
+    return v;
+}
+
+template <typename R, int P, int KIND>
+__global__ __launch_bounds__(SB) void struct_stage_kernel(SArgs<R> a) {
+    constexpr bool RANK1 = KIND == SK_RANK1 || KIND == SK_RANK1_DIRECT;
+    __shared__ double2 sh[SB / 64];
+    __shared__ zc<R> zst[SB];
+    __shared__ R bst[SB];
+    const int t = threadIdx.x;
+    const int64_t n = a.n;
+    const int64_t a0 = (int64_t)blockIdx.x * STILE;
+    const int64_t j0 = a0 + (int64_t)SNPT * t;
+    const int mode = a.mode;
+
+    R tn[SNPT], om[SNPT], av[SNPT], s[SNPT];
+    zc<R> zj[SNPT];
+#pragma unroll
+    for (int e = 0; e < SNPT; e++) {
+        const int64_t j = j0 + e;
+        const bool ok = j < n;
+        tn[e] = om[e] = av[e] = s[e] = (R)0;
+        zj[e] = zc<R>{(R)0, (R)0};
+        if (!ok) continue;
+        if (mode == SM_PREP) {
+            tn[e] = a.state_in[j];
+        } else {
+            if (mode != SM_RHS) tn[e] = a.theta_n[j];
+            if (a.omega) om[e] = a.omega[j];
+            if (mode == SM_RK4 && a.stage > 0) av[e] = a.acc[j];
+            zj[e] = a.z_in[j];
+        }
+    }
+
+    if (mode != SM_PREP) {
+        // ---- s_j = sum_l a_jl h(theta_l - theta_j), without the factor alpha_j ----
+        if constexpr (KIND == SK_RANK1) {
+            zc<R> zk[SNPT];
+#pragma unroll
+            for (int e = 0; e < SNPT; e++) {
+                s[e] = a.d0w;
+                zk[e] = zj[e];
+            }
+#pragma unroll
+            for (int k = 1; k <= P; k++) {
+                const double2 Rk = a.tot[k - 1];
+                const R rx = (R)Rk.x, ry = (R)Rk.y;
+#pragma unroll
+                for (int e = 0; e < SNPT; e++) {
+                    const R wr = rx * zk[e].x + ry * zk[e].y, wi = ry * zk[e].x - rx * zk[e].y;
+                    s[e] += a.dsin[k] * wi + a.dcos[k] * wr;
+                    if (k < P) zk[e] = zmul(zk[e], zj[e]);
+                }
+            }
+        } else if constexpr (KIND == SK_RING) {
+#pragma unroll
+            for (int e = 0; e < SNPT; e++) s[e] = a.d0w;
+            ring_windows<R, P>(a, a0, zj, s, sh);
+        } else if constexpr (KIND == SK_RANK1_DIRECT) {
+            // every partner l, staged SB at a time; FP32 sums per stage chunk, FP64 across
+            double sd[SNPT] = {0.0, 0.0, 0.0, 0.0};
+            for (int64_t l0 = 0; l0 < n; l0 += SB) {
+                __syncthreads();
+                const int64_t l = l0 + t;
+                zst[t] = l < n ? a.z_in[l] : zc<R>{(R)0, (R)0};
+                bst[t] = l < n ? a.beta[l] : (R)0;
+                __syncthreads();
+                const int cnt = (int)(n - l0 < SB ? n - l0 : SB);
+                R sf[SNPT] = {(R)0, (R)0, (R)0, (R)0};
+                for (int u = 0; u < cnt; u++) {
+                    const zc<R> zl = zst[u];
+                    const R b = bst[u];
+#pragma unroll
+                    for (int e = 0; e < SNPT; e++) sf[e] += b * h_pair<R, P>(a, zl, zj[e]);
+                }
+#pragma unroll
+                for (int e = 0; e < SNPT; e++) sd[e] += (double)sf[e];
+            }
+#pragma unroll
+            for (int e = 0; e < SNPT; e++) s[e] = (R)sd[e];
+        } else {
+            // ring, direct: the 2 kw + 1 partners of each node (2 kw + 1 < n)
+#pragma unroll
+            for (int e = 0; e < SNPT; e++) {
+                const int64_t j = j0 + e;
+                if (j >= n) continue;
+                double sd = 0.0;
+                for (int64_t d0 = -a.kw; d0 <= a.kw; d0 += SB) {
+                    const int64_t d1 = d0 + SB - 1 < a.kw ? d0 + SB - 1 : a.kw;
+                    R sf = (R)0;
+                    for (int64_t d = d0; d <= d1; d++) {
+                        int64_t l = (j + d) % n;
+                        if (l < 0) l += n;
+                        sf += h_pair<R, P>(a, a.z_in[l], zj[e]);
+                    }
+                    sd += (double)sf;
+                }
+                s[e] = (R)sd;
+            }
+        }
+    }
+
+    // ---- combine, stage update, next z and its tile sums ----
+    R tnew[SNPT];
+#pragma unroll
+    for (int e = 0; e < SNPT; e++) {
+        const int64_t j = j0 + e;
+        tnew[e] = (R)0;
+        if (j >= n) continue;
+        if (mode == SM_PREP) {
+            tnew[e] = tn[e];
+            a.theta_n[j] = tn[e];
+            continue;
+        }
+        const R w = RANK1 ? a.alpha[j] : (R)1;
+        const R H = om[e] + a.Kn * w * s[e];
+        if (mode == SM_RHS) {
+            a.state_out[j] = H;
+        } else if (mode == SM_EULER) {
+            tnew[e] = wrap_phase<R>(tn[e] + a.dt * H);
+            a.theta_n[j] = tnew[e];
+        } else if (a.stage == 0) {
+            a.acc[j] = H;
+            tnew[e] = tn[e] + (R)0.5 * a.dt * H;
+        } else if (a.stage == 1) {
+            a.acc[j] = av[e] + (R)2 * H;
+            tnew[e] = tn[e] + (R)0.5 * a.dt * H;
+        } else if (a.stage == 2) {
+            a.acc[j] = av[e] + (R)2 * H;
+            tnew[e] = tn[e] + a.dt * H;
+        } else {
+            tnew[e] = wrap_phase<R>(tn[e] + a.dt / (R)6 * (av[e] + H));
+            a.theta_n[j] = tnew[e];
+        }
+    }
+    if (mode == SM_RHS) return;
+    zc<R> zn[SNPT];
+    R wt[SNPT];
+#pragma unroll
+    for (int e = 0; e < SNPT; e++) {
+        const int64_t j = j0 + e;
+        zn[e] = zc<R>{(R)0, (R)0};
+        wt[e] = (R)0;
+        if (j >= n) continue;
+        R sn, c0;
+        zsincos(tnew[e], &sn, &c0);
+        zn[e] = zc<R>{c0, sn};
+        a.z_out[j] = zn[e];
+        wt[e] = (KIND == SK_RANK1) ? a.beta[j] : (R)1;
+    }
+    // tile sums: slot k-1 of w z^k (k = 1..P; the E1 variants), slot P of z
+    if constexpr (KIND == SK_RANK1 || KIND == SK_RING) {
+        zc<R> zk[SNPT];
+#pragma unroll
+        for (int e = 0; e < SNPT; e++) zk[e] = zn[e];
+        for (int k = 1; k <= P; k++) {
+            double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int e = 0; e < SNPT; e++) {
+                v.x += (double)(wt[e] * zk[e].x);
+                v.y += (double)(wt[e] * zk[e].y);
+            }
+            v = block_sum<SB>(v, sh);
+            if (t == 0) a.part[(size_t)blockIdx.x * (P + 1) + (k - 1)] = v;
+            if (k < P) {
+#pragma unroll
+                for (int e = 0; e < SNPT; e++) zk[e] = zmul(zk[e], zn[e]);
+            }
+        }
+    }
+    double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int e = 0; e < SNPT; e++) {
+        v.x += (double)zn[e].x;
+        v.y += (double)zn[e].y;
+    }
+    v = block_sum<SB>(v, sh);
+    if (t == 0) a.part[(size_t)blockIdx.x * (P + 1) + P] = v;
+}
+
+// Totals of the tile sums (every slot) and, for the ring, exclusive tile
+// offsets of slots 0..P-1; r_out (optional) = |total of slot P| / n.  One
+// block; each thread owns a contiguous run of tiles, so the order is fixed.
+__global__ __launch_bounds__(SCAN_T) void struct_scan_kernel(const double2 *part, int32_t ntiles, int P, int ring,
+                                                             double invN, double2 *tot, double *r_out) {
+    __shared__ double2 sh[SCAN_T / 64];
+    const int t = threadIdx.x;
+    const int64_t per = ((int64_t)ntiles + SCAN_T - 1) / SCAN_T;
+    const int64_t b = per * t, e = b + per < ntiles ? b + per : ntiles;
+    double2 *off = tot + (P + 1);
+    for (int sl = 0; sl <= P; sl++) {
+        double2 v = make_double2(0.0, 0.0);
+        for (int64_t i = b; i < e; i++) v = d2add(v, part[i * (P + 1) + sl]);
+        double2 total;
+        double2 run = block_excl_scan<SCAN_T>(v, sh, &total);
+        if (t == 0) {
+            tot[sl] = total;
+            if (sl == P && r_out) r_out[0] = sqrt(total.x * total.x + total.y * total.y) * invN;
+        }
+        if (ring && sl < P) {
+            for (int64_t i = b; i < e; i++) {
+                off[i * P + sl] = run;
+                run = d2add(run, part[i * (P + 1) + sl]);
+            }
+            if (t == 0) off[(int64_t)ntiles * P + sl] = total;
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct StructState {
+    int kind = SK_RANK1;
+    int P = 1;
+    bool f64 = false;
+    double Kn = 0, d0w = 0;
+    double dsin[SPMAX + 1] = {0}, dcos[SPMAX + 1] = {0};
+    int64_t kw = 0;
+    int32_t ntiles = 0;
+    void *omega = nullptr, *alpha = nullptr, *beta = nullptr;
+    void *theta_n = nullptr, *acc = nullptr, *z[2] = {nullptr, nullptr};
+    double2 *part[2] = {nullptr, nullptr};
+    double2 *tot = nullptr;
+    double *r_dev = nullptr;
+    int64_t r_cap = 0;
+};
+
+template <typename R>
+static cia_status upload_as(cia_plan *p, void **dst, const double *src, int64_t n) {
+    std::vector<R> h(n);
+    for (int64_t i = 0; i < n; i++) h[i] = (R)src[i];
+    R *d;
+    CIA_TRY(dupload(p, &d, h.data(), (size_t)n));
+    *dst = d;
+    return CIA_OK;
+}
+
+cia_status struct_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
+                        const double *omega, const cia_options *o) {
+    if (c->model != CIA_MODEL_PHASE)
+        return set_error(CIA_EUNSUPPORTED, "rank-one and ring graphs take the phase model only");
+    if (labels) return set_error(CIA_EINVAL, "rank-one and ring graphs take no community labels (pass NULL)");
+    if (c->p < 1 || c->p > SPMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, SPMAX);
+    if (!c->d_sin || !c->d_cos) return set_error(CIA_EINVAL, "coupling.d_sin/d_cos are NULL");
+    for (int k = 0; k <= c->p; k++)
+        if (!std::isfinite(c->d_sin[k]) || !std::isfinite(c->d_cos[k]))
+            return set_error(CIA_EINVAL, "coupling coefficients must be finite");
+    const int64_t n = g->n;
+    if (n > ((int64_t)1 << 40)) return set_error(CIA_EUNSUPPORTED, "n = %lld is too large", (long long)n);
+    StructState *s = new (std::nothrow) StructState();
+    if (!s) return set_error(CIA_ENOMEM, "host allocation failed");
+    p->structd = s;
+    s->f64 = o->precision == CIA_F64;
+    s->P = c->p;
+    for (int k = 0; k <= c->p; k++) {
+        s->dsin[k] = c->d_sin[k];
+        s->dcos[k] = c->d_cos[k];
+    }
+    s->Kn = c->K / (double)n;
+    if (!std::isfinite(s->Kn)) return set_error(CIA_EINVAL, "coupling.K is not finite");
+    if (omega)
+        for (int64_t i = 0; i < n; i++)
+            if (!std::isfinite(omega[i])) return set_error(CIA_EINVAL, "omega[%lld] is not finite", (long long)i);
+
+    // rank one, or a ring; a ring of 2k + 1 >= n couples every pair (rank one
+    // with unit weights)
+    std::vector<double> ones;
+    const double *alpha = g->alpha, *beta = g->beta;
+    bool rank1 = g->kind == CIA_GRAPH_RANK1;
+    if (g->kind == CIA_GRAPH_RING) {
+        if (g->ring_k < 0) return set_error(CIA_EINVAL, "graph.ring_k = %lld < 0", (long long)g->ring_k);
+        s->kw = g->ring_k;
+        if (2 * g->ring_k + 1 >= n || g->ring_k >= n) {
+            rank1 = true;
+            ones.assign(n, 1.0);
+            alpha = beta = ones.data();
+        }
+    }
+    if (rank1) {
+        if (!alpha || !beta) return set_error(CIA_EINVAL, "rank-one graph: alpha/beta is NULL");
+        double sb = 0.0;
+        for (int64_t i = 0; i < n; i++) {
+            if (!std::isfinite(alpha[i]) || !std::isfinite(beta[i]))
+                return set_error(CIA_EINVAL, "rank-one graph: alpha/beta[%lld] is not finite", (long long)i);
+            sb += beta[i];
+        }
+        s->d0w = c->d_cos[0] * sb;
+        s->kind = o->method == CIA_METHOD_DIRECT ? SK_RANK1_DIRECT : SK_RANK1;
+    } else {
+        s->d0w = c->d_cos[0] * (double)(2 * s->kw + 1);
+        s->kind = o->method == CIA_METHOD_DIRECT ? SK_RING_DIRECT : SK_RING;
+    }
+    const int64_t ntiles = (n + STILE - 1) / STILE;
+    if (ntiles > INT32_MAX) return set_error(CIA_EUNSUPPORTED, "n = %lld is too large", (long long)n);
+    s->ntiles = (int32_t)ntiles;
+
+    const size_t rs = s->f64 ? sizeof(double) : sizeof(float);
+    if (s->f64) {
+        if (omega) CIA_TRY(upload_as<double>(p, &s->omega, omega, n));
+        if (rank1) {
+            CIA_TRY(upload_as<double>(p, &s->alpha, alpha, n));
+            CIA_TRY(upload_as<double>(p, &s->beta, beta, n));
+        }
+    } else {
+        if (omega) CIA_TRY(upload_as<float>(p, &s->omega, omega, n));
+        if (rank1) {
+            CIA_TRY(upload_as<float>(p, &s->alpha, alpha, n));
+            CIA_TRY(upload_as<float>(p, &s->beta, beta, n));
+        }
+    }
+    unsigned char *raw;
+    CIA_TRY(dalloc(p, &raw, rs * n));
+    s->theta_n = raw;
+    CIA_TRY(dalloc(p, &raw, rs * n));
+    s->acc = raw;
+    for (int b = 0; b < 2; b++) {
+        CIA_TRY(dalloc(p, &raw, 2 * rs * n));
+        s->z[b] = raw;
+        CIA_TRY(dalloc(p, &s->part[b], (size_t)ntiles * (s->P + 1)));
+        CIA_HIP(hipMemset(s->part[b], 0, sizeof(double2) * (size_t)ntiles * (s->P + 1)));
+    }
+    CIA_TRY(dalloc(p, &s->tot, (size_t)(s->P + 1) + (size_t)(ntiles + 1) * s->P));
+
+    cia_plan_info &inf = p->info;
+    inf.n = n;
+    inf.nnz_graph = rank1 ? n * n : n * (2 * s->kw + 1);
+    inf.method = o->method;
+    inf.precision = o->precision;
+    inf.model = CIA_MODEL_PHASE;
+    inf.p = s->P;
+    inf.nunits = s->ntiles;
+    inf.ncomm = 1;
+    inf.max_comm = (int32_t)std::min<int64_t>(n, INT32_MAX);
+    // algorithmic bytes per node: theta_n, omega, acc in and out, z read and
+    // written once, and for rank one alpha and beta
+    const double per_node = (4.0 + 2.0 * 2.0) * rs + (rank1 ? 2.0 * rs : 0.0);
+    inf.bytes_per_stage = per_node * (double)n;
+    inf.bytes_per_rhs = (4.0 * rs + 2.0 * rs + (rank1 ? 2.0 * rs : 0.0)) * (double)n;
+    return CIA_OK;
+}
+
+void struct_free(cia_plan *p) {
+    delete p->structd;
+    p->structd = nullptr;
+}
+
+template <typename R, int P>
+static void launch_stage_kind(const StructState *s, const SArgs<R> &a, hipStream_t st) {
+    const dim3 g(s->ntiles), b(SB);
+    switch (s->kind) {
+        case SK_RANK1: hipLaunchKernelGGL((struct_stage_kernel<R, P, SK_RANK1>), g, b, 0, st, a); break;
+        case SK_RING: hipLaunchKernelGGL((struct_stage_kernel<R, P, SK_RING>), g, b, 0, st, a); break;
+        case SK_RANK1_DIRECT: hipLaunchKernelGGL((struct_stage_kernel<R, P, SK_RANK1_DIRECT>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((struct_stage_kernel<R, P, SK_RING_DIRECT>), g, b, 0, st, a); break;
+    }
+}
+
+template <typename R>
+static cia_status launch_stage(cia_plan *p, const StructState *s, const SArgs<R> &a, hipStream_t st, int kind) {
+    CIA_TRY(timing_begin(p, st, kind));
+    switch (s->P) {
+        case 1: launch_stage_kind<R, 1>(s, a, st); break;
+        case 2: launch_stage_kind<R, 2>(s, a, st); break;
+        case 3: launch_stage_kind<R, 3>(s, a, st); break;
+        case 4: launch_stage_kind<R, 4>(s, a, st); break;
+        case 5: launch_stage_kind<R, 5>(s, a, st); break;
+        case 6: launch_stage_kind<R, 6>(s, a, st); break;
+        case 7: launch_stage_kind<R, 7>(s, a, st); break;
+        default: launch_stage_kind<R, 8>(s, a, st); break;
+    }
+    CIA_HIP(hipGetLastError());
+    return timing_end(p, st);
+}
+
+// totals / offsets of the tile sums in part[b]; r_out optional
+static cia_status launch_scan(cia_plan *p, const StructState *s, int b, double *r_out, hipStream_t st) {
+    CIA_TRY(timing_begin(p, st, KK_AUX));
+    hipLaunchKernelGGL(struct_scan_kernel, dim3(1), dim3(SCAN_T), 0, st, s->part[b], s->ntiles, s->P,
+                       s->kind == SK_RING ? 1 : 0, 1.0 / (double)p->n, s->tot, r_out);
+    CIA_HIP(hipGetLastError());
+    return timing_end(p, st);
+}
+
+template <typename R>
+static SArgs<R> base_args(cia_plan *p, const StructState *s) {
+    SArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = p->n;
+    a.kw = s->kw;
+    a.ntiles = s->ntiles;
+    a.Kn = (R)s->Kn;
+    a.d0w = (R)s->d0w;
+    for (int k = 0; k <= SPMAX; k++) {
+        a.dsin[k] = (R)s->dsin[k];
+        a.dcos[k] = (R)s->dcos[k];
+    }
+    a.omega = static_cast<const R *>(s->omega);
+    a.alpha = static_cast<const R *>(s->alpha);
+    a.beta = static_cast<const R *>(s->beta);
+    a.theta_n = static_cast<R *>(s->theta_n);
+    a.acc = static_cast<R *>(s->acc);
+    a.tot = s->tot;
+    return a;
+}
+
+template <typename R>
+static cia_status prep(cia_plan *p, const StructState *s, const void *state, hipStream_t st) {
+    SArgs<R> a = base_args<R>(p, s);
+    a.mode = SM_PREP;
+    a.state_in = static_cast<const R *>(state);
+    a.z_out = static_cast<zc<R> *>(s->z[0]);
+    a.part = s->part[0];
+    return launch_stage<R>(p, s, a, st, KK_PREP);
+}
+
+static bool needs_scan(const StructState *s) { return s->kind == SK_RANK1 || s->kind == SK_RING; }
+
+template <typename R>
+static cia_status rhs_impl(cia_plan *p, StructState *s, const void *state, void *dstate, hipStream_t st) {
+    CIA_TRY(prep<R>(p, s, state, st));
+    if (needs_scan(s)) CIA_TRY(launch_scan(p, s, 0, nullptr, st));
+    SArgs<R> a = base_args<R>(p, s);
+    a.mode = SM_RHS;
+    a.z_in = static_cast<const zc<R> *>(s->z[0]);
+    a.state_out = static_cast<R *>(dstate);
+    return launch_stage<R>(p, s, a, st, KK_STAGE);
+}
+
+template <typename R>
+static cia_status integrate_impl(cia_plan *p, StructState *s, void *state, double dt, int64_t steps,
+                                 double *r_trace, hipStream_t st) {
+    const bool want_r = r_trace != nullptr;
+    if (want_r && s->r_cap < steps + 1) {
+        if (s->r_dev) {
+            CIA_HIP(hipFree(s->r_dev));
+            for (auto &q : p->dev_allocs)
+                if (q == s->r_dev) q = nullptr;
+            s->r_dev = nullptr;
+        }
+        CIA_TRY(dalloc(p, &s->r_dev, (size_t)(steps + 1)));
+        s->r_cap = steps + 1;
+    }
+    const bool rk4 = p->stepper == CIA_RK4;
+    CIA_TRY(prep<R>(p, s, state, st));
+    int cur = 0;
+    for (int64_t k = 0; k < steps; k++) {
+        const int nst = rk4 ? 4 : 1;
+        for (int q = 0; q < nst; q++) {
+            // the scan before a step's first stage also gives r(t_k)
+            double *r_out = want_r && q == 0 ? s->r_dev + k : nullptr;
+            if (needs_scan(s) || r_out) CIA_TRY(launch_scan(p, s, cur, r_out, st));
+            SArgs<R> a = base_args<R>(p, s);
+            a.mode = rk4 ? SM_RK4 : SM_EULER;
+            a.stage = q;
+            a.dt = (R)dt;
+            a.z_in = static_cast<const zc<R> *>(s->z[cur]);
+            a.z_out = static_cast<zc<R> *>(s->z[cur ^ 1]);
+            a.part = s->part[cur ^ 1];
+            CIA_TRY(launch_stage<R>(p, s, a, st, KK_STAGE));
+            cur ^= 1;
+        }
+    }
+    if (want_r) CIA_TRY(launch_scan(p, s, cur, s->r_dev + steps, st));
+    CIA_HIP(hipMemcpyAsync(state, s->theta_n, (s->f64 ? sizeof(double) : sizeof(float)) * (size_t)p->n,
+                           hipMemcpyDeviceToDevice, st));
+    if (want_r) {
+        CIA_HIP(hipMemcpyAsync(r_trace, s->r_dev, sizeof(double) * (size_t)(steps + 1), hipMemcpyDeviceToHost, st));
+        CIA_HIP(hipStreamSynchronize(st));
+        for (int64_t k = 0; k <= steps; k++)
+            if (!std::isfinite(r_trace[k]))
+                return set_error(CIA_ENONFINITE, "state became non-finite (r(t_%lld) = %g)", (long long)k,
+                                 r_trace[k]);
+    }
+    return CIA_OK;
+}
+
+cia_status struct_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t st) {
+    StructState *s = p->structd;
+    return s->f64 ? rhs_impl<double>(p, s, state, dstate, st) : rhs_impl<float>(p, s, state, dstate, st);
+}
+
+cia_status struct_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace, hipStream_t st) {
+    StructState *s = p->structd;
+    return s->f64 ? integrate_impl<double>(p, s, state, dt, steps, r_trace, st)
+                  : integrate_impl<float>(p, s, state, dt, steps, r_trace, st);
+}
+
+}  // namespace cia

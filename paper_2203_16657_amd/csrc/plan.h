@@ -13,6 +13,7 @@ enum KernelKind { KK_STAGE = 0, KK_PREP = 1, KK_AUX = 2 };
 struct PhaseState;
 struct TriadicState;
 struct FlockState;
+struct StructState;
 
 }  // namespace cia
 
@@ -44,6 +45,7 @@ struct cia_plan {
     cia::PhaseState *phase = nullptr;
     cia::TriadicState *tri = nullptr;
     cia::FlockState *flock = nullptr;
+    cia::StructState *structd = nullptr;   // rank-one and ring graphs (App. B)
 };
 
 namespace cia {
@@ -95,6 +97,13 @@ cia_status phase_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t s
 cia_status phase_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
                            hipStream_t s);
 void phase_free(cia_plan *p);
+
+// Phase model on the structured adjacencies of App. B (rank one, ring).
+cia_status struct_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
+                        const double *omega, const cia_options *o);
+cia_status struct_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t s);
+cia_status struct_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace, hipStream_t s);
+void struct_free(cia_plan *p);
 
 // flock model (cia_flock.hip)
 cia_status flock_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
