@@ -78,7 +78,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble", "triadic"],
+    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble", "triadic", "structured"],
                     help="large: the N = 1e6 Kuramoto bench line; flock, ensemble and triadic: the "
                          "Cucker-Smale, batched-ensemble and higher-order workloads (measurement modes, "
                          "not the bench line)")
@@ -132,6 +132,8 @@ def main():
         return bench_flock(args, cia, W, torch, np)
     if args.workload == "ensemble":
         return bench_ensemble(args, cia, W, torch, np)
+    if args.workload == "structured":
+        return bench_structured(args, cia, W, torch, np)
     if args.workload == "triadic":
         return bench_triadic(args, cia, W, torch, np)
 
@@ -410,6 +412,62 @@ def bench_triadic(args, cia, W, torch, np):
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                            "traffic": None}
     print(json.dumps(out), flush=True)
+
+
+def bench_structured(args, cia, W, torch, np):
+    """Phase model on the structured adjacencies of App. B, FP32, RK4: rank-one
+    coupling and the k-nearest-neighbour ring with k = N/10 at N = 1e7 (E1
+    only: O(N) per stage for any k), then CIA against the direct method at
+    N = 1e5 (ring k = 1e4; rank one, O(N^2) direct)."""
+    rng = np.random.default_rng(31)
+
+    def make(n, kind, k, method):
+        om = rng.standard_normal(n)
+        kw = dict(alpha=rng.uniform(0.5, 1.5, n), beta=rng.uniform(0.5, 1.5, n)) if kind == "rank1" else dict(ring_k=k)
+        return cia.Plan.structured(n, kind, om, K=2.0, method=method, **kw)
+
+    def run(n, kind, k, method, steps):
+        plan = make(n, kind, k, method)
+        info = plan.info()
+        th0 = rng.uniform(0, 2 * np.pi, n).astype(np.float32)
+        th = torch.as_tensor(th0, device="cuda")
+        plan.integrate(th, 0.01, 2)
+        plan.set_timing(1)
+        plan.timing(reset=True)
+        ms = timed(torch, lambda s: plan.integrate(th, 0.01, steps, stream=s))
+        t = plan.timing(reset=True)
+        stage_us = 1e3 * t.stage_ms / max(t.stage_launches, 1)
+        res = {"n": n, "kind": kind, "k": k, "method": "cia" if method == 0 else "direct", "steps": steps,
+               "ms_per_step": ms / steps, "value": n * 4 * steps / (ms / 1e3), "stage_us": round(stage_us, 2),
+               "scan_us": round(1e3 * t.aux_ms / max(t.aux_launches, 1), 2),
+               "bytes_per_stage": info.bytes_per_stage}
+        if method == 0:
+            gbs = info.bytes_per_stage / (stage_us * 1e-6) / 1e9
+            res["roofline"] = {"kernel": "struct_stage_kernel", "bound": "hbm", "achieved": round(gbs, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                               "traffic": None}
+        log("%-6s %-6s n=%d k=%d: %.4f ms/step, stage %.2f us, scan %.2f us" % (
+            kind, res["method"], n, k, res["ms_per_step"], stage_us, res["scan_us"]))
+        plan.close()
+        return res
+
+    big = int(1e7)
+    out = {"rank1": run(big, "rank1", 0, 0, 50), "ring": run(big, "ring", big // 10, 0, 50)}
+    small = int(1e5)
+    cmp = {}
+    for kind, k in (("rank1", 0), ("ring", small // 10)):
+        a = run(small, kind, k, 0, 50)
+        b = run(small, kind, k, 1, 3)
+        cmp[kind] = {"cia": a, "direct": b, "speedup": b["ms_per_step"] / a["ms_per_step"]}
+    line = {
+        "metric": "structured-adjacency RHS node-updates/s (ring, k = N/10), 1 MI355X",
+        "value": out["ring"]["value"], "unit": "RHS node-updates/s", "n_gpus": 1, "steps": 50, "warmup": 2,
+        "ms_per_step": out["ring"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "structured_ring_n1e7_k1e6", "n": big, "stepper": "rk4", "dt": 0.01},
+        "roofline": out["ring"]["roofline"], "large": out, "vs_direct_n1e5": cmp,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -33,10 +33,10 @@ namespace cia {
 namespace {
 
 constexpr int SB = 256;            // threads per stage block
-constexpr int SNPT = 4;            // consecutive nodes per thread
+constexpr int SNPT = 4;            // consecutive nodes per thread (the vector helpers take 4)
 constexpr int STILE = SB * SNPT;   // nodes per block
 constexpr int SPMAX = 8;           // harmonics
-constexpr int SCAN_T = 1024;       // threads of the scan launch
+constexpr int SCAN_T = 256;        // threads of the scan launch
 
 enum SKind { SK_RANK1 = 0, SK_RING = 1, SK_RANK1_DIRECT = 2, SK_RING_DIRECT = 3 };
 enum SMode { SM_PREP = 0, SM_RHS = 1, SM_RK4 = 2, SM_EULER = 3 };
@@ -81,6 +81,70 @@ __device__ __forceinline__ double wrap_phase<double>(double t) {
 }
 
 __device__ __forceinline__ double2 d2add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Four consecutive entries from j0 (a multiple of 4, in a library-owned
+// allocation, so full groups are aligned vector accesses); entries at or
+// past n read as zero and are not written.
+template <typename R>
+__device__ __forceinline__ void load4(const R *p, int64_t j0, int64_t n, R (&v)[4]) {
+    if (j0 + 4 <= n) {
+        if constexpr (sizeof(R) == 4) {
+            const float4 q = *reinterpret_cast<const float4 *>(p + j0);
+            v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+        } else {
+            const double2 q0 = *reinterpret_cast<const double2 *>(p + j0);
+            const double2 q1 = *reinterpret_cast<const double2 *>(p + j0 + 2);
+            v[0] = q0.x, v[1] = q0.y, v[2] = q1.x, v[3] = q1.y;
+        }
+    } else {
+        for (int e = 0; e < 4; e++) v[e] = j0 + e < n ? p[j0 + e] : (R)0;
+    }
+}
+template <typename R>
+__device__ __forceinline__ void store4(R *p, int64_t j0, int64_t n, const R (&v)[4]) {
+    if (j0 + 4 <= n) {
+        if constexpr (sizeof(R) == 4) {
+            *reinterpret_cast<float4 *>(p + j0) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+            *reinterpret_cast<double2 *>(p + j0) = make_double2(v[0], v[1]);
+            *reinterpret_cast<double2 *>(p + j0 + 2) = make_double2(v[2], v[3]);
+        }
+    } else {
+        for (int e = 0; e < 4; e++)
+            if (j0 + e < n) p[j0 + e] = v[e];
+    }
+}
+template <typename R>
+__device__ __forceinline__ void load4z(const zc<R> *p, int64_t j0, int64_t n, zc<R> (&v)[4]) {
+    if (j0 + 4 <= n) {
+        if constexpr (sizeof(R) == 4) {
+            const float4 q0 = *reinterpret_cast<const float4 *>(p + j0);
+            const float4 q1 = *reinterpret_cast<const float4 *>(p + j0 + 2);
+            v[0] = {q0.x, q0.y}, v[1] = {q0.z, q0.w}, v[2] = {q1.x, q1.y}, v[3] = {q1.z, q1.w};
+        } else {
+            for (int e = 0; e < 4; e++) {
+                const double2 q = *reinterpret_cast<const double2 *>(p + j0 + e);
+                v[e] = {q.x, q.y};
+            }
+        }
+    } else {
+        for (int e = 0; e < 4; e++) v[e] = j0 + e < n ? p[j0 + e] : zc<R>{(R)0, (R)0};
+    }
+}
+template <typename R>
+__device__ __forceinline__ void store4z(zc<R> *p, int64_t j0, int64_t n, const zc<R> (&v)[4]) {
+    if (j0 + 4 <= n) {
+        if constexpr (sizeof(R) == 4) {
+            *reinterpret_cast<float4 *>(p + j0) = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+            *reinterpret_cast<float4 *>(p + j0 + 2) = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+        } else {
+            for (int e = 0; e < 4; e++) *reinterpret_cast<double2 *>(p + j0 + e) = make_double2(v[e].x, v[e].y);
+        }
+    } else {
+        for (int e = 0; e < 4; e++)
+            if (j0 + e < n) p[j0 + e] = v[e];
+    }
+}
 
 // Block sum of one double2 per thread (fixed order), broadcast to all threads.
 template <int NT>
@@ -231,23 +295,24 @@ __global__ __launch_bounds__(SB) void struct_stage_kernel(SArgs<R> a) {
     const int64_t j0 = a0 + (int64_t)SNPT * t;
     const int mode = a.mode;
 
-    R tn[SNPT], om[SNPT], av[SNPT], s[SNPT];
+    R tn[SNPT], om[SNPT], av[SNPT], s[SNPT], al[SNPT];
     zc<R> zj[SNPT];
 #pragma unroll
     for (int e = 0; e < SNPT; e++) {
-        const int64_t j = j0 + e;
-        const bool ok = j < n;
         tn[e] = om[e] = av[e] = s[e] = (R)0;
+        al[e] = (R)1;
         zj[e] = zc<R>{(R)0, (R)0};
-        if (!ok) continue;
-        if (mode == SM_PREP) {
-            tn[e] = a.state_in[j];
-        } else {
-            if (mode != SM_RHS) tn[e] = a.theta_n[j];
-            if (a.omega) om[e] = a.omega[j];
-            if (mode == SM_RK4 && a.stage > 0) av[e] = a.acc[j];
-            zj[e] = a.z_in[j];
-        }
+    }
+    if (mode == SM_PREP) {
+#pragma unroll
+        for (int e = 0; e < SNPT; e++)
+            if (j0 + e < n) tn[e] = a.state_in[j0 + e];   // caller's buffer: no alignment assumed
+    } else {
+        if (mode != SM_RHS) load4(a.theta_n, j0, n, tn);
+        if (a.omega) load4(a.omega, j0, n, om);
+        if (mode == SM_RK4 && a.stage > 0) load4(a.acc, j0, n, av);
+        if (RANK1) load4(a.alpha, j0, n, al);
+        load4z(a.z_in, j0, n, zj);
     }
 
     if (mode != SM_PREP) {
@@ -319,53 +384,50 @@ __global__ __launch_bounds__(SB) void struct_stage_kernel(SArgs<R> a) {
     }
 
     // ---- combine, stage update, next z and its tile sums ----
-    R tnew[SNPT];
+    R tnew[SNPT], H[SNPT];
 #pragma unroll
     for (int e = 0; e < SNPT; e++) {
-        const int64_t j = j0 + e;
-        tnew[e] = (R)0;
-        if (j >= n) continue;
-        if (mode == SM_PREP) {
-            tnew[e] = tn[e];
-            a.theta_n[j] = tn[e];
-            continue;
-        }
-        const R w = RANK1 ? a.alpha[j] : (R)1;
-        const R H = om[e] + a.Kn * w * s[e];
-        if (mode == SM_RHS) {
-            a.state_out[j] = H;
-        } else if (mode == SM_EULER) {
-            tnew[e] = wrap_phase<R>(tn[e] + a.dt * H);
-            a.theta_n[j] = tnew[e];
-        } else if (a.stage == 0) {
-            a.acc[j] = H;
-            tnew[e] = tn[e] + (R)0.5 * a.dt * H;
-        } else if (a.stage == 1) {
-            a.acc[j] = av[e] + (R)2 * H;
-            tnew[e] = tn[e] + (R)0.5 * a.dt * H;
-        } else if (a.stage == 2) {
-            a.acc[j] = av[e] + (R)2 * H;
-            tnew[e] = tn[e] + a.dt * H;
-        } else {
-            tnew[e] = wrap_phase<R>(tn[e] + a.dt / (R)6 * (av[e] + H));
-            a.theta_n[j] = tnew[e];
-        }
+        H[e] = om[e] + a.Kn * al[e] * s[e];
+        tnew[e] = tn[e];
     }
-    if (mode == SM_RHS) return;
+    if (mode == SM_RHS) {
+#pragma unroll
+        for (int e = 0; e < SNPT; e++)
+            if (j0 + e < n) a.state_out[j0 + e] = H[e];
+        return;
+    }
+    if (mode == SM_PREP) {
+        store4(a.theta_n, j0, n, tn);
+    } else if (mode == SM_EULER) {
+#pragma unroll
+        for (int e = 0; e < SNPT; e++) tnew[e] = wrap_phase<R>(tn[e] + a.dt * H[e]);
+        store4(a.theta_n, j0, n, tnew);
+    } else if (a.stage < 3) {
+        R acc[SNPT];
+        const R c = a.stage == 2 ? a.dt : (R)0.5 * a.dt;
+#pragma unroll
+        for (int e = 0; e < SNPT; e++) {
+            acc[e] = a.stage == 0 ? H[e] : av[e] + (R)2 * H[e];
+            tnew[e] = tn[e] + c * H[e];
+        }
+        store4(a.acc, j0, n, acc);
+    } else {
+#pragma unroll
+        for (int e = 0; e < SNPT; e++) tnew[e] = wrap_phase<R>(tn[e] + a.dt / (R)6 * (av[e] + H[e]));
+        store4(a.theta_n, j0, n, tnew);
+    }
     zc<R> zn[SNPT];
     R wt[SNPT];
+    if (KIND == SK_RANK1) load4(a.beta, j0, n, wt);
 #pragma unroll
     for (int e = 0; e < SNPT; e++) {
-        const int64_t j = j0 + e;
-        zn[e] = zc<R>{(R)0, (R)0};
-        wt[e] = (R)0;
-        if (j >= n) continue;
         R sn, c0;
         zsincos(tnew[e], &sn, &c0);
-        zn[e] = zc<R>{c0, sn};
-        a.z_out[j] = zn[e];
-        wt[e] = (KIND == SK_RANK1) ? a.beta[j] : (R)1;
+        const bool ok = j0 + e < n;
+        zn[e] = ok ? zc<R>{c0, sn} : zc<R>{(R)0, (R)0};
+        if (KIND != SK_RANK1) wt[e] = (R)1;
     }
+    store4z(a.z_out, j0, n, zn);
     // tile sums: slot k-1 of w z^k (k = 1..P; the E1 variants), slot P of z
     if constexpr (KIND == SK_RANK1 || KIND == SK_RING) {
         zc<R> zk[SNPT];
@@ -398,29 +460,44 @@ __global__ __launch_bounds__(SB) void struct_stage_kernel(SArgs<R> a) {
 
 // Totals of the tile sums (every slot) and, for the ring, exclusive tile
 // offsets of slots 0..P-1; r_out (optional) = |total of slot P| / n.  One
-// block; each thread owns a contiguous run of tiles, so the order is fixed.
+// block; a batch of SCAN_T * SCAN_R tiles gives every thread SCAN_R
+// consecutive tiles, all loaded at once (the loads are in flight together),
+// summed in order, then one block scan of the thread sums; the order is fixed.
+constexpr int SCAN_R = 16;
 __global__ __launch_bounds__(SCAN_T) void struct_scan_kernel(const double2 *part, int32_t ntiles, int P, int ring,
                                                              double invN, double2 *tot, double *r_out) {
     __shared__ double2 sh[SCAN_T / 64];
     const int t = threadIdx.x;
-    const int64_t per = ((int64_t)ntiles + SCAN_T - 1) / SCAN_T;
-    const int64_t b = per * t, e = b + per < ntiles ? b + per : ntiles;
     double2 *off = tot + (P + 1);
     for (int sl = 0; sl <= P; sl++) {
-        double2 v = make_double2(0.0, 0.0);
-        for (int64_t i = b; i < e; i++) v = d2add(v, part[i * (P + 1) + sl]);
-        double2 total;
-        double2 run = block_excl_scan<SCAN_T>(v, sh, &total);
-        if (t == 0) {
-            tot[sl] = total;
-            if (sl == P && r_out) r_out[0] = sqrt(total.x * total.x + total.y * total.y) * invN;
-        }
-        if (ring && sl < P) {
-            for (int64_t i = b; i < e; i++) {
-                off[i * P + sl] = run;
-                run = d2add(run, part[i * (P + 1) + sl]);
+        const bool scan = ring && sl < P;
+        double2 carry = make_double2(0.0, 0.0);
+        for (int64_t b0 = 0; b0 < ntiles; b0 += (int64_t)SCAN_T * SCAN_R) {
+            const int64_t i0 = b0 + (int64_t)t * SCAN_R;
+            double2 v[SCAN_R];
+#pragma unroll
+            for (int r = 0; r < SCAN_R; r++)
+                v[r] = i0 + r < ntiles ? part[(i0 + r) * (P + 1) + sl] : make_double2(0.0, 0.0);
+            double2 ts = v[0];
+#pragma unroll
+            for (int r = 1; r < SCAN_R; r++) ts = d2add(ts, v[r]);
+            if (!scan) {
+                carry = d2add(carry, block_sum<SCAN_T>(ts, sh));
+            } else {
+                double2 bt;
+                double2 run = d2add(carry, block_excl_scan<SCAN_T>(ts, sh, &bt));
+#pragma unroll
+                for (int r = 0; r < SCAN_R; r++) {
+                    if (i0 + r < ntiles) off[(i0 + r) * P + sl] = run;
+                    run = d2add(run, v[r]);
+                }
+                carry = d2add(carry, bt);
             }
-            if (t == 0) off[(int64_t)ntiles * P + sl] = total;
+        }
+        if (t == 0) {
+            tot[sl] = carry;
+            if (scan) off[(int64_t)ntiles * P + sl] = carry;
+            if (sl == P && r_out) r_out[0] = sqrt(carry.x * carry.x + carry.y * carry.y) * invN;
         }
     }
 }
