@@ -33,7 +33,7 @@ _vp = ctypes.c_void_p
 
 def build(force: bool = False) -> str:
     """Compile the oracle: gcc -O2, no fast-math (libm sin/cos, IEEE FP64)."""
-    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "basis.c", "structured.c")]
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "basis.c", "structured.c", "poly.c")]
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in srcs):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
@@ -97,6 +97,12 @@ def _load():
         lib.oracle_structured_integrate.restype = ctypes.c_int
         lib.oracle_structured_integrate.argtypes = [ctypes.c_int, i64, i64, _vp, _vp, _vp, d, ctypes.c_int,
                                                     _vp, _vp, _vp, d, i64, ctypes.c_int, _vp]
+        lib.oracle_poly_rhs.restype = None
+        lib.oracle_poly_rhs.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp, ctypes.c_int, _vp,
+                                        _vp, _vp, i64, _vp]
+        lib.oracle_poly_integrate.restype = ctypes.c_int
+        lib.oracle_poly_integrate.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp, ctypes.c_int,
+                                              _vp, _vp, d, i64, ctypes.c_int]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -210,6 +216,39 @@ def structured_integrate(kind, n, omega, K, d_sin, d_cos, theta0, dt, steps, k=0
     if rc != 0:
         raise MemoryError("oracle_structured_integrate")
     return th, r
+
+
+# ---------------------------------------------------------------------------
+# polynomial difference coupling (App. A.3 difference form; Desai-Zwanzig)
+# ---------------------------------------------------------------------------
+
+def poly_rhs(n, row_ptr, col, omega, K, h, f, x, rows=None, complete=False):
+    """x_m' = omega_m + f(x_m) + (K/N) sum_l a_ml h(x_l - x_m), h and f given by
+    their coefficients in increasing powers (f may be None)."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    h = _f64(h)
+    fq = -1 if f is None else len(f) - 1
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    out = np.empty(cnt, dtype=np.float64)
+    lib.oracle_poly_rhs(int(n), _p(rp), _p(cl), int(bool(complete)), _p(_f64(omega)), float(K), len(h) - 1, _p(h),
+                        fq, _p(_f64(f)), _p(_f64(x)), _p(rws), 0 if rws is None else len(rws), _p(out))
+    return out
+
+
+def poly_integrate(n, row_ptr, col, omega, K, h, f, x0, dt, steps, stepper="rk4", complete=False):
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    h = _f64(h)
+    fq = -1 if f is None else len(f) - 1
+    x = np.array(x0, dtype=np.float64, copy=True)
+    rc = lib.oracle_poly_integrate(int(n), _p(rp), _p(cl), int(bool(complete)), _p(_f64(omega)), float(K),
+                                   len(h) - 1, _p(h), fq, _p(_f64(f)), _p(x), float(dt), int(steps),
+                                   1 if stepper == "euler" else 0)
+    if rc != 0:
+        raise MemoryError("oracle_poly_integrate")
+    return x
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,105 @@
+"""Pins of the polynomial-coupling oracle (App. A.3 difference form and the
+Desai-Zwanzig model of App. A.5): the graph Laplacian for h(x) = x, the
+paper's fast forms on the complete graph (first moment for Desai-Zwanzig,
+binomial expansion over the moments w_k for general h), the odd-coupling
+invariant, and the exact solution of the linear system."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse
+import scipy.sparse.csgraph
+
+import oracle
+
+
+def random_graph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    up = np.triu(rng.random((n, n)) < p, 1)
+    A = (up | up.T).astype(np.float64)
+    S = scipy.sparse.csr_matrix(A)
+    S.sort_indices()
+    return A, S.indptr.astype(np.int64), S.indices.astype(np.int32)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_linear_coupling_is_the_graph_laplacian():
+    n, K = 80, 2.0
+    A, rp, col = random_graph(n, 0.2, 1)
+    x = np.random.default_rng(2).normal(size=n)
+    got = oracle.poly_rhs(n, rp, col, None, K, [0.0, 1.0], None, x)
+    L = scipy.sparse.csgraph.laplacian(A)
+    assert rel(got, -K / n * (L @ x)) < 1e-13
+
+
+def test_desai_zwanzig_mean_field_form():
+    """App. A.5: x_m' = -V'(x_m) + (w_1 - x_m) on the complete graph (K = 1);
+    the l = m pair contributes h(0) = 0.  V(x) = x^4/4 - x^2/2, -V'(x) = x - x^3."""
+    n = 300
+    x = np.random.default_rng(3).normal(size=n)
+    got = oracle.poly_rhs(n, None, None, None, 1.0, [0.0, 1.0], [0.0, 1.0, 0.0, -1.0], x, complete=True)
+    want = (x - x ** 3) + (x.mean() - x)
+    assert rel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_binomial_moment_form(p):
+    """eq. PolyDifferenceRHSfast: sum_l h(x_l - x_m) = sum_a h_a sum_k C(a,k) W_k (-x_m)^(a-k)
+    with W_k = sum_l x_l^k (l = m included, so h(0) is removed for the
+    complete graph without self loops)."""
+    rng = np.random.default_rng(4 + p)
+    n, K = 200, 1.5
+    h = rng.normal(size=p + 1)
+    x = rng.uniform(-1.2, 1.2, n)
+    got = oracle.poly_rhs(n, None, None, None, K, h, None, x, complete=True)
+    W = [np.sum(x ** k) for k in range(p + 1)]
+    s = np.zeros(n)
+    for a in range(p + 1):
+        for k in range(a + 1):
+            s += h[a] * math.comb(a, k) * W[k] * (-x) ** (a - k)
+    want = K / n * (s - h[0])
+    assert rel(got, want) < 1e-11
+
+
+def test_odd_coupling_conserves_the_sum():
+    n = 120
+    A, rp, col = random_graph(n, 0.15, 5)
+    x = np.random.default_rng(6).normal(size=n)
+    c = oracle.poly_rhs(n, rp, col, None, 3.0, [0.0, 1.0, 0.0, 0.4, 0.0, -0.1], None, x)
+    assert abs(c.sum()) < 1e-12 * np.abs(c).sum()
+
+
+@pytest.mark.parametrize("stepper", ["rk4", "euler"])
+def test_linear_system_exact_solution(stepper):
+    """f(x) = -g x, h(x) = x: x' = -M x with M = g I + (K/N) L.  One step of
+    the stepper is exactly the matrix polynomial R(-dt M) (Euler: I - dt M;
+    RK4: the degree-4 Taylor polynomial of the exponential), so the trajectory
+    is R^steps x0; RK4 also tracks expm(-t M) x0."""
+    n, K, g = 40, 4.0, 0.3
+    A, rp, col = random_graph(n, 0.3, 7)
+    x0 = np.random.default_rng(8).normal(size=n)
+    M = g * np.eye(n) + K / n * scipy.sparse.csgraph.laplacian(A)
+    T, steps = 2.0, 400
+    dt = T / steps
+    got = oracle.poly_integrate(n, rp, col, None, K, [0.0, 1.0], [0.0, -g], x0, dt, steps, stepper=stepper)
+    Z = -dt * M
+    I = np.eye(n)
+    Rm = I + Z if stepper == "euler" else I + Z + Z @ Z / 2 + Z @ Z @ Z / 6 + Z @ Z @ Z @ Z / 24
+    assert rel(got, np.linalg.matrix_power(Rm, steps) @ x0) < 1e-12
+    if stepper == "rk4":
+        assert rel(got, scipy.linalg.expm(-T * M) @ x0) < 1e-10
+
+
+def test_frequencies_and_local_term_add():
+    n = 50
+    A, rp, col = random_graph(n, 0.3, 9)
+    rng = np.random.default_rng(10)
+    x, om = rng.normal(size=n), rng.normal(size=n)
+    f = [0.5, -1.0, 0.25]
+    base = oracle.poly_rhs(n, rp, col, None, 2.0, [0.1, 1.0, 0.3], None, x)
+    full = oracle.poly_rhs(n, rp, col, om, 2.0, [0.1, 1.0, 0.3], f, x)
+    assert rel(full - base, om + f[0] + f[1] * x + f[2] * x * x) < 1e-13
