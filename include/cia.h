@@ -65,6 +65,10 @@ typedef enum cia_status {
 #define CIA_MODEL_TRIADIC 1  /* phase model with h = sin plus the higher-order term
                                 (K2/N^2) sum_{(j,k) ordered} B_mjk sin(theta_j + theta_k - 2 theta_m)
                                 (App. A.7 with lambda = (1,1,-2), on a hypergraph) */
+#define CIA_MODEL_POLY 3     /* polynomial difference coupling (App. A.3; Desai-Zwanzig, App. A.5):
+                                x_m' = omega_m + sum_{j<=poly_q} f_j x_m^j
+                                       + (K/N) sum_l a_ml h(x_l - x_m),
+                                h(x) = sum_{a<=p} h_a x^a; no phase wrapping, no r(t) */
 #define CIA_MODEL_FLOCK 2    /* Cucker-Smale in 3-D (App. A.6): s_m' = v_m,
                                 v_m' = (1/N) sum_l a_ml w(|s_l - s_m|) (v_l - v_m),
                                 w(r) = cs_K / (cs_sigma^2 + r^2)^cs_beta */
@@ -152,6 +156,11 @@ typedef struct cia_coupling {
                                   the state of the first cia_rhs / cia_integrate call unless
                                   parameters were set or trained before (0 = 3000) */
     int32_t reserved;
+    int32_t poly_q;            /* polynomial model: degree of the local polynomial f, -1..8
+                                  (-1 = none) */
+    int32_t reserved2;
+    const double *poly_h;      /* polynomial model: host [p+1] coefficients h_0..h_p of h, p = 1..8 */
+    const double *poly_f;      /* polynomial model: host [poly_q+1] coefficients f_0..f_q of f */
 } cia_coupling;
 
 typedef struct cia_options {

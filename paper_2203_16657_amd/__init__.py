@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libcia.so")
 # ---- constants (mirror of cia.h) ----
 CIA_OK, CIA_EINVAL, CIA_ENOMEM, CIA_EHIP, CIA_EUNSUPPORTED, CIA_ENONFINITE = 0, -1, -2, -3, -4, -5
 CIA_GRAPH_CSR, CIA_GRAPH_COMPLETE, CIA_GRAPH_RANK1, CIA_GRAPH_RING = 0, 1, 2, 3
-CIA_MODEL_PHASE, CIA_MODEL_TRIADIC, CIA_MODEL_FLOCK = 0, 1, 2
+CIA_MODEL_PHASE, CIA_MODEL_TRIADIC, CIA_MODEL_FLOCK, CIA_MODEL_POLY = 0, 1, 2, 3
 CIA_METHOD_CIA, CIA_METHOD_DIRECT = 0, 1
 CIA_F32, CIA_F64 = 0, 1
 CIA_RK4, CIA_EULER = 0, 1
@@ -48,7 +48,8 @@ class cia_coupling(_c.Structure):
                 ("K", _c.c_double), ("K2", _c.c_double), ("hyper", _vp),
                 ("cs_K", _c.c_double), ("cs_sigma", _c.c_double), ("cs_beta", _c.c_double),
                 ("cs_L", _c.c_double), ("cs_basis", _c.c_int32), ("rank", _c.c_int32),
-                ("train_iters", _c.c_int32), ("reserved", _c.c_int32)]
+                ("train_iters", _c.c_int32), ("reserved", _c.c_int32), ("poly_q", _c.c_int32),
+                ("reserved2", _c.c_int32), ("poly_h", _vp), ("poly_f", _vp)]
 
 
 class cia_options(_c.Structure):
@@ -413,6 +414,33 @@ class Plan:
         o.unit_work, o.block, o.dense_alpha, o.device = unit_work, block, dense_alpha, device
         h = cia_build(g, labels, c, omega, o)
         return cls(h, int(n), precision, CIA_MODEL_PHASE)
+
+    @classmethod
+    def poly(cls, n, row_ptr=None, col=None, labels=None, omega=None, K=1.0, h=(0.0, 1.0), f=None,
+             method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4, flags=0, complete=False, unit_work=0,
+             block=0, dense_alpha=2.0, device=-1):
+        """Polynomial difference coupling (App. A.3; Desai-Zwanzig, App. A.5):
+        x_m' = omega_m + f(x_m) + (K/N) sum_l a_ml h(x_l - x_m), h and f by
+        their coefficients in increasing powers (f optional)."""
+        load()
+        rp = None if complete else np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = None if complete else np.ascontiguousarray(col, dtype=np.int32)
+        g = cia_graph(n=int(n), kind=CIA_GRAPH_COMPLETE if complete else CIA_GRAPH_CSR, reserved=0,
+                      row_ptr=_np_ptr(rp), col=_np_ptr(cl))
+        hc = np.ascontiguousarray(h, dtype=np.float64)
+        fc = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
+        c = cia_coupling_default()
+        c.model = CIA_MODEL_POLY
+        c.p = len(hc) - 1
+        c.poly_h = _np_ptr(hc)
+        c.poly_q = -1 if fc is None else len(fc) - 1
+        c.poly_f = _np_ptr(fc)
+        c.K = float(K)
+        o = cia_options_default()
+        o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
+        o.unit_work, o.block, o.dense_alpha, o.device = unit_work, block, dense_alpha, device
+        h_ = cia_build(g, labels, c, omega, o)
+        return cls(h_, int(n), precision, CIA_MODEL_POLY)
 
     @classmethod
     def structured(cls, n, kind, omega=None, K=1.0, d_sin=(0.0, 1.0), d_cos=(0.0, 0.0), alpha=None, beta=None,

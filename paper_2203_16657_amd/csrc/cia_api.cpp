@@ -147,7 +147,8 @@ cia_status cia_build(const cia_graph *g, const int32_t *labels, const cia_coupli
     cia_options_default(&def);
     if (!o) o = &def;
     if (g->n <= 0) return set_error(CIA_EINVAL, "graph: n = %lld, need n >= 1", (long long)g->n);
-    if (c->model != CIA_MODEL_PHASE && c->model != CIA_MODEL_TRIADIC && c->model != CIA_MODEL_FLOCK)
+    if (c->model != CIA_MODEL_PHASE && c->model != CIA_MODEL_TRIADIC && c->model != CIA_MODEL_FLOCK &&
+        c->model != CIA_MODEL_POLY)
         return set_error(CIA_EINVAL, "coupling.model = %d", c->model);
     return make_plan(o, g->n, c->model, out, [&](cia_plan *p) -> cia_status {
         if (g->kind == CIA_GRAPH_RANK1 || g->kind == CIA_GRAPH_RING) return struct_build(p, g, labels, c, omega, o);
@@ -210,6 +211,7 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream) {
     switch (p->structd ? -1 : p->model) {
         case -1: st = struct_rhs(p, state, dstate, s); break;
         case CIA_MODEL_PHASE:
+        case CIA_MODEL_POLY:
         case CIA_MODEL_TRIADIC: st = phase_rhs(p, state, dstate, s); break;
         case CIA_MODEL_FLOCK: st = flock_rhs(p, state, dstate, s); break;
         default: st = set_error(CIA_EUNSUPPORTED, "model %d", p->model);
@@ -232,6 +234,10 @@ cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, dou
         case -1: st = struct_integrate(p, state, dt, steps, r_trace, s); break;
         case CIA_MODEL_PHASE:
         case CIA_MODEL_TRIADIC: st = phase_integrate(p, state, dt, steps, r_trace, s); break;
+        case CIA_MODEL_POLY:
+            st = r_trace ? set_error(CIA_EINVAL, "r_trace is defined for the phase models only")
+                         : phase_integrate(p, state, dt, steps, nullptr, s);
+            break;
         case CIA_MODEL_FLOCK:
             st = r_trace ? set_error(CIA_EINVAL, "r_trace is defined for the phase models only")
                          : flock_integrate(p, state, dt, steps, s);

@@ -316,6 +316,7 @@ void cia_coupling_default(cia_coupling *c) {
     c->cs_L = 20.0;
     c->cs_basis = CIA_BASIS_EXACT;
     c->rank = 32;
+    c->poly_q = -1;
 }
 
 cia_status cia_fourier_coeffs(const double *samples, int64_t m, int32_t p, double *d_sin,

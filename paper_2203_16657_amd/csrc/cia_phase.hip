@@ -172,6 +172,8 @@ struct PhaseArgs {
     R Kn, dt, d0, hzero;
     R K2n;                    // triadic strength K2 / N^2
     R dsin[PMAX + 1], dcos[PMAX + 1];
+    double ph[PMAX + 1], pf[PMAX + 1];   // polynomial model: h and f coefficients
+    int32_t pq;
     int32_t stage, mode, want_r, lds_cap;
     uint32_t pad_pos;         // position whose z is 0 (= n): target of padded int32 entries
 };
@@ -685,6 +687,217 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
 }
 
 // ---------------------------------------------------------------------------
+// polynomial difference coupling (App. A.3; Desai-Zwanzig, App. A.5)
+// ---------------------------------------------------------------------------
+// The stage kernel of the polynomial model on the same units, slices and
+// remainder streams as the phase model; the staged and gathered value is x
+// itself.  E1: per-community moments W_k = sum_{l in c} x_l^k (FP64 unit
+// partials, summed in a fixed order).  E2: per row, the partners' moments
+// T_k = sum_{S+} x_l^k - sum_{S-} x_l^k.  Combine (eq. PolyDifferenceRHSfast
+// by Taylor coefficients): with M_k = W_k + T_k and M_0 = lambda_c + |S+| -
+// |S-|, sum_l a_ml h(x_l - x_m) = sum_k M_k g_k(x_m) - h(0), where g_k(x) =
+// sum_{a>=k} C(a,k) h_a (-x)^(a-k) are the coefficients of h(y - x) in y,
+// and h(0) removes the l = m term that the community sum includes.  The
+// direct variant evaluates h(x_l - x_m) on every edge.
+
+// value staged in LDS at a byte offset
+template <typename R>
+__device__ __forceinline__ R xat(const R *xsh, uint32_t byte_off) {
+    return *reinterpret_cast<const R *>(reinterpret_cast<const unsigned char *>(xsh) + byte_off);
+}
+
+template <typename R, int P>
+__device__ __forceinline__ void acc_pow(R (&T)[P], R x, R sign) {
+    R xk = x;
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        T[k] += sign * xk;
+        xk *= x;
+    }
+}
+
+template <typename R, int P, int BLOCK, bool DIRECT>
+__global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
+    constexpr int NW = BLOCK / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    R *xsh = reinterpret_cast<R *>(smem);   // [lds_cap + 1]
+    __shared__ double qsh[P];
+    __shared__ double red[NW][P];
+
+    const Unit Un = a.units[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const bool assigned = !DIRECT && (Un.flags & UF_ASSIGNED) != 0;
+    const bool staged = !DIRECT && (Un.flags & UF_STAGED) != 0;
+    const int mode = a.mode;
+    const bool gather = mode != M_PREP;
+    const int off = Un.off, lam = Un.lam;
+
+    // ---- unit start: the community's x in LDS and its moments W_1..W_P ----
+    if (gather && assigned) {
+        if (staged) {
+            for (int j = tid; j < lam; j += BLOCK) xsh[j] = a.th_in[off + j];
+            if (tid == 0) xsh[lam] = (R)0;
+        }
+        if (wid == NW - 1) {
+            for (int k = 0; k < P; k++) {
+                double sx = 0.0;
+                for (int j = Un.qbeg + lane; j < Un.qend; j += 64) sx += a.q_in[(size_t)j * P + k].x;
+                for (int o = 32; o > 0; o >>= 1) sx += __shfl_xor(sx, o);
+                if (lane == 0) qsh[k] = sx;
+            }
+        }
+    }
+    __syncthreads();
+    double W[P];
+#pragma unroll
+    for (int k = 0; k < P; k++) W[k] = (gather && assigned) ? qsh[k] : 0.0;
+    double pd[P];
+#pragma unroll
+    for (int k = 0; k < P; k++) pd[k] = 0.0;
+
+    const uint32_t padb = (uint32_t)lam * (uint32_t)sizeof(R);
+    const uint32_t pad = a.pad_pos;
+
+    for (int sl = Un.s0 + wid; sl < Un.s1; sl += NW) {
+        const Slice S = a.slices[sl];
+        const bool mine = lane < S.rows;
+        const int i = S.row0 + lane;
+        R tn = (R)0, om = (R)0, av = (R)0, xm = (R)0, knv = a.Kn;
+        int cv = 0;
+        if (mine) {
+            if (mode == M_PREP) {
+                tn = a.state_in[a.perm[i]];
+            } else {
+                if (mode != M_RHS) tn = a.theta_n[i];
+                if (a.omega) om = a.omega[i];
+                if (a.kn) knv = a.kn[i];
+                if (mode == M_RK4 && a.stage > 0) av = a.acc[i];
+                cv = a.cnt[i];
+                xm = staged ? xsh[i - off] : a.th_in[i];
+            }
+        }
+        R T[P];
+#pragma unroll
+        for (int k = 0; k < P; k++) T[k] = (R)0;
+        double Eh = 0.0;   // direct: sum of h(x_l - x_m)
+        if (gather) {
+            if (!DIRECT) {
+                const uint4 *col = a.negdata + S.beg[0] + lane;
+                for (int k = 0; k < S.w[0]; k++) {
+                    const uint4 v = ld_stream(col + (size_t)k * SLICE);
+                    const uint32_t q4[4] = {v.x, v.y, v.z, v.w};
+                    if (staged) {
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            acc_pow<R, P>(T, xat(xsh, q4[q] & 0xffffu), (R)-1);
+                            acc_pow<R, P>(T, xat(xsh, q4[q] >> 16), (R)-1);
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; q++) acc_pow<R, P>(T, a.th_in[q4[q]], (R)-1);
+                    }
+                }
+                (void)padb;
+            }
+            const uint4 *col = a.posdata + S.beg[1] + lane;
+            for (int k = 0; k < S.w[1]; k++) {
+                const uint4 v = ld_stream(col + (size_t)k * SLICE);
+                const uint32_t q4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const R xl = a.th_in[q4[q]];   // the padding position holds 0
+                    if (DIRECT) {
+                        if (q4[q] != pad) {
+                            const R d = xl - xm;
+                            R hv = (R)a.ph[P];
+#pragma unroll
+                            for (int e = P - 1; e >= 0; e--) hv = hv * d + (R)a.ph[e];
+                            Eh += (double)hv;
+                        }
+                    } else {
+                        acc_pow<R, P>(T, xl, (R)1);
+                    }
+                }
+            }
+        }
+        if (mine) {
+            R xnew;
+            if (mode == M_PREP) {
+                xnew = tn;
+                a.theta_n[i] = tn;
+            } else {
+                double s;
+                if (DIRECT) {
+                    s = Eh;
+                } else {
+                    // g_k(x_m): Taylor shift of h by -x_m (repeated synthetic division)
+                    double g[P + 1];
+#pragma unroll
+                    for (int k = 0; k <= P; k++) g[k] = a.ph[k];
+                    const double c = -(double)xm;
+#pragma unroll
+                    for (int k = 0; k < P; k++)
+#pragma unroll
+                        for (int j = P - 1; j >= k; j--) g[j] += c * g[j + 1];
+                    s = g[0] * ((assigned ? (double)lam : 0.0) + (double)cv);
+#pragma unroll
+                    for (int k = 1; k <= P; k++) s += g[k] * (W[k - 1] + (double)T[k - 1]);
+                    if (assigned) s -= a.ph[0];
+                }
+                double f = 0.0;
+                for (int j = a.pq; j >= 0; j--) f = f * (double)xm + a.pf[j];
+                const R H = (R)((double)om + f + (double)knv * s);
+                if (mode == M_RHS) {
+                    a.state_out[a.perm[i]] = H;
+                    xnew = (R)0;
+                } else if (mode == M_EULER) {
+                    xnew = tn + a.dt * H;
+                    a.theta_n[i] = xnew;
+                } else if (a.stage == 0) {
+                    a.acc[i] = H;
+                    xnew = tn + (R)0.5 * a.dt * H;
+                } else if (a.stage == 1) {
+                    a.acc[i] = av + (R)2 * H;
+                    xnew = tn + (R)0.5 * a.dt * H;
+                } else if (a.stage == 2) {
+                    a.acc[i] = av + (R)2 * H;
+                    xnew = tn + a.dt * H;
+                } else {
+                    xnew = tn + a.dt / (R)6 * (av + H);
+                    a.theta_n[i] = xnew;
+                }
+            }
+            if (mode != M_RHS) {
+                a.th_out[i] = xnew;
+                if (assigned) {
+                    double xk = (double)xnew;
+#pragma unroll
+                    for (int k = 0; k < P; k++) {
+                        pd[k] += xk;
+                        xk *= (double)xnew;
+                    }
+                }
+            }
+        }
+    }
+    if (mode == M_RHS || !assigned) return;
+    // ---- unit moments of the next stage: fixed-order block reduction ----
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        double v = pd[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (tid == 0)
+        for (int k = 0; k < P; k++) {
+            double v = red[0][k];
+            for (int w = 1; w < NW; w++) v += red[w][k];
+            a.q_out[(size_t)Un.qslot * P + k] = make_double2(v, 0.0);
+        }
+}
+
+// ---------------------------------------------------------------------------
 // triadic model: intra-community hyperedges (App. A.7 on a hypergraph)
 // ---------------------------------------------------------------------------
 // A triple {m, j, k} of one community is a hyperedge iff
@@ -1069,6 +1282,9 @@ struct PhaseState {
     int block = 256;
     bool has_wide = false;   // F32 plan with at least one FP64-observable community
     bool tri = false;        // triadic model
+    bool poly = false;       // polynomial difference coupling
+    int pq = -1;             // degree of the local polynomial f (-1: none)
+    double ph[PMAX + 1] = {0}, pf[PMAX + 1] = {0};   // coefficients of h and f
     double K2n = 0;
     uint64_t tri_seed = 0, tri_thr = 0;
     TriBlock *tri_blocks = nullptr;   // direct triadic: (community, centres) blocks
@@ -1536,6 +1752,26 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     const bool f64 = o->precision == CIA_F64;
     s->f64 = f64;
     s->direct = o->method == CIA_METHOD_DIRECT;
+    if (c->model == CIA_MODEL_POLY) {
+        if (c->p < 1 || c->p > PMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, PMAX);
+        if (!c->poly_h) return set_error(CIA_EINVAL, "polynomial model: coupling.poly_h is NULL");
+        if (c->poly_q < -1 || c->poly_q > PMAX)
+            return set_error(CIA_EINVAL, "coupling.poly_q = %d; supported -1..%d", c->poly_q, PMAX);
+        if (c->poly_q >= 0 && !c->poly_f) return set_error(CIA_EINVAL, "polynomial model: coupling.poly_f is NULL");
+        for (int k = 0; k <= c->p; k++)
+            if (!std::isfinite(c->poly_h[k])) return set_error(CIA_EINVAL, "coupling.poly_h must be finite");
+        for (int k = 0; k <= c->poly_q; k++)
+            if (!std::isfinite(c->poly_f[k])) return set_error(CIA_EINVAL, "coupling.poly_f must be finite");
+        if (g->kind == CIA_GRAPH_COMPLETE && o->method == CIA_METHOD_DIRECT)
+            return set_error(CIA_EUNSUPPORTED, "polynomial model: the direct method needs an explicit CSR graph");
+        s->poly = true;
+        s->P = c->p;
+        s->pq = c->poly_q;
+        for (int k = 0; k <= c->p; k++) s->ph[k] = c->poly_h[k];
+        for (int k = 0; k <= c->poly_q; k++) s->pf[k] = c->poly_f[k];
+        // the zeroth moment of every row's partners (|S+| - |S-|) is always needed
+        s->d0 = 1.0;
+    }
     if (c->model == CIA_MODEL_PHASE) {
         if (c->p < 1 || c->p > PMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, PMAX);
         if (!c->d_sin || !c->d_cos) return set_error(CIA_EINVAL, "coupling.d_sin/d_cos are NULL");
@@ -1582,7 +1818,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     const bool keep = (o->flags & CIA_FLAG_KEEP_LABELS) != 0;
     const int64_t n = g->n;
     const size_t rs = f64 ? sizeof(double) : sizeof(float);
-    const int64_t zbytes = f64 ? 16 : 8;
+    // bytes per staged value: z for the phase models, x for the polynomial one
+    const int64_t zbytes = s->poly ? (int64_t)rs : (f64 ? 16 : 8);
 
     // LDS staging capacity (community z values, plus one zero slot); uint16
     // local indices also bound it (the padding index lambda must fit)
@@ -1713,6 +1950,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     }
     if (f64)
         for (Unit &u : units) u.flags &= ~UF_WIDE;   // FP64 plans compute everything in FP64
+    if (s->poly)
+        for (Unit &u : units) u.flags &= ~UF_WIDE;   // the polynomial moments are FP64 throughout
     for (const Unit &u : units)
         if (u.flags & UF_WIDE) s->has_wide = true;
     s->nunits = (int32_t)units.size();
@@ -1735,7 +1974,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     inf.wide_comms = s->direct ? 0 : wide;
     inf.method = o->method;
     inf.precision = o->precision;
-    inf.model = s->tri ? CIA_MODEL_TRIADIC : CIA_MODEL_PHASE;
+    inf.model = s->tri ? CIA_MODEL_TRIADIC : (s->poly ? CIA_MODEL_POLY : CIA_MODEL_PHASE);
     inf.p = s->P;
     inf.nnz_extra = nnz_tri;
     {
@@ -1745,7 +1984,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         // RK stage replaces "theta in / H out" by theta_n in plus acc in and
         // out.
         double idx = 2.0 * (double)nnz_neg_staged + 4.0 * (double)(nnz_neg - nnz_neg_staged) + 4.0 * (double)nnz_pos;
-        double zb = 2.0 * rs;
+        double zb = s->poly ? (double)rs : 2.0 * rs;   // staged and gathered value: z, or x
         inf.bytes_per_rhs = (3.0 * rs + 2.0 * zb) * (double)n + idx;
         inf.bytes_per_stage = (4.0 * rs + 2.0 * zb) * (double)n + idx;
         if (s->complete_direct) inf.bytes_per_rhs = inf.bytes_per_stage = (double)n * (2 * zb + 2 * rs);
@@ -1900,6 +2139,11 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
     a.tposdata = s->tposdata;
     a.h_extra = static_cast<const cx<R> *>(s->h_extra);
     a.K2n = (R)s->K2n;
+    for (int k = 0; k <= PMAX; k++) {
+        a.ph[k] = s->ph[k];
+        a.pf[k] = s->pf[k];
+    }
+    a.pq = s->pq;
     a.cnt = s->cnt;
     a.perm = s->perm;
     a.omega = static_cast<const R *>(s->omega);
@@ -1922,6 +2166,11 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
 template <typename R, int P, int BLOCK>
 static void launch_stage_v(PhaseState *s, const PhaseArgs<R> &a, hipStream_t st) {
     const dim3 g(s->nunits), b(BLOCK);
+    if (s->poly) {
+        if (s->direct) hipLaunchKernelGGL((poly_stage_kernel<R, P, BLOCK, true>), g, b, s->smem, st, a);
+        else hipLaunchKernelGGL((poly_stage_kernel<R, P, BLOCK, false>), g, b, s->smem, st, a);
+        return;
+    }
     if (s->tri) {
         if constexpr (P == 2) {
             if (s->direct) hipLaunchKernelGGL((phase_stage_kernel<R, 2, BLOCK, true, false, true>), g, b, s->smem, st, a);
