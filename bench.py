@@ -78,7 +78,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble", "triadic", "structured"],
+    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble", "triadic", "structured", "poly"],
                     help="large: the N = 1e6 Kuramoto bench line; flock, ensemble and triadic: the "
                          "Cucker-Smale, batched-ensemble and higher-order workloads (measurement modes, "
                          "not the bench line)")
@@ -132,6 +132,8 @@ def main():
         return bench_flock(args, cia, W, torch, np)
     if args.workload == "ensemble":
         return bench_ensemble(args, cia, W, torch, np)
+    if args.workload == "poly":
+        return bench_poly(args, cia, W, torch, np)
     if args.workload == "structured":
         return bench_structured(args, cia, W, torch, np)
     if args.workload == "triadic":
@@ -412,6 +414,53 @@ def bench_triadic(args, cia, W, torch, np):
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                            "traffic": None}
     print(json.dumps(out), flush=True)
+
+
+def bench_poly(args, cia, W, torch, np):
+    """Desai-Zwanzig dynamics (App. A.5: h(x) = x, f = x - x^3) and a cubic
+    difference coupling on the N = 1e6 power-law community graph of the phase
+    bench, FP32, RK4: CIA against the direct method on the same GPU."""
+    P = W.kuramoto_large()
+    g = P.graph
+    n = g.n
+    log("poly workload: n=%d nnz=%d communities=%d" % (n, g.nnz, g.ncomm))
+    x0 = np.random.default_rng(17).uniform(-1.5, 1.5, n).astype(np.float32)
+    res = {}
+    for name, h in (("dz", [0.0, 1.0]), ("cubic", [0.0, 1.0, 0.0, -0.2])):
+        for method in (cia.CIA_METHOD_CIA, cia.CIA_METHOD_DIRECT):
+            plan = cia.Plan.poly(n, g.row_ptr, g.col, g.labels, None, K=3.0, h=h, f=[0.0, 1.0, 0.0, -1.0],
+                                 method=method, flags=cia.CIA_FLAG_NO_VALIDATE)
+            info = plan.info()
+            steps = 50 if method == cia.CIA_METHOD_CIA else 5
+            x = torch.as_tensor(x0, device="cuda")
+            plan.integrate(x, 0.01, 2)
+            plan.set_timing(1)
+            plan.timing(reset=True)
+            ms = timed(torch, lambda s: plan.integrate(x, 0.01, steps, stream=s))
+            t = plan.timing(reset=True)
+            stage_us = 1e3 * t.stage_ms / max(t.stage_launches, 1)
+            key = "%s_%s" % (name, "cia" if method == cia.CIA_METHOD_CIA else "direct")
+            res[key] = {"ms_per_step": ms / steps, "value": n * 4 * steps / (ms / 1e3), "stage_us": round(stage_us, 2),
+                        "bytes_per_stage": info.bytes_per_stage,
+                        "achieved_gbs": round(info.bytes_per_stage / (stage_us * 1e-6) / 1e9, 1)}
+            log("%-12s %.4f ms/step, stage %.2f us, %.1f GB/s" % (key, ms / steps, stage_us,
+                                                                  res[key]["achieved_gbs"]))
+            plan.close()
+    dz = res["dz_cia"]
+    line = {
+        "metric": "Desai-Zwanzig RHS node-updates/s (CIA), 1 MI355X, N=1e6 community graph",
+        "value": dz["value"], "unit": "RHS node-updates/s", "n_gpus": 1, "steps": 50, "warmup": 2,
+        "ms_per_step": dz["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "poly_dz_n1e6", "n": n, "stepper": "rk4", "dt": 0.01},
+        "roofline": {"kernel": "poly_stage_kernel", "bound": "hbm", "achieved": dz["achieved_gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dz["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "methods": res,
+        "speedup_vs_direct": {k: res[k + "_direct"]["ms_per_step"] / res[k + "_cia"]["ms_per_step"]
+                              for k in ("dz", "cubic")},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def bench_structured(args, cia, W, torch, np):

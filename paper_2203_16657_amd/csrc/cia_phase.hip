@@ -756,7 +756,10 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
     for (int k = 0; k < P; k++) pd[k] = 0.0;
 
     const uint32_t padb = (uint32_t)lam * (uint32_t)sizeof(R);
+    const uint32_t pad16 = padb | (padb << 16);
+    const uint4 padl = make_uint4(pad16, pad16, pad16, pad16);
     const uint32_t pad = a.pad_pos;
+    const uint4 padp = make_uint4(pad, pad, pad, pad);
 
     for (int sl = Un.s0 + wid; sl < Un.s1; sl += NW) {
         const Slice S = a.slices[sl];
@@ -782,40 +785,76 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
         double Eh = 0.0;   // direct: sum of h(x_l - x_m)
         if (gather) {
             if (!DIRECT) {
+                // S-neg: up to UN chunks in flight (LDS gathers), or UGL (global gathers)
                 const uint4 *col = a.negdata + S.beg[0] + lane;
-                for (int k = 0; k < S.w[0]; k++) {
-                    const uint4 v = ld_stream(col + (size_t)k * SLICE);
-                    const uint32_t q4[4] = {v.x, v.y, v.z, v.w};
-                    if (staged) {
+                if (staged) {
+                    constexpr int UN = 8;
+                    for (int k = 0; k < S.w[0]; k += UN) {
+                        uint4 v[UN];
 #pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            acc_pow<R, P>(T, xat(xsh, q4[q] & 0xffffu), (R)-1);
-                            acc_pow<R, P>(T, xat(xsh, q4[q] >> 16), (R)-1);
+                        for (int u = 0; u < UN; u++) v[u] = k + u < S.w[0] ? ld_stream(col + (size_t)(k + u) * SLICE) : padl;
+#pragma unroll
+                        for (int u = 0; u < UN; u++) {
+                            const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                            for (int q = 0; q < 4; q++) {
+                                acc_pow<R, P>(T, xat(xsh, q4[q] & 0xffffu), (R)-1);
+                                acc_pow<R, P>(T, xat(xsh, q4[q] >> 16), (R)-1);
+                            }
                         }
-                    } else {
+                    }
+                } else {
+                    constexpr int UGL = 4;
+                    for (int k = 0; k < S.w[0]; k += UGL) {
+                        uint4 v[UGL];
 #pragma unroll
-                        for (int q = 0; q < 4; q++) acc_pow<R, P>(T, a.th_in[q4[q]], (R)-1);
+                        for (int u = 0; u < UGL; u++) v[u] = k + u < S.w[0] ? ld_stream(col + (size_t)(k + u) * SLICE) : padp;
+                        R xl[UGL][4];
+#pragma unroll
+                        for (int u = 0; u < UGL; u++) {
+                            xl[u][0] = a.th_in[v[u].x];
+                            xl[u][1] = a.th_in[v[u].y];
+                            xl[u][2] = a.th_in[v[u].z];
+                            xl[u][3] = a.th_in[v[u].w];
+                        }
+#pragma unroll
+                        for (int u = 0; u < UGL; u++)
+#pragma unroll
+                            for (int q = 0; q < 4; q++) acc_pow<R, P>(T, xl[u][q], (R)-1);
                     }
                 }
-                (void)padb;
             }
+            // S-pos (the whole adjacency for the direct method): UGP chunks in flight
+            constexpr int UGP = 4;
             const uint4 *col = a.posdata + S.beg[1] + lane;
-            for (int k = 0; k < S.w[1]; k++) {
-                const uint4 v = ld_stream(col + (size_t)k * SLICE);
-                const uint32_t q4[4] = {v.x, v.y, v.z, v.w};
+            for (int k = 0; k < S.w[1]; k += UGP) {
+                uint4 v[UGP];
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const R xl = a.th_in[q4[q]];   // the padding position holds 0
-                    if (DIRECT) {
-                        if (q4[q] != pad) {
-                            const R d = xl - xm;
-                            R hv = (R)a.ph[P];
+                for (int u = 0; u < UGP; u++) v[u] = k + u < S.w[1] ? ld_stream(col + (size_t)(k + u) * SLICE) : padp;
+                R xl[UGP][4];
 #pragma unroll
-                            for (int e = P - 1; e >= 0; e--) hv = hv * d + (R)a.ph[e];
-                            Eh += (double)hv;
+                for (int u = 0; u < UGP; u++) {
+                    xl[u][0] = a.th_in[v[u].x];   // the padding position holds 0
+                    xl[u][1] = a.th_in[v[u].y];
+                    xl[u][2] = a.th_in[v[u].z];
+                    xl[u][3] = a.th_in[v[u].w];
+                }
+#pragma unroll
+                for (int u = 0; u < UGP; u++) {
+                    const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        if (DIRECT) {
+                            if (q4[q] != pad) {
+                                const R d = xl[u][q] - xm;
+                                R hv = (R)a.ph[P];
+#pragma unroll
+                                for (int e = P - 1; e >= 0; e--) hv = hv * d + (R)a.ph[e];
+                                Eh += (double)hv;
+                            }
+                        } else {
+                            acc_pow<R, P>(T, xl[u][q], (R)1);
                         }
-                    } else {
-                        acc_pow<R, P>(T, xl, (R)1);
                     }
                 }
             }
