@@ -397,6 +397,23 @@ cia_status cia_fourier_coeffs(const double *samples, int64_t m, int32_t p, doubl
                               double *d_cos);
 
 /*
+ * Community labels for a graph that has none (P1, Sec. 3.1 leaves the
+ * detection method open), chosen to minimise the work of one CIA right-hand
+ * side: nnz(S-neg) + nnz(S-pos) + dense_alpha * (members of kept communities),
+ * which P1's cost rule (see cia_options.dense_alpha) also uses.  Louvain-style
+ * local moving and aggregation, sequential and deterministic; communities
+ * that the cost rule would dissolve, and single nodes, get label -1.  Host
+ * only (no device is used).
+ *  g           : CSR graph (validated like cia_build); COMPLETE, RANK1, RING: CIA_EUNSUPPORTED
+ *  init_labels : host [n] starting partition to refine (-1 = on its own), or NULL (singletons)
+ *  dense_alpha : >= 0; 2 is cia_options_default's value
+ *  labels      : host [n], written: dense ids 0..C-1 in order of first member, or -1
+ *  work        : optional, written: the work of the result (the minimised sum)
+ */
+cia_status cia_detect_communities(const cia_graph *g, const int32_t *init_labels, double dense_alpha,
+                                  int32_t *labels, double *work);
+
+/*
  * P1 alone, on the host (Sec. 3.1 / App. A.1), for inspection and tests.
  * cia_p1_build runs validation, the cost rule, the permutation and the
  * construction of S exactly as cia_build does.

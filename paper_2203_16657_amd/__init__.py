@@ -84,7 +84,7 @@ EXPORTS = ["cia_build", "cia_rhs", "cia_integrate", "cia_destroy", "cia_last_err
            "cia_fourier_coeffs", "cia_p1_build", "cia_p1_sizes", "cia_p1_export", "cia_p1_free",
            "cia_abi_sizeof", "cia_basis_param_count", "cia_basis_set_params", "cia_basis_get_params",
            "cia_basis_train", "cia_basis_loss_grad", "cia_basis_features", "cia_build_batch",
-           "cia_batch_offsets", "cia_autotune", "cia_plan_set_timing"]
+           "cia_batch_offsets", "cia_autotune", "cia_plan_set_timing", "cia_detect_communities"]
 
 _lib = None
 
@@ -126,6 +126,8 @@ def load():
     lib.cia_fourier_coeffs.argtypes = [_vp, _c.c_int64, _c.c_int32, _vp, _vp]
     lib.cia_p1_build.restype = _c.c_int
     lib.cia_p1_build.argtypes = [P(cia_graph), _vp, P(cia_options), P(_vp)]
+    lib.cia_detect_communities.restype = _c.c_int
+    lib.cia_detect_communities.argtypes = [P(cia_graph), _vp, _c.c_double, _vp, P(_c.c_double)]
     lib.cia_p1_sizes.restype = _c.c_int
     lib.cia_p1_sizes.argtypes = [_vp, _vp]
     lib.cia_p1_export.restype = _c.c_int
@@ -286,6 +288,21 @@ def cia_p1(n, row_ptr, col, labels=None, options=None, complete=False):
         return out
     finally:
         lib.cia_p1_free(h)
+
+
+def detect_communities(n, row_ptr, col, init_labels=None, dense_alpha=2.0):
+    """Community labels minimising the work of one CIA right-hand side (host
+    only).  Returns (labels int32 [n], -1 = no community; work)."""
+    lib = load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    g = cia_graph(n=int(n), kind=CIA_GRAPH_CSR, reserved=0, row_ptr=_np_ptr(rp), col=_np_ptr(cl))
+    init = None if init_labels is None else np.ascontiguousarray(init_labels, dtype=np.int32)
+    labels = np.empty(int(n), dtype=np.int32)
+    work = _c.c_double(0.0)
+    _check(lib.cia_detect_communities(_c.byref(g), _np_ptr(init), float(dense_alpha), _np_ptr(labels),
+                                      _c.byref(work)))
+    return labels, float(work.value)
 
 
 # ---------------------------------------------------------------------------

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libcia.so")
 
-SOURCES = ["cia_host.cpp", "cia_api.cpp", "cia_phase.hip", "cia_flock.hip", "cia_batch.cpp", "cia_struct.hip"]
+SOURCES = ["cia_host.cpp", "cia_api.cpp", "cia_phase.hip", "cia_flock.hip", "cia_batch.cpp", "cia_struct.hip", "cia_detect.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -280,3 +280,22 @@ def test_full_size_sampled_rows(env):
             # the remainder has the size the workload recipe implies
             assert 5.5e7 < info.nnz_neg < 7.5e7
             assert 4.5e6 < info.nnz_pos < 5.5e6
+
+
+def test_plan_from_detected_communities(env):
+    """Labels from cia_detect_communities (no planted labels used) give a CIA
+    plan whose RHS matches the oracle."""
+    cia, torch = env
+    P = W.scaled_kuramoto(20000, seed=12, hi=1000)
+    g = P.graph
+    lab, work = cia.detect_communities(g.n, g.row_ptr, g.col)
+    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, lab, None, K=P.K)
+    th = torch.as_tensor(P.theta0.astype(np.float32), device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    want = oracle.phase_rhs(g.n, g.row_ptr, g.col, None, P.K, [0, 1], [0, 0], th.cpu().numpy().astype(np.float64))
+    err = rel_inf(out.cpu().numpy().astype(np.float64), want)
+    say("detected communities", plan.info().ncomm, "work", work, "rel_inf", err)
+    assert plan.info().ncomm == len(np.unique(lab[lab >= 0])) and err < TOL32
+    plan.close()
