@@ -103,6 +103,9 @@ def _load():
         lib.oracle_poly_integrate.restype = ctypes.c_int
         lib.oracle_poly_integrate.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp, ctypes.c_int,
                                               _vp, _vp, d, i64, ctypes.c_int]
+        lib.oracle_phase_rhs_general.restype = None
+        lib.oracle_phase_rhs_general.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp, _vp,
+                                                 _vp, _vp, _vp, _vp, i64, _vp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -149,6 +152,24 @@ def phase_rhs(n, row_ptr, col, omega, K, d_sin, d_cos, theta, rows=None, complet
     out = np.empty(cnt, dtype=np.float64)
     lib.oracle_phase_rhs(n, _p(rp), _p(cl), int(bool(complete)), _p(omega), float(K), p, _p(d_sin),
                          _p(d_cos), _p(theta), _p(rws), 0 if rws is None else len(rws), _p(out))
+    return out
+
+
+def phase_rhs_general(n, row_ptr, col, omega, K, c11, c12, c21, c22, theta, rows=None, complete=False):
+    """H_m = omega_m + (K/N) sum_l a_ml g(theta_l, theta_m) with g the real
+    2-D Fourier series of App. A.2 (eq. FourierRealExpansion); c.. are
+    (p+1) x (p+1) arrays, row = partner harmonic, column = own harmonic."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    cs = [np.ascontiguousarray(c, dtype=np.float64) for c in (c11, c12, c21, c22)]
+    p = cs[0].shape[0] - 1
+    assert all(c.shape == (p + 1, p + 1) for c in cs)
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    out = np.empty(cnt, dtype=np.float64)
+    lib.oracle_phase_rhs_general(int(n), _p(rp), _p(cl), int(bool(complete)), _p(_f64(omega)), float(K), p,
+                                 *[_p(c) for c in cs], _p(_f64(theta)), _p(rws), 0 if rws is None else len(rws),
+                                 _p(out))
     return out
 
 

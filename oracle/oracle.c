@@ -363,3 +363,49 @@ void oracle_set_num_threads(int t) {
     (void)t;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* phase model with a general (non-difference) coupling                */
+/* ------------------------------------------------------------------ */
+
+/*
+ * g(x, y) as the real two-dimensional Fourier series of App. A.2 (eq.
+ * FourierRealExpansion, period 2 pi): for partner phase x and own phase y,
+ *   g = sum_{a,b=0..p} c11[a][b] cos(a x) cos(b y) + c12[a][b] cos(a x) sin(b y)
+ *                    + c21[a][b] sin(a x) cos(b y) + c22[a][b] sin(a x) sin(b y),
+ * coefficient arrays row-major [(p+1)*(p+1)].
+ */
+static double g_eval(int p, const double *c11, const double *c12, const double *c21, const double *c22,
+                     double x, double y) {
+    double v = 0.0;
+    for (int a = 0; a <= p; a++)
+        for (int b = 0; b <= p; b++) {
+            const int i = a * (p + 1) + b;
+            v += c11[i] * cos(a * x) * cos(b * y) + c12[i] * cos(a * x) * sin(b * y) +
+                 c21[i] * sin(a * x) * cos(b * y) + c22[i] * sin(a * x) * sin(b * y);
+        }
+    return v;
+}
+
+/* H_m = omega_m + (K/N) sum_l a_ml g(theta_l, theta_m); complete != 0:
+   a_ml = 1 for l != m. */
+void oracle_phase_rhs_general(int64_t n, const int64_t *rp, const int32_t *col, int complete,
+                              const double *omega, double K, int p, const double *c11, const double *c12,
+                              const double *c21, const double *c22, const double *theta, const int64_t *rows,
+                              int64_t nrows, double *out) {
+    int64_t cnt = rows ? nrows : n;
+    double scale = K / (double)n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < cnt; r++) {
+        int64_t m = rows ? rows[r] : r;
+        double acc = 0.0;
+        if (complete) {
+            for (int64_t l = 0; l < n; l++)
+                if (l != m) acc += g_eval(p, c11, c12, c21, c22, theta[l], theta[m]);
+        } else {
+            for (int64_t e = rp[m]; e < rp[m + 1]; e++)
+                acc += g_eval(p, c11, c12, c21, c22, theta[col[e]], theta[m]);
+        }
+        out[r] = (omega ? omega[m] : 0.0) + scale * acc;
+    }
+}
