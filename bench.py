@@ -78,7 +78,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble", "triadic", "structured", "poly"],
+    ap.add_argument("--workload", default="large", choices=["large", "small", "flock", "ensemble", "triadic", "structured", "poly", "general"],
                     help="large: the N = 1e6 Kuramoto bench line; flock, ensemble and triadic: the "
                          "Cucker-Smale, batched-ensemble and higher-order workloads (measurement modes, "
                          "not the bench line)")
@@ -132,6 +132,8 @@ def main():
         return bench_flock(args, cia, W, torch, np)
     if args.workload == "ensemble":
         return bench_ensemble(args, cia, W, torch, np)
+    if args.workload == "general":
+        return bench_general(args, cia, W, torch, np)
     if args.workload == "poly":
         return bench_poly(args, cia, W, torch, np)
     if args.workload == "structured":
@@ -414,6 +416,50 @@ def bench_triadic(args, cia, W, torch, np):
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                            "traffic": None}
     print(json.dumps(out), flush=True)
+
+
+def bench_general(args, cia, W, torch, np):
+    """A general (non-difference) phase coupling, the real 2-D Fourier series
+    of App. A.2 with p = 2 and seeded coefficients, on the N = 1e6 power-law
+    community graph of the phase bench, FP32, RK4: CIA against the direct
+    method on the same GPU."""
+    P = W.kuramoto_large()
+    g = P.graph
+    n = g.n
+    rng = np.random.default_rng(23)
+    cs = [rng.normal(size=(3, 3)) / 3.0 for _ in range(4)]
+    log("general-coupling workload: n=%d nnz=%d communities=%d p=2" % (n, g.nnz, g.ncomm))
+    th0 = P.theta0.astype(np.float32)
+    res = {}
+    for name, method, steps in (("cia", cia.CIA_METHOD_CIA, 50), ("direct", cia.CIA_METHOD_DIRECT, 5)):
+        plan = cia.Plan.phase(n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, gen=cs, method=method,
+                              flags=cia.CIA_FLAG_NO_VALIDATE)
+        info = plan.info()
+        th = torch.as_tensor(th0, device="cuda")
+        plan.integrate(th, P.dt, 2)
+        plan.set_timing(1)
+        plan.timing(reset=True)
+        ms = timed(torch, lambda s: plan.integrate(th, P.dt, steps, stream=s))
+        t = plan.timing(reset=True)
+        stage_us = 1e3 * t.stage_ms / max(t.stage_launches, 1)
+        res[name] = {"ms_per_step": ms / steps, "value": n * 4 * steps / (ms / 1e3), "stage_us": round(stage_us, 2),
+                     "bytes_per_stage": info.bytes_per_stage,
+                     "achieved_gbs": round(info.bytes_per_stage / (stage_us * 1e-6) / 1e9, 1)}
+        log("%-7s %.4f ms/step, stage %.2f us, %.1f GB/s" % (name, ms / steps, stage_us, res[name]["achieved_gbs"]))
+        plan.close()
+    c = res["cia"]
+    line = {
+        "metric": "general-coupling RHS node-updates/s (CIA), 1 MI355X, N=1e6 community graph",
+        "value": c["value"], "unit": "RHS node-updates/s", "n_gpus": 1, "steps": 50, "warmup": 2,
+        "ms_per_step": c["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "general_p2_n1e6", "n": n, "stepper": "rk4", "dt": P.dt},
+        "roofline": {"kernel": "phase_stage_kernel (general)", "bound": "hbm", "achieved": c["achieved_gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(c["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "methods": res, "speedup_vs_direct": res["direct"]["ms_per_step"] / c["ms_per_step"],
+    }
+    print(json.dumps(line), flush=True)
 
 
 def bench_poly(args, cia, W, torch, np):

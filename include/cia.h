@@ -161,6 +161,15 @@ typedef struct cia_coupling {
     int32_t reserved2;
     const double *poly_h;      /* polynomial model: host [p+1] coefficients h_0..h_p of h, p = 1..8 */
     const double *poly_f;      /* polynomial model: host [poly_q+1] coefficients f_0..f_q of f */
+    /* phase model, optional: a general coupling g(theta_l, theta_m) as the real
+       2-D Fourier series of App. A.2 (eq. FourierRealExpansion):
+         g = sum_{a,b=0..p} c11[a][b] cos(a theta_l) cos(b theta_m) + c12[a][b] cos(a theta_l) sin(b theta_m)
+                          + c21[a][b] sin(a theta_l) cos(b theta_m) + c22[a][b] sin(a theta_l) sin(b theta_m);
+       host [(p+1)*(p+1)] each (p = 1..4), row a, column b.  All four set: they define the
+       coupling and d_sin/d_cos are ignored; all NULL: the difference form.
+       CSR or complete graphs, CIA or direct (not the all-to-all direct kernel),
+       not batched. */
+    const double *gen_c11, *gen_c12, *gen_c21, *gen_c22;
 } cia_coupling;
 
 typedef struct cia_options {

@@ -49,7 +49,8 @@ class cia_coupling(_c.Structure):
                 ("cs_K", _c.c_double), ("cs_sigma", _c.c_double), ("cs_beta", _c.c_double),
                 ("cs_L", _c.c_double), ("cs_basis", _c.c_int32), ("rank", _c.c_int32),
                 ("train_iters", _c.c_int32), ("reserved", _c.c_int32), ("poly_q", _c.c_int32),
-                ("reserved2", _c.c_int32), ("poly_h", _vp), ("poly_f", _vp)]
+                ("reserved2", _c.c_int32), ("poly_h", _vp), ("poly_f", _vp), ("gen_c11", _vp), ("gen_c12", _vp),
+                ("gen_c21", _vp), ("gen_c22", _vp)]
 
 
 class cia_options(_c.Structure):
@@ -412,7 +413,10 @@ class Plan:
     @classmethod
     def phase(cls, n, row_ptr=None, col=None, labels=None, omega=None, K=1.0, d_sin=(0.0, 1.0),
               d_cos=(0.0, 0.0), method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4,
-              flags=0, complete=False, unit_work=0, block=0, dense_alpha=2.0, device=-1):
+              flags=0, complete=False, unit_work=0, block=0, dense_alpha=2.0, device=-1, gen=None):
+        """gen: optional (c11, c12, c21, c22), (p+1) x (p+1) arrays of a general
+        coupling g(theta_l, theta_m) (App. A.2 real 2-D series); then d_sin and
+        d_cos are not used."""
         load()
         rp = None if complete else np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = None if complete else np.ascontiguousarray(col, dtype=np.int32)
@@ -426,6 +430,11 @@ class Plan:
         c.d_sin = _np_ptr(ds)
         c.d_cos = _np_ptr(dc)
         c.K = float(K)
+        if gen is not None:
+            gc = [np.ascontiguousarray(x, dtype=np.float64) for x in gen]
+            c.p = gc[0].shape[0] - 1
+            assert all(x.shape == (c.p + 1, c.p + 1) for x in gc)
+            c.gen_c11, c.gen_c12, c.gen_c21, c.gen_c22 = (_np_ptr(x) for x in gc)
         o = cia_options_default()
         o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
         o.unit_work, o.block, o.dense_alpha, o.device = unit_work, block, dense_alpha, device

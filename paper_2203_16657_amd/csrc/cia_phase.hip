@@ -47,6 +47,7 @@ namespace cia {
 constexpr int PMAX = 8;
 constexpr double WIDE_COMMUNITY = 1e5;   // FP64 observables above this size
 constexpr size_t LDS_BYTES = 64 * 1024;  // dynamic LDS budget of a stage block
+constexpr int GEN_PMAX = 4;              // largest order of the general (non-difference) coupling
 constexpr int SLICE = 64;                // rows per slice = lanes per wavefront
 
 // unit flag bits
@@ -173,6 +174,7 @@ struct PhaseArgs {
     R K2n;                    // triadic strength K2 / N^2
     R dsin[PMAX + 1], dcos[PMAX + 1];
     double ph[PMAX + 1], pf[PMAX + 1];   // polynomial model: h and f coefficients
+    const R *gen;             // general coupling: c11, c12, c21, c22, each [(P+1)^2]; NULL = difference form
     int32_t pq;
     int32_t stage, mode, want_r, lds_cap;
     uint32_t pad_pos;         // position whose z is 0 (= n): target of padded int32 entries
@@ -369,12 +371,55 @@ __device__ __forceinline__ cx<R> gather_pairs(const uint4 *__restrict__ col, int
     return M;
 }
 
+// General coupling (App. A.2, eq. FourierRealExpansion): sum over partners
+// of g(theta_l, theta_m) from the partner harmonics C_a = sum cos(a theta_l),
+// S_a = sum sin(a theta_l) (C_0 = M0, the partner count) and this node's
+// cos/sin(b theta_m); for an assigned row the l = m term that the community
+// sums include is removed.
+template <typename T, int P>
+__device__ __forceinline__ T gen_sum(const float *gf, const double *gd, const T (&C)[P + 1], const T (&Sn)[P + 1],
+                                     cx<T> z, bool self) {
+    constexpr int NP = (P + 1) * (P + 1);
+    T cb[P + 1], sb[P + 1];
+    cb[0] = (T)1;
+    sb[0] = (T)0;
+    cx<T> zk = z;
+#pragma unroll
+    for (int b = 1; b <= P; b++) {
+        cb[b] = zk.x;
+        sb[b] = zk.y;
+        if (b < P) zk = cmul(zk, z);
+    }
+    T s = (T)0, own = (T)0;
+#pragma unroll
+    for (int a = 0; a <= P; a++)
+#pragma unroll
+        for (int b = 0; b <= P; b++) {
+            const int i = a * (P + 1) + b;
+            const T c11 = gf ? (T)gf[i] : (T)gd[i], c12 = gf ? (T)gf[NP + i] : (T)gd[NP + i];
+            const T c21 = gf ? (T)gf[2 * NP + i] : (T)gd[2 * NP + i], c22 = gf ? (T)gf[3 * NP + i] : (T)gd[3 * NP + i];
+            s += (c11 * C[a] + c21 * Sn[a]) * cb[b] + (c12 * C[a] + c22 * Sn[a]) * sb[b];
+            if (self) own += (c11 * cb[a] + c21 * sb[a]) * cb[b] + (c12 * cb[a] + c22 * sb[a]) * sb[b];
+        }
+    return s - own;
+}
+template <typename R>
+__device__ __forceinline__ const float *gen_f(const R *g) {
+    if constexpr (sizeof(R) == 4) return reinterpret_cast<const float *>(g);
+    else return nullptr;
+}
+template <typename R>
+__device__ __forceinline__ const double *gen_d(const R *g) {
+    if constexpr (sizeof(R) == 8) return reinterpret_cast<const double *>(g);
+    else return nullptr;
+}
+
 // DIRECT: every row is an outside row with its whole adjacency in the +1
 // list (no observables, no staging).  WIDE: the FP64 path of very large
 // communities is compiled in (F32 plans that have such communities).
 // TRI: the triadic term of the higher-order model (P = 2 observables give
 // S1 = sum z and S2 = sum z^2 per community).
-template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE, bool TRI>
+template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE, bool TRI, bool GEN = false>
 __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     constexpr int NW = BLOCK / 64;
     constexpr int UL = P >= 4 ? 2 : 8 / P;  // chunks per batch, LDS-gathered rows
@@ -503,15 +548,27 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                 if (!wide) {
                     cx<R> z = staged ? zsh[i - off] : a.cs_in[i];
                     R s = (R)0;
-                    if (a.d0 != (R)0) s = a.d0 * ((assigned ? (R)lam : (R)0) + (R)cv);
-                    if (assigned) s -= a.hzero;
-                    cx<R> zk = z;
+                    if constexpr (GEN) {
+                        R Cg[P + 1], Sg[P + 1];
+                        Cg[0] = (assigned ? (R)lam : (R)0) + (R)cv;
+                        Sg[0] = (R)0;
 #pragma unroll
-                    for (int k = 0; k < P; k++) {
-                        cx<R> A = {qx[k] + T[k].x, qy[k] + T[k].y};
-                        cx<R> B = cmul(A, cx<R>{zk.x, -zk.y});
-                        s += a.dcos[k + 1] * B.x + a.dsin[k + 1] * B.y;
-                        if (k + 1 < P) zk = cmul(zk, z);
+                        for (int k = 0; k < P; k++) {
+                            Cg[k + 1] = qx[k] + T[k].x;
+                            Sg[k + 1] = qy[k] + T[k].y;
+                        }
+                        s = gen_sum<R, P>(gen_f(a.gen), gen_d(a.gen), Cg, Sg, z, assigned);
+                    } else {
+                        if (a.d0 != (R)0) s = a.d0 * ((assigned ? (R)lam : (R)0) + (R)cv);
+                        if (assigned) s -= a.hzero;
+                        cx<R> zk = z;
+#pragma unroll
+                        for (int k = 0; k < P; k++) {
+                            cx<R> A = {qx[k] + T[k].x, qy[k] + T[k].y};
+                            cx<R> B = cmul(A, cx<R>{zk.x, -zk.y});
+                            s += a.dcos[k + 1] * B.x + a.dsin[k + 1] * B.y;
+                            if (k + 1 < P) zk = cmul(zk, z);
+                        }
                     }
                     H = om + knv * s;
                     if constexpr (TRI && P >= 2) {
@@ -541,15 +598,27 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                     sincos((double)thc, &zs, &zc0);
                     cx<double> z = {zc0, zs};
                     double s = 0.0;
-                    if (a.d0 != (R)0) s = (double)a.d0 * ((double)lam + (double)cv);
-                    s -= (double)a.hzero;
-                    cx<double> zk = z;
+                    if constexpr (GEN) {
+                        double Cg[P + 1], Sg[P + 1];
+                        Cg[0] = (double)lam + (double)cv;
+                        Sg[0] = 0.0;
 #pragma unroll
-                    for (int k = 0; k < P; k++) {
-                        cx<double> A = {qdx[k] + (double)T[k].x, qdy[k] + (double)T[k].y};
-                        cx<double> B = cmul(A, cx<double>{zk.x, -zk.y});
-                        s += (double)a.dcos[k + 1] * B.x + (double)a.dsin[k + 1] * B.y;
-                        if (k + 1 < P) zk = cmul(zk, z);
+                        for (int k = 0; k < P; k++) {
+                            Cg[k + 1] = qdx[k] + (double)T[k].x;
+                            Sg[k + 1] = qdy[k] + (double)T[k].y;
+                        }
+                        s = gen_sum<double, P>(gen_f(a.gen), gen_d(a.gen), Cg, Sg, z, true);
+                    } else {
+                        if (a.d0 != (R)0) s = (double)a.d0 * ((double)lam + (double)cv);
+                        s -= (double)a.hzero;
+                        cx<double> zk = z;
+#pragma unroll
+                        for (int k = 0; k < P; k++) {
+                            cx<double> A = {qdx[k] + (double)T[k].x, qdy[k] + (double)T[k].y};
+                            cx<double> B = cmul(A, cx<double>{zk.x, -zk.y});
+                            s += (double)a.dcos[k + 1] * B.x + (double)a.dsin[k + 1] * B.y;
+                            if (k + 1 < P) zk = cmul(zk, z);
+                        }
                     }
                     H = (R)((double)om + (double)knv * s);
                 }
@@ -1322,6 +1391,7 @@ struct PhaseState {
     bool has_wide = false;   // F32 plan with at least one FP64-observable community
     bool tri = false;        // triadic model
     bool poly = false;       // polynomial difference coupling
+    void *gen = nullptr;     // general coupling coefficients on the device (R), or NULL
     int pq = -1;             // degree of the local polynomial f (-1: none)
     double ph[PMAX + 1] = {0}, pf[PMAX + 1] = {0};   // coefficients of h and f
     double K2n = 0;
@@ -1811,19 +1881,54 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         // the zeroth moment of every row's partners (|S+| - |S-|) is always needed
         s->d0 = 1.0;
     }
+    const bool gen = c->model == CIA_MODEL_PHASE && (c->gen_c11 || c->gen_c12 || c->gen_c21 || c->gen_c22);
     if (c->model == CIA_MODEL_PHASE) {
         if (c->p < 1 || c->p > PMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, PMAX);
-        if (!c->d_sin || !c->d_cos) return set_error(CIA_EINVAL, "coupling.d_sin/d_cos are NULL");
-        for (int k = 0; k <= c->p; k++)
-            if (!std::isfinite(c->d_sin[k]) || !std::isfinite(c->d_cos[k]))
-                return set_error(CIA_EINVAL, "coupling coefficients must be finite");
+        if (!gen) {
+            if (!c->d_sin || !c->d_cos) return set_error(CIA_EINVAL, "coupling.d_sin/d_cos are NULL");
+            for (int k = 0; k <= c->p; k++)
+                if (!std::isfinite(c->d_sin[k]) || !std::isfinite(c->d_cos[k]))
+                    return set_error(CIA_EINVAL, "coupling coefficients must be finite");
+            s->d0 = c->d_cos[0];
+            s->hzero = c->d_cos[0];
+            for (int k = 1; k <= c->p; k++) {
+                s->dsin[k] = c->d_sin[k];
+                s->dcos[k] = c->d_cos[k];
+                s->hzero += c->d_cos[k];
+            }
+        }
         s->P = c->p;
-        s->d0 = c->d_cos[0];
-        s->hzero = c->d_cos[0];
-        for (int k = 1; k <= c->p; k++) {
-            s->dsin[k] = c->d_sin[k];
-            s->dcos[k] = c->d_cos[k];
-            s->hzero += c->d_cos[k];
+        if (gen) {
+            if (c->p > GEN_PMAX)
+                return set_error(CIA_EUNSUPPORTED, "general coupling: order p = %d; supported 1..%d", c->p, GEN_PMAX);
+            if (!c->gen_c11 || !c->gen_c12 || !c->gen_c21 || !c->gen_c22)
+                return set_error(CIA_EINVAL, "general coupling: set all of gen_c11, gen_c12, gen_c21, gen_c22");
+            const int np = (c->p + 1) * (c->p + 1);
+            for (int i = 0; i < np; i++)
+                if (!std::isfinite(c->gen_c11[i]) || !std::isfinite(c->gen_c12[i]) || !std::isfinite(c->gen_c21[i]) ||
+                    !std::isfinite(c->gen_c22[i]))
+                    return set_error(CIA_EINVAL, "general coupling coefficients must be finite");
+            if (g->kind == CIA_GRAPH_COMPLETE && o->method == CIA_METHOD_DIRECT)
+                return set_error(CIA_EUNSUPPORTED, "general coupling: the direct method needs an explicit CSR graph");
+            if (bs) return set_error(CIA_EUNSUPPORTED, "general coupling: ensembles are not batched");
+            std::vector<double> gh(4 * (size_t)np);
+            for (int i = 0; i < np; i++) {
+                gh[i] = c->gen_c11[i];
+                gh[np + i] = c->gen_c12[i];
+                gh[2 * np + i] = c->gen_c21[i];
+                gh[3 * np + i] = c->gen_c22[i];
+            }
+            if (o->precision == CIA_F64) {
+                double *d;
+                CIA_TRY(dupload(p, &d, gh.data(), gh.size()));
+                s->gen = d;
+            } else {
+                std::vector<float> gf(gh.begin(), gh.end());
+                float *d;
+                CIA_TRY(dupload(p, &d, gf.data(), gf.size()));
+                s->gen = d;
+            }
+            s->d0 = 1.0;   // the partner counts are always needed
         }
     }
     s->K = c->K;
@@ -2183,6 +2288,7 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
         a.pf[k] = s->pf[k];
     }
     a.pq = s->pq;
+    a.gen = static_cast<const R *>(s->gen);
     a.cnt = s->cnt;
     a.perm = s->perm;
     a.omega = static_cast<const R *>(s->omega);
@@ -2216,6 +2322,19 @@ static void launch_stage_v(PhaseState *s, const PhaseArgs<R> &a, hipStream_t st)
             else hipLaunchKernelGGL((phase_stage_kernel<R, 2, BLOCK, false, false, true>), g, b, s->smem, st, a);
         }
         return;
+    }
+    if constexpr (P <= GEN_PMAX) {
+      if (s->gen) {
+        // general (non-difference) coupling: its own instantiations, so the
+        // difference form keeps its register budget
+        if (s->direct)
+            hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, true, false, false, true>), g, b, s->smem, st, a);
+        else if (sizeof(R) == 4 && s->has_wide)
+            hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, true, false, true>), g, b, s->smem, st, a);
+        else
+            hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, false, false, true>), g, b, s->smem, st, a);
+        return;
+      }
     }
     if (s->direct)
         hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, true, false, false>), g, b, s->smem, st, a);

@@ -539,6 +539,8 @@ cia_status struct_build(cia_plan *p, const cia_graph *g, const int32_t *labels, 
     if (c->model != CIA_MODEL_PHASE)
         return set_error(CIA_EUNSUPPORTED, "rank-one and ring graphs take the phase model only");
     if (labels) return set_error(CIA_EINVAL, "rank-one and ring graphs take no community labels (pass NULL)");
+    if (c->gen_c11 || c->gen_c12 || c->gen_c21 || c->gen_c22)
+        return set_error(CIA_EUNSUPPORTED, "rank-one and ring graphs take the difference form of the coupling");
     if (c->p < 1 || c->p > SPMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, SPMAX);
     if (!c->d_sin || !c->d_cos) return set_error(CIA_EINVAL, "coupling.d_sin/d_cos are NULL");
     for (int k = 0; k <= c->p; k++)
