@@ -106,6 +106,9 @@ def _load():
         lib.oracle_phase_rhs_general.restype = None
         lib.oracle_phase_rhs_general.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp, _vp,
                                                  _vp, _vp, _vp, _vp, i64, _vp]
+        lib.oracle_poly_rhs_general.restype = None
+        lib.oracle_poly_rhs_general.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp,
+                                                ctypes.c_int, _vp, _vp, _vp, i64, _vp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -255,6 +258,23 @@ def poly_rhs(n, row_ptr, col, omega, K, h, f, x, rows=None, complete=False):
     out = np.empty(cnt, dtype=np.float64)
     lib.oracle_poly_rhs(int(n), _p(rp), _p(cl), int(bool(complete)), _p(_f64(omega)), float(K), len(h) - 1, _p(h),
                         fq, _p(_f64(f)), _p(_f64(x)), _p(rws), 0 if rws is None else len(rws), _p(out))
+    return out
+
+
+def poly_rhs_general(n, row_ptr, col, omega, K, c, f, x, rows=None, complete=False):
+    """x_m' = omega_m + f(x_m) + (K/N) sum_l a_ml g(x_l, x_m), g(x, y) =
+    sum_{a,b} c[a, b] x^a y^b (App. A.3, eq. PolyApprox); c is (p+1) x (p+1)."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    p = c.shape[0] - 1
+    assert c.shape == (p + 1, p + 1)
+    fq = -1 if f is None else len(f) - 1
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    out = np.empty(cnt, dtype=np.float64)
+    lib.oracle_poly_rhs_general(int(n), _p(rp), _p(cl), int(bool(complete)), _p(_f64(omega)), float(K), p, _p(c),
+                                fq, _p(_f64(f)), _p(_f64(x)), _p(rws), 0 if rws is None else len(rws), _p(out))
     return out
 
 

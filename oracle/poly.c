@@ -69,3 +69,39 @@ int oracle_poly_integrate(int64_t n, const int64_t *rp, const int32_t *col, int 
     free(k1); free(k2); free(k3); free(k4); free(tmp);
     return 0;
 }
+
+/* General polynomial coupling (App. A.3, eq. PolyApprox): g(x, y) =
+   sum_{a,b=0..p} c[a][b] x^a y^b for partner value x and own value y
+   (row-major [(p+1)*(p+1)]), instead of h(x - y). */
+static double g_poly(int p, const double *c, double x, double y) {
+    double v = 0.0;
+    double xa = 1.0;
+    for (int a = 0; a <= p; a++) {
+        double yb = 1.0;
+        for (int b = 0; b <= p; b++) {
+            v += c[a * (p + 1) + b] * xa * yb;
+            yb *= y;
+        }
+        xa *= x;
+    }
+    return v;
+}
+
+void oracle_poly_rhs_general(int64_t n, const int64_t *rp, const int32_t *col, int complete, const double *omega,
+                             double K, int p, const double *c, int q, const double *f, const double *x,
+                             const int64_t *rows, int64_t nrows, double *out) {
+    const int64_t cnt = rows ? nrows : n;
+    const double scale = K / (double)n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < cnt; r++) {
+        const int64_t m = rows ? rows[r] : r;
+        double acc = 0.0;
+        if (complete) {
+            for (int64_t l = 0; l < n; l++)
+                if (l != m) acc += g_poly(p, c, x[l], x[m]);
+        } else {
+            for (int64_t e = rp[m]; e < rp[m + 1]; e++) acc += g_poly(p, c, x[col[e]], x[m]);
+        }
+        out[r] = (omega ? omega[m] : 0.0) + (q >= 0 && f ? horner(q, f, x[m]) : 0.0) + scale * acc;
+    }
+}

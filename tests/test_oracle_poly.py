@@ -103,3 +103,44 @@ def test_frequencies_and_local_term_add():
     base = oracle.poly_rhs(n, rp, col, None, 2.0, [0.1, 1.0, 0.3], None, x)
     full = oracle.poly_rhs(n, rp, col, om, 2.0, [0.1, 1.0, 0.3], f, x)
     assert rel(full - base, om + f[0] + f[1] * x + f[2] * x * x) < 1e-13
+
+
+def test_general_polynomial_reduces_to_the_difference_form():
+    """h(x - y) = sum_a h_a (x - y)^a expands to c[i, j] = h_{i+j} C(i+j, i) (-1)^j."""
+    rng = np.random.default_rng(30)
+    n, p, K = 70, 3, 2.0
+    A, rp, col = random_graph(n, 0.25, 31)
+    h = rng.normal(size=p + 1)
+    c = np.zeros((p + 1, p + 1))
+    for i in range(p + 1):
+        for j in range(p + 1 - i):
+            c[i, j] = h[i + j] * math.comb(i + j, i) * (-1) ** j
+    x = rng.uniform(-1, 1, n)
+    got = oracle.poly_rhs_general(n, rp, col, None, K, c, None, x)
+    assert rel(got, oracle.poly_rhs(n, rp, col, None, K, h, None, x)) < 1e-12
+
+
+def test_general_polynomial_moment_form():
+    """App. A.3 eq. PolyRHS on the complete graph: sum_{l != m} g(x_l, x_m) =
+    sum_{a,b} c[a, b] W_a x_m^b - g(x_m, x_m), W_a = sum_l x_l^a."""
+    rng = np.random.default_rng(32)
+    n, p, K = 200, 3, 1.5
+    c = rng.normal(size=(p + 1, p + 1))
+    x = rng.uniform(-1.2, 1.2, n)
+    got = oracle.poly_rhs_general(n, None, None, None, K, c, None, x, complete=True)
+    Wm = np.array([np.sum(x ** a) for a in range(p + 1)])
+    V = np.vstack([x ** b for b in range(p + 1)])
+    full = Wm @ c @ V
+    own = np.einsum("an,ab,bn->n", V, c, V)
+    assert rel(got, K / n * (full - own)) < 1e-11
+
+
+def test_general_polynomial_separable_product():
+    """g(x, y) = x^2 y: the coupling is x_m (A x^2)_m."""
+    n = 90
+    A, rp, col = random_graph(n, 0.3, 33)
+    x = np.random.default_rng(34).normal(size=n)
+    c = np.zeros((3, 3))
+    c[2, 1] = 1.0
+    got = oracle.poly_rhs_general(n, rp, col, None, 3.0, c, None, x)
+    assert rel(got, 3.0 / n * x * (A @ x ** 2)) < 1e-12
