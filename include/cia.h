@@ -170,6 +170,10 @@ typedef struct cia_coupling {
        CSR or complete graphs, CIA or direct (not the all-to-all direct kernel),
        not batched. */
     const double *gen_c11, *gen_c12, *gen_c21, *gen_c22;
+    /* polynomial model, optional: a general coupling g(x_l, x_m) =
+       sum_{a,b=0..p} poly_g[a*(p+1)+b] x_l^a x_m^b (App. A.3, eq. PolyApprox);
+       set: it defines the coupling and poly_h is not used. */
+    const double *poly_g;
 } cia_coupling;
 
 typedef struct cia_options {

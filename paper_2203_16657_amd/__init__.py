@@ -50,7 +50,7 @@ class cia_coupling(_c.Structure):
                 ("cs_L", _c.c_double), ("cs_basis", _c.c_int32), ("rank", _c.c_int32),
                 ("train_iters", _c.c_int32), ("reserved", _c.c_int32), ("poly_q", _c.c_int32),
                 ("reserved2", _c.c_int32), ("poly_h", _vp), ("poly_f", _vp), ("gen_c11", _vp), ("gen_c12", _vp),
-                ("gen_c21", _vp), ("gen_c22", _vp)]
+                ("gen_c21", _vp), ("gen_c22", _vp), ("poly_g", _vp)]
 
 
 class cia_options(_c.Structure):
@@ -444,15 +444,15 @@ class Plan:
     @classmethod
     def poly(cls, n, row_ptr=None, col=None, labels=None, omega=None, K=1.0, h=(0.0, 1.0), f=None,
              method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4, flags=0, complete=False, unit_work=0,
-             block=0, dense_alpha=2.0, device=-1):
+             block=0, dense_alpha=2.0, device=-1, g=None):
         """Polynomial difference coupling (App. A.3; Desai-Zwanzig, App. A.5):
         x_m' = omega_m + f(x_m) + (K/N) sum_l a_ml h(x_l - x_m), h and f by
         their coefficients in increasing powers (f optional)."""
         load()
         rp = None if complete else np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = None if complete else np.ascontiguousarray(col, dtype=np.int32)
-        g = cia_graph(n=int(n), kind=CIA_GRAPH_COMPLETE if complete else CIA_GRAPH_CSR, reserved=0,
-                      row_ptr=_np_ptr(rp), col=_np_ptr(cl))
+        graph = cia_graph(n=int(n), kind=CIA_GRAPH_COMPLETE if complete else CIA_GRAPH_CSR, reserved=0,
+                          row_ptr=_np_ptr(rp), col=_np_ptr(cl))
         hc = np.ascontiguousarray(h, dtype=np.float64)
         fc = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
         c = cia_coupling_default()
@@ -461,11 +461,17 @@ class Plan:
         c.poly_h = _np_ptr(hc)
         c.poly_q = -1 if fc is None else len(fc) - 1
         c.poly_f = _np_ptr(fc)
+        if g is not None:
+            # general coupling g(x_l, x_m) = sum c[a, b] x_l^a x_m^b replaces h
+            gc = np.ascontiguousarray(g, dtype=np.float64)
+            c.p = gc.shape[0] - 1
+            assert gc.shape == (c.p + 1, c.p + 1)
+            c.poly_g = _np_ptr(gc)
         c.K = float(K)
         o = cia_options_default()
         o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
         o.unit_work, o.block, o.dense_alpha, o.device = unit_work, block, dense_alpha, device
-        h_ = cia_build(g, labels, c, omega, o)
+        h_ = cia_build(graph, labels, c, omega, o)
         return cls(h_, int(n), precision, CIA_MODEL_POLY)
 
     @classmethod

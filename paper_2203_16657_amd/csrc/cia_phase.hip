@@ -175,6 +175,7 @@ struct PhaseArgs {
     R dsin[PMAX + 1], dcos[PMAX + 1];
     double ph[PMAX + 1], pf[PMAX + 1];   // polynomial model: h and f coefficients
     const R *gen;             // general coupling: c11, c12, c21, c22, each [(P+1)^2]; NULL = difference form
+    const double *pgen;       // polynomial model, general coupling c[a][b] [(P+1)^2]; NULL = h(x_l - x_m)
     int32_t pq;
     int32_t stage, mode, want_r, lds_cap;
     uint32_t pad_pos;         // position whose z is 0 (= n): target of padded int32 entries
@@ -851,7 +852,20 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
         R T[P];
 #pragma unroll
         for (int k = 0; k < P; k++) T[k] = (R)0;
-        double Eh = 0.0;   // direct: sum of h(x_l - x_m)
+        double Eh = 0.0;   // direct: sum of h(x_l - x_m), or of g(x_l, x_m)
+        // direct with a general coupling: g(x_l, x_m) = sum_a x_l^a B_a, B_a = sum_b c[a][b] x_m^b
+        R Bg[P + 1];
+        if (DIRECT && a.pgen) {
+#pragma unroll
+            for (int q = 0; q <= P; q++) {
+                double v = 0.0, xb = 1.0;
+                for (int b = 0; b <= P; b++) {
+                    v += a.pgen[q * (P + 1) + b] * xb;
+                    xb *= (double)xm;
+                }
+                Bg[q] = (R)v;
+            }
+        }
         if (gather) {
             if (!DIRECT) {
                 // S-neg: up to UN chunks in flight (LDS gathers), or UGL (global gathers)
@@ -915,10 +929,17 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                     for (int q = 0; q < 4; q++) {
                         if (DIRECT) {
                             if (q4[q] != pad) {
-                                const R d = xl[u][q] - xm;
-                                R hv = (R)a.ph[P];
+                                R hv;
+                                if (a.pgen) {
+                                    hv = Bg[P];
 #pragma unroll
-                                for (int e = P - 1; e >= 0; e--) hv = hv * d + (R)a.ph[e];
+                                    for (int e = P - 1; e >= 0; e--) hv = hv * xl[u][q] + Bg[e];
+                                } else {
+                                    const R d = xl[u][q] - xm;
+                                    hv = (R)a.ph[P];
+#pragma unroll
+                                    for (int e = P - 1; e >= 0; e--) hv = hv * d + (R)a.ph[e];
+                                }
                                 Eh += (double)hv;
                             }
                         } else {
@@ -937,6 +958,28 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                 double s;
                 if (DIRECT) {
                     s = Eh;
+                } else if (a.pgen) {
+                    // general coupling: sum_b x_m^b sum_a c[a][b] M_a, minus g(x_m, x_m)
+                    double M[P + 1];
+                    M[0] = (assigned ? (double)lam : 0.0) + (double)cv;
+#pragma unroll
+                    for (int k = 1; k <= P; k++) M[k] = W[k - 1] + (double)T[k - 1];
+                    const double x = (double)xm;
+                    double xp[2 * P + 1];
+                    xp[0] = 1.0;
+#pragma unroll
+                    for (int k = 1; k <= 2 * P; k++) xp[k] = xp[k - 1] * x;
+                    s = 0.0;
+                    double own = 0.0;
+#pragma unroll
+                    for (int q = 0; q <= P; q++)
+#pragma unroll
+                        for (int b = 0; b <= P; b++) {
+                            const double cab = a.pgen[q * (P + 1) + b];
+                            s += cab * M[q] * xp[b];
+                            own += cab * xp[q + b];
+                        }
+                    if (assigned) s -= own;
                 } else {
                     // g_k(x_m): Taylor shift of h by -x_m (repeated synthetic division)
                     double g[P + 1];
@@ -1392,6 +1435,7 @@ struct PhaseState {
     bool tri = false;        // triadic model
     bool poly = false;       // polynomial difference coupling
     void *gen = nullptr;     // general coupling coefficients on the device (R), or NULL
+    double *pgen = nullptr;  // polynomial model: general coupling coefficients, or NULL
     int pq = -1;             // degree of the local polynomial f (-1: none)
     double ph[PMAX + 1] = {0}, pf[PMAX + 1] = {0};   // coefficients of h and f
     double K2n = 0;
@@ -1863,12 +1907,19 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     s->direct = o->method == CIA_METHOD_DIRECT;
     if (c->model == CIA_MODEL_POLY) {
         if (c->p < 1 || c->p > PMAX) return set_error(CIA_EINVAL, "coupling.p = %d; supported 1..%d", c->p, PMAX);
-        if (!c->poly_h) return set_error(CIA_EINVAL, "polynomial model: coupling.poly_h is NULL");
+        if (!c->poly_h && !c->poly_g) return set_error(CIA_EINVAL, "polynomial model: coupling.poly_h is NULL");
         if (c->poly_q < -1 || c->poly_q > PMAX)
             return set_error(CIA_EINVAL, "coupling.poly_q = %d; supported -1..%d", c->poly_q, PMAX);
         if (c->poly_q >= 0 && !c->poly_f) return set_error(CIA_EINVAL, "polynomial model: coupling.poly_f is NULL");
-        for (int k = 0; k <= c->p; k++)
-            if (!std::isfinite(c->poly_h[k])) return set_error(CIA_EINVAL, "coupling.poly_h must be finite");
+        if (c->poly_g) {
+            const int np = (c->p + 1) * (c->p + 1);
+            for (int k = 0; k < np; k++)
+                if (!std::isfinite(c->poly_g[k])) return set_error(CIA_EINVAL, "coupling.poly_g must be finite");
+            CIA_TRY(dupload(p, &s->pgen, c->poly_g, (size_t)np));
+        } else {
+            for (int k = 0; k <= c->p; k++)
+                if (!std::isfinite(c->poly_h[k])) return set_error(CIA_EINVAL, "coupling.poly_h must be finite");
+        }
         for (int k = 0; k <= c->poly_q; k++)
             if (!std::isfinite(c->poly_f[k])) return set_error(CIA_EINVAL, "coupling.poly_f must be finite");
         if (g->kind == CIA_GRAPH_COMPLETE && o->method == CIA_METHOD_DIRECT)
@@ -1876,7 +1927,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         s->poly = true;
         s->P = c->p;
         s->pq = c->poly_q;
-        for (int k = 0; k <= c->p; k++) s->ph[k] = c->poly_h[k];
+        if (!c->poly_g)
+            for (int k = 0; k <= c->p; k++) s->ph[k] = c->poly_h[k];
         for (int k = 0; k <= c->poly_q; k++) s->pf[k] = c->poly_f[k];
         // the zeroth moment of every row's partners (|S+| - |S-|) is always needed
         s->d0 = 1.0;
@@ -2289,6 +2341,7 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
     }
     a.pq = s->pq;
     a.gen = static_cast<const R *>(s->gen);
+    a.pgen = s->pgen;
     a.cnt = s->cnt;
     a.perm = s->perm;
     a.omega = static_cast<const R *>(s->omega);

@@ -146,3 +146,39 @@ def test_poly_full_size_sampled_rows(env):
         say("N = 1e6 method", method, "sampled coupling rel_inf", err)
         assert err < 1e-5
         plan.close()
+
+
+@pytest.mark.parametrize("graph", ["config1", "config2_scaled"])
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_general_polynomial_coupling(env, graph, method, precision):
+    """g(x_l, x_m) = sum c[a, b] x_l^a x_m^b (App. A.3, eq. PolyApprox), order 3,
+    with the Desai-Zwanzig local term."""
+    cia, torch = env
+    P = W.kuramoto_small() if graph == "config1" else W.scaled_kuramoto(20000, seed=12, hi=1000)
+    g = P.graph
+    rng = np.random.default_rng(40 + method)
+    c = rng.normal(size=(4, 4)) / 4.0
+    x = rng.uniform(-1.2, 1.2, g.n)
+    plan = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, None, K=2.0, g=c, f=DZ_F, method=method,
+                         precision=precision)
+    got, xr = gpu_rhs(env, plan, x, precision)
+    want = oracle.poly_rhs_general(g.n, g.row_ptr, g.col, None, 2.0, c, DZ_F, xr)
+    base = xr - xr ** 3
+    err = coupling_err(got, want, base)
+    say("general poly", graph, "method", method, "prec", precision, "coupling rel_inf", err)
+    assert err < (1e-12 if precision else 1e-5)
+    plan.close()
+
+
+def test_general_polynomial_complete_graph(env):
+    cia, torch = env
+    n = 5000
+    rng = np.random.default_rng(41)
+    c = rng.normal(size=(3, 3)) / 3.0
+    x = rng.uniform(-1, 1, n)
+    plan = cia.Plan.poly(n, complete=True, K=1.0, g=c, precision=1)
+    got, _ = gpu_rhs(env, plan, x, 1)
+    want = oracle.poly_rhs_general(n, None, None, None, 1.0, c, None, x, complete=True)
+    assert coupling_err(got, want, 0.0) < 1e-12
+    plan.close()
