@@ -240,6 +240,30 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def oracle_baseline(args, fn, n, what, target_s=8.0):
+    """The oracle timed on the host on a bounded sample: fn(rows) evaluates
+    the FP64 right-hand side of the sampled rows of the workload; the sample
+    grows until it takes about target_s / 4 .. target_s seconds."""
+    if args.no_cpu:
+        return None
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(0)
+    k = 64
+    while True:
+        rows = np.sort(rng.choice(n, min(k, n), replace=False)).astype(np.int64)
+        t0 = time.time()
+        fn(rows)
+        ct = time.time() - t0
+        if ct >= target_s / 4 or k >= n:
+            break
+        k = int(min(n, k * max(2.0, target_s / max(ct, 1e-3))))
+    out = {"value": len(rows) / ct, "unit": "RHS node-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": "%s: %d sampled rows of one FP64 right-hand side, %.1f s" % (what, len(rows), ct)}
+    log("cpu oracle (%s): %.3e RHS node-updates/s on %d threads" % (what, out["value"], out["cores"]))
+    return out
+
+
 def timed(torch, fn):
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -317,6 +341,8 @@ def bench_flock(args, cia, W, torch, np):
                   "loss_last": float(lt[-100:].mean())},
         "gain_vs_fourier": errs["fourier_p1"] / errs["learned_no_judge"],
     }
+    out["cpu_baseline"] = oracle_baseline(args, lambda r_: oracle.cs_rhs(
+        n, g.row_ptr, g.col, F.K, F.sigma, F.beta, s64[:3], s64[3:], rows=r_), n, "flock_n200000 exact sum")
     print(json.dumps(out), flush=True)
 
 
@@ -365,6 +391,30 @@ def bench_ensemble(args, cia, W, torch, np):
                    "dt": 0.01},
         "methods": res, "speedup_vs_sequential": res["batched"]["value"] / res["sequential"]["value"],
     }
+    # the oracle over every instance, a bounded share of each one's rows
+    import oracle
+    share = 1.0
+    if not args.no_cpu:
+        t0 = time.time()
+        P0 = ens[0]
+        oracle.phase_rhs(P0.graph.n, P0.graph.row_ptr, P0.graph.col, P0.omega, P0.K, [0, 1], [0, 0],
+                         P0.theta0, rows=np.arange(min(256, P0.graph.n), dtype=np.int64))
+        share = min(1.0, max(0.002, 6.0 / max((time.time() - t0) * ntot / min(256, P0.graph.n), 1e-9)))
+    def ens_rows(_rows):
+        for P in ens:
+            m = max(1, int(P.graph.n * share))
+            oracle.phase_rhs(P.graph.n, P.graph.row_ptr, P.graph.col, P.omega, P.K, [0, 1], [0, 0], P.theta0,
+                             rows=np.arange(m, dtype=np.int64))
+    if not args.no_cpu:
+        t0 = time.time()
+        ens_rows(None)
+        ct = time.time() - t0
+        done = sum(max(1, int(P.graph.n * share)) for P in ens)
+        out["cpu_baseline"] = {"value": done / ct, "unit": "RHS node-updates/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": "the first %.1f%% of the rows of every instance, "
+                               "one FP64 right-hand side, %.1f s" % (100 * share, ct)}
+    else:
+        out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 
@@ -408,6 +458,11 @@ def bench_triadic(args, cia, W, torch, np):
         "config": {"workload": "triadic_n%d" % n, "n": n, "communities": g.ncomm, "stepper": "rk4", "dt": T.dt},
         "methods": res, "speedup_vs_direct": res["cia"]["value"] / res["direct"]["value"],
     }
+    import oracle
+    th64 = T.theta0.astype(np.float32).astype(np.float64)
+    out["cpu_baseline"] = oracle_baseline(args, lambda rows: oracle.triadic_rhs(
+        n, g.row_ptr, g.col, g.labels, T.tri_seed, T.p_tri, T.cross_tri, None, T.K1, T.K2, th64, rows=rows),
+        n, "triadic_n%d" % n)
     aux_us = res["cia"]["aux_us"]
     if aux_us > 0 and res["cia"]["bytes_aux"] > 0:
         # the missing-pair sum launch streams the stored lists once per stage
@@ -459,6 +514,10 @@ def bench_general(args, cia, W, torch, np):
                      "traffic": None},
         "methods": res, "speedup_vs_direct": res["direct"]["ms_per_step"] / c["ms_per_step"],
     }
+    import oracle
+    th64 = th0.astype(np.float64)
+    line["cpu_baseline"] = oracle_baseline(args, lambda rows: oracle.phase_rhs_general(
+        n, g.row_ptr, g.col, P.omega, P.K, *cs, th64, rows=rows), n, "general_p2_n1e6")
     print(json.dumps(line), flush=True)
 
 
@@ -506,6 +565,10 @@ def bench_poly(args, cia, W, torch, np):
         "speedup_vs_direct": {k: res[k + "_direct"]["ms_per_step"] / res[k + "_cia"]["ms_per_step"]
                               for k in ("dz", "cubic")},
     }
+    import oracle
+    x64 = x0.astype(np.float64)
+    line["cpu_baseline"] = oracle_baseline(args, lambda rows: oracle.poly_rhs(
+        n, g.row_ptr, g.col, None, 3.0, [0.0, 1.0], [0.0, 1.0, 0.0, -1.0], x64, rows=rows), n, "poly_dz_n1e6")
     print(json.dumps(line), flush=True)
 
 
@@ -562,6 +625,10 @@ def bench_structured(args, cia, W, torch, np):
         "config": {"workload": "structured_ring_n1e7_k1e6", "n": big, "stepper": "rk4", "dt": 0.01},
         "roofline": out["ring"]["roofline"], "large": out, "vs_direct_n1e5": cmp,
     }
+    import oracle
+    th64 = rng.uniform(0, 2 * np.pi, big)
+    line["cpu_baseline"] = oracle_baseline(args, lambda rows: oracle.structured_rhs(
+        "ring", big, None, 2.0, [0.0, 1.0], [0.0, 0.0], th64, k=big // 10, rows=rows), big, "structured_ring_n1e7_k1e6")
     print(json.dumps(line), flush=True)
 
 
