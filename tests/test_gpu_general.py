@@ -141,3 +141,19 @@ def test_general_rejections(env):
         cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, None, gen=coeffs(5, 1))      # order above 4
     with pytest.raises(cia.CIAError):
         cia.Plan.phase(1000, complete=True, gen=coeffs(1, 2), method=1)              # all-to-all direct kernel
+
+
+def test_general_graph_replay(env):
+    cia, torch = env
+    P = W.kuramoto_small()
+    g = P.graph
+    cs = coeffs(2, 99)
+    outs = []
+    for flags in (0, cia.CIA_FLAG_HIPGRAPH):
+        plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=4.0, gen=cs, flags=flags)
+        t = torch.as_tensor(P.theta0.astype(np.float32), device="cuda")
+        r = np.zeros(21)
+        plan.integrate(t, 0.01, 20, r)
+        outs.append((t.cpu().numpy(), r))
+        plan.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])

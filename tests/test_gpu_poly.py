@@ -182,3 +182,28 @@ def test_general_polynomial_complete_graph(env):
     want = oracle.poly_rhs_general(n, None, None, None, 1.0, c, None, x, complete=True)
     assert coupling_err(got, want, 0.0) < 1e-12
     plan.close()
+
+
+def test_poly_graph_replay_and_autotune(env):
+    """The replayed RK4 step graph gives bitwise the eager trajectory, and
+    the autotuner's re-cut units keep the right-hand side."""
+    cia, torch = env
+    P = W.scaled_kuramoto(20000, seed=12, hi=1000)
+    g = P.graph
+    x0 = np.random.default_rng(50).uniform(-1, 1, g.n).astype(np.float32)
+    outs = []
+    for flags in (0, cia.CIA_FLAG_HIPGRAPH):
+        plan = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, None, K=2.0, h=[0.0, 1.0, 0.0, -0.2], f=DZ_F,
+                             flags=flags)
+        x = torch.as_tensor(x0, device="cuda")
+        plan.integrate(x, 0.01, 15)
+        plan.integrate(x, 0.01, 15)
+        outs.append(x.cpu().numpy())
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
+    plan = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, None, K=2.0, h=[0.0, 1.0], f=DZ_F)
+    a, _ = gpu_rhs(env, plan, x0, 0)
+    rep = plan.autotune()
+    b, _ = gpu_rhs(env, plan, x0, 0)
+    assert rep.best_us <= rep.default_us and np.abs(a - b).max() <= 1e-6 * np.abs(a).max()
+    plan.close()
