@@ -109,6 +109,9 @@ def _load():
         lib.oracle_poly_rhs_general.restype = None
         lib.oracle_poly_rhs_general.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp,
                                                 ctypes.c_int, _vp, _vp, _vp, i64, _vp]
+        lib.oracle_osc2_rhs.restype = None
+        lib.oracle_osc2_rhs.argtypes = [i64, _vp, _vp, ctypes.c_int, _vp, d, ctypes.c_int, _vp, _vp, _vp, _vp, i64,
+                                        _vp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -275,6 +278,24 @@ def poly_rhs_general(n, row_ptr, col, omega, K, c, f, x, rows=None, complete=Fal
     out = np.empty(cnt, dtype=np.float64)
     lib.oracle_poly_rhs_general(int(n), _p(rp), _p(cl), int(bool(complete)), _p(_f64(omega)), float(K), p, _p(c),
                                 fq, _p(_f64(f)), _p(_f64(x)), _p(rws), 0 if rws is None else len(rws), _p(out))
+    return out
+
+
+def osc2_rhs(n, row_ptr, col, omega, K, h, F, x, rows=None, complete=False):
+    """Two-component oscillators (the paper's Table 1, van der Pol /
+    FitzHugh-Nagumo): x is [2, n]; F is [2, 4, 4] with f_d(u, v) =
+    sum F[d, i, j] u^i v^j; omega (optional) drives component 0.  Returns
+    [2, len(rows) or n]."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    h = _f64(h)
+    F = np.ascontiguousarray(F, dtype=np.float64).reshape(2, 4, 4)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(2, n)
+    rws = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if rws is None else len(rws)
+    out = np.empty((2, cnt), dtype=np.float64)
+    lib.oracle_osc2_rhs(int(n), _p(rp), _p(cl), int(bool(complete)), _p(_f64(omega)), float(K), len(h) - 1, _p(h),
+                        _p(F), _p(x), _p(rws), 0 if rws is None else len(rws), _p(out))
     return out
 
 

@@ -105,3 +105,44 @@ void oracle_poly_rhs_general(int64_t n, const int64_t *rp, const int32_t *col, i
         out[r] = (omega ? omega[m] : 0.0) + (q >= 0 && f ? horner(q, f, x[m]) : 0.0) + scale * acc;
     }
 }
+
+/* Two-component oscillators (Table 1 of the paper: van der Pol /
+   FitzHugh-Nagumo with h(xi) = xi): for d = 0, 1
+     x_{d,m}' = [d = 0] omega_m + f_d(x_{0,m}, x_{1,m})
+                + (K/N) sum_l a_ml h(x_{d,l} - x_{d,m}),
+   f_d(u, v) = sum_{i,j=0..3} F[d][i][j] u^i v^j, h as above (both components).
+   x and out are [2][n] (rows: out[d][r]). */
+static double f2_eval(const double *F, double u, double v) {
+    double s = 0.0, ui = 1.0;
+    for (int i = 0; i <= 3; i++) {
+        double vj = 1.0;
+        for (int j = 0; j <= 3; j++) {
+            s += F[i * 4 + j] * ui * vj;
+            vj *= v;
+        }
+        ui *= u;
+    }
+    return s;
+}
+
+void oracle_osc2_rhs(int64_t n, const int64_t *rp, const int32_t *col, int complete, const double *omega, double K,
+                     int p, const double *h, const double *F, const double *x, const int64_t *rows, int64_t nrows,
+                     double *out) {
+    const int64_t cnt = rows ? nrows : n;
+    const double scale = K / (double)n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < cnt; r++) {
+        const int64_t m = rows ? rows[r] : r;
+        for (int d = 0; d < 2; d++) {
+            const double *xd = x + d * n;
+            double acc = 0.0;
+            if (complete) {
+                for (int64_t l = 0; l < n; l++)
+                    if (l != m) acc += horner(p, h, xd[l] - xd[m]);
+            } else {
+                for (int64_t e = rp[m]; e < rp[m + 1]; e++) acc += horner(p, h, xd[col[e]] - xd[m]);
+            }
+            out[d * cnt + r] = (d == 0 && omega ? omega[m] : 0.0) + f2_eval(F + 16 * d, x[m], x[n + m]) + scale * acc;
+        }
+    }
+}

@@ -144,3 +144,42 @@ def test_general_polynomial_separable_product():
     c[2, 1] = 1.0
     got = oracle.poly_rhs_general(n, rp, col, None, 3.0, c, None, x)
     assert rel(got, 3.0 / n * x * (A @ x ** 2)) < 1e-12
+
+
+def vdp_F(eps):
+    """van der Pol in the paper's Table 1 form: f = (x2 - x1^3/3 + x1, -eps x1)."""
+    F = np.zeros((2, 4, 4))
+    F[0, 0, 1] = 1.0
+    F[0, 3, 0] = -1.0 / 3.0
+    F[0, 1, 0] = 1.0
+    F[1, 1, 0] = -eps
+    return F
+
+
+def test_osc2_local_term_is_van_der_pol():
+    n = 50
+    rng = np.random.default_rng(60)
+    x = rng.normal(size=(2, n))
+    got = oracle.osc2_rhs(n, None, None, None, 0.0, [0.0, 1.0], vdp_F(0.3), x, complete=True)
+    assert rel(got[0], x[1] - x[0] ** 3 / 3 + x[0]) < 1e-14 and rel(got[1], -0.3 * x[0]) < 1e-14
+
+
+def test_osc2_coupling_is_the_laplacian_per_component():
+    n, K = 80, 2.5
+    A, rp, col = random_graph(n, 0.2, 61)
+    x = np.random.default_rng(62).normal(size=(2, n))
+    got = oracle.osc2_rhs(n, rp, col, None, K, [0.0, 1.0], np.zeros((2, 4, 4)), x)
+    L = scipy.sparse.csgraph.laplacian(A)
+    assert rel(got, -K / n * (L @ x.T).T) < 1e-13
+
+
+def test_osc2_components_match_the_one_component_oracle():
+    """Each component's coupling is the one-component polynomial oracle's."""
+    n = 60
+    A, rp, col = random_graph(n, 0.3, 63)
+    rng = np.random.default_rng(64)
+    x = rng.uniform(-1, 1, (2, n))
+    h = [0.1, 1.0, 0.0, -0.3]
+    got = oracle.osc2_rhs(n, rp, col, None, 3.0, h, np.zeros((2, 4, 4)), x)
+    for d in range(2):
+        assert rel(got[d], oracle.poly_rhs(n, rp, col, None, 3.0, h, None, x[d])) < 1e-13
