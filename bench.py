@@ -522,9 +522,10 @@ def bench_general(args, cia, W, torch, np):
 
 
 def bench_poly(args, cia, W, torch, np):
-    """Desai-Zwanzig dynamics (App. A.5: h(x) = x, f = x - x^3) and a cubic
-    difference coupling on the N = 1e6 power-law community graph of the phase
-    bench, FP32, RK4: CIA against the direct method on the same GPU."""
+    """Desai-Zwanzig dynamics (App. A.5: h(x) = x, f = x - x^3), a cubic
+    difference coupling and coupled van der Pol oscillators (two components,
+    Table 1) on the N = 1e6 power-law community graph of the phase bench,
+    FP32, RK4: CIA against the direct method on the same GPU."""
     P = W.kuramoto_large()
     g = P.graph
     n = g.n
@@ -551,6 +552,28 @@ def bench_poly(args, cia, W, torch, np):
             log("%-12s %.4f ms/step, stage %.2f us, %.1f GB/s" % (key, ms / steps, stage_us,
                                                                   res[key]["achieved_gbs"]))
             plan.close()
+    # coupled van der Pol oscillators (two components, Table 1 with eps = 0.3)
+    F = np.zeros((2, 4, 4))
+    F[0, 0, 1], F[0, 3, 0], F[0, 1, 0], F[1, 1, 0] = 1.0, -1.0 / 3.0, 1.0, -0.3
+    xv0 = np.random.default_rng(18).uniform(-1.5, 1.5, (2, n)).astype(np.float32)
+    for method in (cia.CIA_METHOD_CIA, cia.CIA_METHOD_DIRECT):
+        plan = cia.Plan.poly(n, g.row_ptr, g.col, g.labels, None, K=3.0, h=[0.0, 1.0], dim=2, f2=F,
+                             method=method, flags=cia.CIA_FLAG_NO_VALIDATE)
+        info = plan.info()
+        steps = 50 if method == cia.CIA_METHOD_CIA else 5
+        x = torch.as_tensor(xv0, device="cuda")
+        plan.integrate(x, 0.01, 2)
+        plan.set_timing(1)
+        plan.timing(reset=True)
+        ms = timed(torch, lambda s: plan.integrate(x, 0.01, steps, stream=s))
+        t = plan.timing(reset=True)
+        stage_us = 1e3 * t.stage_ms / max(t.stage_launches, 1)
+        key = "vdp_%s" % ("cia" if method == cia.CIA_METHOD_CIA else "direct")
+        res[key] = {"ms_per_step": ms / steps, "value": n * 4 * steps / (ms / 1e3), "stage_us": round(stage_us, 2),
+                    "bytes_per_stage": info.bytes_per_stage,
+                    "achieved_gbs": round(info.bytes_per_stage / (stage_us * 1e-6) / 1e9, 1)}
+        log("%-12s %.4f ms/step, stage %.2f us, %.1f GB/s" % (key, ms / steps, stage_us, res[key]["achieved_gbs"]))
+        plan.close()
     dz = res["dz_cia"]
     line = {
         "metric": "Desai-Zwanzig RHS node-updates/s (CIA), 1 MI355X, N=1e6 community graph",
@@ -563,7 +586,7 @@ def bench_poly(args, cia, W, torch, np):
                      "traffic": None},
         "methods": res,
         "speedup_vs_direct": {k: res[k + "_direct"]["ms_per_step"] / res[k + "_cia"]["ms_per_step"]
-                              for k in ("dz", "cubic")},
+                              for k in ("dz", "cubic", "vdp")},
     }
     import oracle
     x64 = x0.astype(np.float64)

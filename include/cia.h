@@ -174,6 +174,17 @@ typedef struct cia_coupling {
        sum_{a,b=0..p} poly_g[a*(p+1)+b] x_l^a x_m^b (App. A.3, eq. PolyApprox);
        set: it defines the coupling and poly_h is not used. */
     const double *poly_g;
+    /* polynomial model: state components per node, 0 or 1 = one (x_m), 2 = two (u_m, v_m), the
+       oscillators of Table 1 (van der Pol, FitzHugh-Nagumo) with the difference coupling h applied
+       to each component separately:
+         u_m' = omega_m + f_0(u_m, v_m) + (K/N) sum_l a_ml h(u_l - u_m),
+         v_m' =           f_1(u_m, v_m) + (K/N) sum_l a_ml h(v_l - v_m),
+         f_d(u, v) = sum_{i,j=0..3} poly_f2[16 d + 4 i + j] u^i v^j.
+       Two components: the state arrays are [2][n] (all u, then all v), poly_f2 is host
+       [2][4][4] (NULL = no local term), poly_f/poly_q and poly_g are not allowed, CSR graphs. */
+    int32_t poly_dim;
+    int32_t reserved3;
+    const double *poly_f2;
 } cia_coupling;
 
 typedef struct cia_options {

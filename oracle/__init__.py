@@ -299,6 +299,26 @@ def osc2_rhs(n, row_ptr, col, omega, K, h, F, x, rows=None, complete=False):
     return out
 
 
+def osc2_integrate(n, row_ptr, col, omega, K, h, F, x0, dt, steps, stepper="rk4"):
+    """The two-component system stepped by the classical RK4 (or explicit
+    Euler) scheme, each stage one osc2_rhs evaluation."""
+    x = np.array(x0, dtype=np.float64, copy=True).reshape(2, n)
+
+    def rhs(y):
+        return osc2_rhs(n, row_ptr, col, omega, K, h, F, y)
+
+    for _ in range(int(steps)):
+        if stepper == "euler":
+            x = x + dt * rhs(x)
+            continue
+        k1 = rhs(x)
+        k2 = rhs(x + 0.5 * dt * k1)
+        k3 = rhs(x + 0.5 * dt * k2)
+        k4 = rhs(x + dt * k3)
+        x = x + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    return x
+
+
 def poly_integrate(n, row_ptr, col, omega, K, h, f, x0, dt, steps, stepper="rk4", complete=False):
     lib = _load()
     rp, cl = _csr(row_ptr, col)

@@ -50,7 +50,8 @@ class cia_coupling(_c.Structure):
                 ("cs_L", _c.c_double), ("cs_basis", _c.c_int32), ("rank", _c.c_int32),
                 ("train_iters", _c.c_int32), ("reserved", _c.c_int32), ("poly_q", _c.c_int32),
                 ("reserved2", _c.c_int32), ("poly_h", _vp), ("poly_f", _vp), ("gen_c11", _vp), ("gen_c12", _vp),
-                ("gen_c21", _vp), ("gen_c22", _vp), ("poly_g", _vp)]
+                ("gen_c21", _vp), ("gen_c22", _vp), ("poly_g", _vp),
+                ("poly_dim", _c.c_int32), ("reserved3", _c.c_int32), ("poly_f2", _vp)]
 
 
 class cia_options(_c.Structure):
@@ -444,10 +445,13 @@ class Plan:
     @classmethod
     def poly(cls, n, row_ptr=None, col=None, labels=None, omega=None, K=1.0, h=(0.0, 1.0), f=None,
              method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4, flags=0, complete=False, unit_work=0,
-             block=0, dense_alpha=2.0, device=-1, g=None):
+             block=0, dense_alpha=2.0, device=-1, g=None, dim=1, f2=None):
         """Polynomial difference coupling (App. A.3; Desai-Zwanzig, App. A.5):
         x_m' = omega_m + f(x_m) + (K/N) sum_l a_ml h(x_l - x_m), h and f by
-        their coefficients in increasing powers (f optional)."""
+        their coefficients in increasing powers (f optional).  dim=2: two
+        components per node (van der Pol / FitzHugh-Nagumo of Table 1), state
+        [2, n], h on each component, local terms f2[d, i, j] u^i v^j (f2 a
+        [2, 4, 4] array, optional; f and g not allowed), omega on component 0."""
         load()
         rp = None if complete else np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = None if complete else np.ascontiguousarray(col, dtype=np.int32)
@@ -467,12 +471,18 @@ class Plan:
             c.p = gc.shape[0] - 1
             assert gc.shape == (c.p + 1, c.p + 1)
             c.poly_g = _np_ptr(gc)
+        c.poly_dim = int(dim)
+        f2c = None
+        if f2 is not None:
+            f2c = np.ascontiguousarray(f2, dtype=np.float64)
+            assert f2c.shape == (2, 4, 4)
+            c.poly_f2 = _np_ptr(f2c)
         c.K = float(K)
         o = cia_options_default()
         o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
         o.unit_work, o.block, o.dense_alpha, o.device = unit_work, block, dense_alpha, device
         h_ = cia_build(graph, labels, c, omega, o)
-        return cls(h_, int(n), precision, CIA_MODEL_POLY)
+        return cls(h_, int(n), precision, CIA_MODEL_POLY, dim=max(1, int(dim)))
 
     @classmethod
     def structured(cls, n, kind, omega=None, K=1.0, d_sin=(0.0, 1.0), d_cos=(0.0, 0.0), alpha=None, beta=None,

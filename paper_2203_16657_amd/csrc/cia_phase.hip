@@ -176,6 +176,7 @@ struct PhaseArgs {
     double ph[PMAX + 1], pf[PMAX + 1];   // polynomial model: h and f coefficients
     const R *gen;             // general coupling: c11, c12, c21, c22, each [(P+1)^2]; NULL = difference form
     const double *pgen;       // polynomial model, general coupling c[a][b] [(P+1)^2]; NULL = h(x_l - x_m)
+    double pf2[32];           // polynomial model with two components: F[d][i][j], f_d = sum F u^i v^j
     int32_t pq;
     int32_t stage, mode, want_r, lds_cap;
     uint32_t pad_pos;         // position whose z is 0 (= n): target of padded int32 entries
@@ -786,13 +787,19 @@ __device__ __forceinline__ void acc_pow(R (&T)[P], R x, R sign) {
     }
 }
 
-template <typename R, int P, int BLOCK, bool DIRECT>
+// D state components (1, or 2 for the two-component oscillators of the
+// paper's Table 1): component d of position i lives at d * n + i
+// (theta_n, acc) and d * (n + 1) + i (stage values, zero slot at n); LDS
+// holds the community's values interleaved, [lambda + 1][D], so one byte
+// offset of the S-neg stream reaches every component; the unit moments of
+// component d go to the .x (d = 0) and .y (d = 1) halves of the partials.
+template <typename R, int P, int BLOCK, bool DIRECT, int D>
 __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
     constexpr int NW = BLOCK / 64;
     extern __shared__ __align__(16) unsigned char smem[];
-    R *xsh = reinterpret_cast<R *>(smem);   // [lds_cap + 1]
-    __shared__ double qsh[P];
-    __shared__ double red[NW][P];
+    R *xsh = reinterpret_cast<R *>(smem);   // [lds_cap + 1][D]
+    __shared__ double qsh[D][P];
+    __shared__ double red[NW][D][P];
 
     const Unit Un = a.units[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -801,31 +808,47 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
     const int mode = a.mode;
     const bool gather = mode != M_PREP;
     const int off = Un.off, lam = Un.lam;
+    const int64_t n = a.pad_pos;          // nodes; stage arrays have a zero slot at n
+    const int64_t xs = n + 1;             // stride of a component in the stage arrays
 
-    // ---- unit start: the community's x in LDS and its moments W_1..W_P ----
+    // ---- unit start: the community's values in LDS and its moments ----
     if (gather && assigned) {
         if (staged) {
-            for (int j = tid; j < lam; j += BLOCK) xsh[j] = a.th_in[off + j];
-            if (tid == 0) xsh[lam] = (R)0;
+            for (int j = tid; j < lam; j += BLOCK)
+#pragma unroll
+                for (int d = 0; d < D; d++) xsh[j * D + d] = a.th_in[d * xs + off + j];
+            if (tid < D) xsh[lam * D + tid] = (R)0;
         }
         if (wid == NW - 1) {
             for (int k = 0; k < P; k++) {
-                double sx = 0.0;
-                for (int j = Un.qbeg + lane; j < Un.qend; j += 64) sx += a.q_in[(size_t)j * P + k].x;
-                for (int o = 32; o > 0; o >>= 1) sx += __shfl_xor(sx, o);
-                if (lane == 0) qsh[k] = sx;
+                double sx = 0.0, sy = 0.0;
+                for (int j = Un.qbeg + lane; j < Un.qend; j += 64) {
+                    const double2 q = a.q_in[(size_t)j * P + k];
+                    sx += q.x;
+                    sy += q.y;
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    sx += __shfl_xor(sx, o);
+                    sy += __shfl_xor(sy, o);
+                }
+                if (lane == 0) {
+                    qsh[0][k] = sx;
+                    if (D == 2) qsh[D - 1][k] = sy;
+                }
             }
         }
     }
     __syncthreads();
-    double W[P];
+    double W[D][P], pd[D][P];
 #pragma unroll
-    for (int k = 0; k < P; k++) W[k] = (gather && assigned) ? qsh[k] : 0.0;
-    double pd[P];
+    for (int d = 0; d < D; d++)
 #pragma unroll
-    for (int k = 0; k < P; k++) pd[k] = 0.0;
+        for (int k = 0; k < P; k++) {
+            W[d][k] = (gather && assigned) ? qsh[d][k] : 0.0;
+            pd[d][k] = 0.0;
+        }
 
-    const uint32_t padb = (uint32_t)lam * (uint32_t)sizeof(R);
+    const uint32_t padb = (uint32_t)lam * (uint32_t)(D * sizeof(R));
     const uint32_t pad16 = padb | (padb << 16);
     const uint4 padl = make_uint4(pad16, pad16, pad16, pad16);
     const uint32_t pad = a.pad_pos;
@@ -835,33 +858,44 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
         const Slice S = a.slices[sl];
         const bool mine = lane < S.rows;
         const int i = S.row0 + lane;
-        R tn = (R)0, om = (R)0, av = (R)0, xm = (R)0, knv = a.Kn;
+        R tn[D], av[D], xm[D];
+        R om = (R)0, knv = a.Kn;
         int cv = 0;
+#pragma unroll
+        for (int d = 0; d < D; d++) tn[d] = av[d] = xm[d] = (R)0;
         if (mine) {
             if (mode == M_PREP) {
-                tn = a.state_in[a.perm[i]];
+#pragma unroll
+                for (int d = 0; d < D; d++) tn[d] = a.state_in[d * n + a.perm[i]];
             } else {
-                if (mode != M_RHS) tn = a.theta_n[i];
                 if (a.omega) om = a.omega[i];
                 if (a.kn) knv = a.kn[i];
-                if (mode == M_RK4 && a.stage > 0) av = a.acc[i];
                 cv = a.cnt[i];
-                xm = staged ? xsh[i - off] : a.th_in[i];
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    if (mode != M_RHS) tn[d] = a.theta_n[d * n + i];
+                    if (mode == M_RK4 && a.stage > 0) av[d] = a.acc[d * n + i];
+                    xm[d] = staged ? xsh[(i - off) * D + d] : a.th_in[d * xs + i];
+                }
             }
         }
-        R T[P];
+        R T[D][P];
 #pragma unroll
-        for (int k = 0; k < P; k++) T[k] = (R)0;
-        double Eh = 0.0;   // direct: sum of h(x_l - x_m), or of g(x_l, x_m)
-        // direct with a general coupling: g(x_l, x_m) = sum_a x_l^a B_a, B_a = sum_b c[a][b] x_m^b
+        for (int d = 0; d < D; d++)
+#pragma unroll
+            for (int k = 0; k < P; k++) T[d][k] = (R)0;
+        double Eh[D];   // direct: sum of h(x_l - x_m), or of g(x_l, x_m)
+#pragma unroll
+        for (int d = 0; d < D; d++) Eh[d] = 0.0;
+        // direct with a general coupling (one component): g(x_l, x_m) = sum_a x_l^a B_a
         R Bg[P + 1];
-        if (DIRECT && a.pgen) {
+        if (DIRECT && D == 1 && a.pgen) {
 #pragma unroll
             for (int q = 0; q <= P; q++) {
                 double v = 0.0, xb = 1.0;
                 for (int b = 0; b <= P; b++) {
                     v += a.pgen[q * (P + 1) + b] * xb;
-                    xb *= (double)xm;
+                    xb *= (double)xm[0];
                 }
                 Bg[q] = (R)v;
             }
@@ -871,7 +905,7 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                 // S-neg: up to UN chunks in flight (LDS gathers), or UGL (global gathers)
                 const uint4 *col = a.negdata + S.beg[0] + lane;
                 if (staged) {
-                    constexpr int UN = 8;
+                    constexpr int UN = D == 1 ? 8 : 4;
                     for (int k = 0; k < S.w[0]; k += UN) {
                         uint4 v[UN];
 #pragma unroll
@@ -880,10 +914,12 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                         for (int u = 0; u < UN; u++) {
                             const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-                            for (int q = 0; q < 4; q++) {
-                                acc_pow<R, P>(T, xat(xsh, q4[q] & 0xffffu), (R)-1);
-                                acc_pow<R, P>(T, xat(xsh, q4[q] >> 16), (R)-1);
-                            }
+                            for (int q = 0; q < 4; q++)
+#pragma unroll
+                                for (int d = 0; d < D; d++) {
+                                    acc_pow<R, P>(T[d], xat(xsh, (q4[q] & 0xffffu) + d * (uint32_t)sizeof(R)), (R)-1);
+                                    acc_pow<R, P>(T[d], xat(xsh, (q4[q] >> 16) + d * (uint32_t)sizeof(R)), (R)-1);
+                                }
                         }
                     }
                 } else {
@@ -892,18 +928,21 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                         uint4 v[UGL];
 #pragma unroll
                         for (int u = 0; u < UGL; u++) v[u] = k + u < S.w[0] ? ld_stream(col + (size_t)(k + u) * SLICE) : padp;
-                        R xl[UGL][4];
 #pragma unroll
-                        for (int u = 0; u < UGL; u++) {
-                            xl[u][0] = a.th_in[v[u].x];
-                            xl[u][1] = a.th_in[v[u].y];
-                            xl[u][2] = a.th_in[v[u].z];
-                            xl[u][3] = a.th_in[v[u].w];
+                        for (int d = 0; d < D; d++) {
+                            R xl[UGL][4];
+#pragma unroll
+                            for (int u = 0; u < UGL; u++) {
+                                xl[u][0] = a.th_in[d * xs + v[u].x];
+                                xl[u][1] = a.th_in[d * xs + v[u].y];
+                                xl[u][2] = a.th_in[d * xs + v[u].z];
+                                xl[u][3] = a.th_in[d * xs + v[u].w];
+                            }
+#pragma unroll
+                            for (int u = 0; u < UGL; u++)
+#pragma unroll
+                                for (int q = 0; q < 4; q++) acc_pow<R, P>(T[d], xl[u][q], (R)-1);
                         }
-#pragma unroll
-                        for (int u = 0; u < UGL; u++)
-#pragma unroll
-                            for (int q = 0; q < 4; q++) acc_pow<R, P>(T, xl[u][q], (R)-1);
                     }
                 }
             }
@@ -914,118 +953,151 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                 uint4 v[UGP];
 #pragma unroll
                 for (int u = 0; u < UGP; u++) v[u] = k + u < S.w[1] ? ld_stream(col + (size_t)(k + u) * SLICE) : padp;
-                R xl[UGP][4];
 #pragma unroll
-                for (int u = 0; u < UGP; u++) {
-                    xl[u][0] = a.th_in[v[u].x];   // the padding position holds 0
-                    xl[u][1] = a.th_in[v[u].y];
-                    xl[u][2] = a.th_in[v[u].z];
-                    xl[u][3] = a.th_in[v[u].w];
-                }
+                for (int d = 0; d < D; d++) {
+                    R xl[UGP][4];
 #pragma unroll
-                for (int u = 0; u < UGP; u++) {
-                    const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                    for (int u = 0; u < UGP; u++) {
+                        xl[u][0] = a.th_in[d * xs + v[u].x];   // the padding position holds 0
+                        xl[u][1] = a.th_in[d * xs + v[u].y];
+                        xl[u][2] = a.th_in[d * xs + v[u].z];
+                        xl[u][3] = a.th_in[d * xs + v[u].w];
+                    }
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        if (DIRECT) {
-                            if (q4[q] != pad) {
-                                R hv;
-                                if (a.pgen) {
-                                    hv = Bg[P];
+                    for (int u = 0; u < UGP; u++) {
+                        const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-                                    for (int e = P - 1; e >= 0; e--) hv = hv * xl[u][q] + Bg[e];
-                                } else {
-                                    const R d = xl[u][q] - xm;
-                                    hv = (R)a.ph[P];
+                        for (int q = 0; q < 4; q++) {
+                            if (DIRECT) {
+                                if (q4[q] != pad) {
+                                    R hv;
+                                    if (D == 1 && a.pgen) {
+                                        hv = Bg[P];
 #pragma unroll
-                                    for (int e = P - 1; e >= 0; e--) hv = hv * d + (R)a.ph[e];
+                                        for (int e = P - 1; e >= 0; e--) hv = hv * xl[u][q] + Bg[e];
+                                    } else {
+                                        const R dd = xl[u][q] - xm[d];
+                                        hv = (R)a.ph[P];
+#pragma unroll
+                                        for (int e = P - 1; e >= 0; e--) hv = hv * dd + (R)a.ph[e];
+                                    }
+                                    Eh[d] += (double)hv;
                                 }
-                                Eh += (double)hv;
+                            } else {
+                                acc_pow<R, P>(T[d], xl[u][q], (R)1);
                             }
-                        } else {
-                            acc_pow<R, P>(T, xl[u][q], (R)1);
                         }
                     }
                 }
             }
         }
         if (mine) {
-            R xnew;
+            R xnew[D];
             if (mode == M_PREP) {
-                xnew = tn;
-                a.theta_n[i] = tn;
-            } else {
-                double s;
-                if (DIRECT) {
-                    s = Eh;
-                } else if (a.pgen) {
-                    // general coupling: sum_b x_m^b sum_a c[a][b] M_a, minus g(x_m, x_m)
-                    double M[P + 1];
-                    M[0] = (assigned ? (double)lam : 0.0) + (double)cv;
 #pragma unroll
-                    for (int k = 1; k <= P; k++) M[k] = W[k - 1] + (double)T[k - 1];
-                    const double x = (double)xm;
-                    double xp[2 * P + 1];
-                    xp[0] = 1.0;
-#pragma unroll
-                    for (int k = 1; k <= 2 * P; k++) xp[k] = xp[k - 1] * x;
-                    s = 0.0;
-                    double own = 0.0;
-#pragma unroll
-                    for (int q = 0; q <= P; q++)
-#pragma unroll
-                        for (int b = 0; b <= P; b++) {
-                            const double cab = a.pgen[q * (P + 1) + b];
-                            s += cab * M[q] * xp[b];
-                            own += cab * xp[q + b];
-                        }
-                    if (assigned) s -= own;
-                } else {
-                    // g_k(x_m): Taylor shift of h by -x_m (repeated synthetic division)
-                    double g[P + 1];
-#pragma unroll
-                    for (int k = 0; k <= P; k++) g[k] = a.ph[k];
-                    const double c = -(double)xm;
-#pragma unroll
-                    for (int k = 0; k < P; k++)
-#pragma unroll
-                        for (int j = P - 1; j >= k; j--) g[j] += c * g[j + 1];
-                    s = g[0] * ((assigned ? (double)lam : 0.0) + (double)cv);
-#pragma unroll
-                    for (int k = 1; k <= P; k++) s += g[k] * (W[k - 1] + (double)T[k - 1]);
-                    if (assigned) s -= a.ph[0];
+                for (int d = 0; d < D; d++) {
+                    xnew[d] = tn[d];
+                    a.theta_n[d * n + i] = tn[d];
                 }
-                double f = 0.0;
-                for (int j = a.pq; j >= 0; j--) f = f * (double)xm + a.pf[j];
-                const R H = (R)((double)om + f + (double)knv * s);
-                if (mode == M_RHS) {
-                    a.state_out[a.perm[i]] = H;
-                    xnew = (R)0;
-                } else if (mode == M_EULER) {
-                    xnew = tn + a.dt * H;
-                    a.theta_n[i] = xnew;
-                } else if (a.stage == 0) {
-                    a.acc[i] = H;
-                    xnew = tn + (R)0.5 * a.dt * H;
-                } else if (a.stage == 1) {
-                    a.acc[i] = av + (R)2 * H;
-                    xnew = tn + (R)0.5 * a.dt * H;
-                } else if (a.stage == 2) {
-                    a.acc[i] = av + (R)2 * H;
-                    xnew = tn + a.dt * H;
+            } else {
+                // local term: f(x) (one component, Horner) or f_d(x_0, x_1)
+                double fl[D];
+                if (D == 1) {
+                    double f = 0.0;
+                    for (int j = a.pq; j >= 0; j--) f = f * (double)xm[0] + a.pf[j];
+                    fl[0] = f;
                 } else {
-                    xnew = tn + a.dt / (R)6 * (av + H);
-                    a.theta_n[i] = xnew;
+#pragma unroll
+                    for (int d = 0; d < D; d++) {
+                        double f = 0.0, ui = 1.0;
+#pragma unroll
+                        for (int ii = 0; ii <= 3; ii++) {
+                            double vj = 1.0;
+#pragma unroll
+                            for (int jj = 0; jj <= 3; jj++) {
+                                f += a.pf2[d * 16 + ii * 4 + jj] * ui * vj;
+                                vj *= (double)xm[D - 1];
+                            }
+                            ui *= (double)xm[0];
+                        }
+                        fl[d] = f;
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    double s;
+                    if (DIRECT) {
+                        s = Eh[d];
+                    } else if (D == 1 && a.pgen) {
+                        // general coupling: sum_b x_m^b sum_a c[a][b] M_a, minus g(x_m, x_m)
+                        double M[P + 1];
+                        M[0] = (assigned ? (double)lam : 0.0) + (double)cv;
+#pragma unroll
+                        for (int k = 1; k <= P; k++) M[k] = W[d][k - 1] + (double)T[d][k - 1];
+                        const double x = (double)xm[d];
+                        double xp[2 * P + 1];
+                        xp[0] = 1.0;
+#pragma unroll
+                        for (int k = 1; k <= 2 * P; k++) xp[k] = xp[k - 1] * x;
+                        s = 0.0;
+                        double own = 0.0;
+#pragma unroll
+                        for (int q = 0; q <= P; q++)
+#pragma unroll
+                            for (int b = 0; b <= P; b++) {
+                                const double cab = a.pgen[q * (P + 1) + b];
+                                s += cab * M[q] * xp[b];
+                                own += cab * xp[q + b];
+                            }
+                        if (assigned) s -= own;
+                    } else {
+                        // g_k(x_m): Taylor shift of h by -x_m (repeated synthetic division)
+                        double g[P + 1];
+#pragma unroll
+                        for (int k = 0; k <= P; k++) g[k] = a.ph[k];
+                        const double c = -(double)xm[d];
+#pragma unroll
+                        for (int k = 0; k < P; k++)
+#pragma unroll
+                            for (int j = P - 1; j >= k; j--) g[j] += c * g[j + 1];
+                        s = g[0] * ((assigned ? (double)lam : 0.0) + (double)cv);
+#pragma unroll
+                        for (int k = 1; k <= P; k++) s += g[k] * (W[d][k - 1] + (double)T[d][k - 1]);
+                        if (assigned) s -= a.ph[0];
+                    }
+                    const R H = (R)((d == 0 ? (double)om : 0.0) + fl[d] + (double)knv * s);
+                    if (mode == M_RHS) {
+                        a.state_out[d * n + a.perm[i]] = H;
+                        xnew[d] = (R)0;
+                    } else if (mode == M_EULER) {
+                        xnew[d] = tn[d] + a.dt * H;
+                        a.theta_n[d * n + i] = xnew[d];
+                    } else if (a.stage == 0) {
+                        a.acc[d * n + i] = H;
+                        xnew[d] = tn[d] + (R)0.5 * a.dt * H;
+                    } else if (a.stage == 1) {
+                        a.acc[d * n + i] = av[d] + (R)2 * H;
+                        xnew[d] = tn[d] + (R)0.5 * a.dt * H;
+                    } else if (a.stage == 2) {
+                        a.acc[d * n + i] = av[d] + (R)2 * H;
+                        xnew[d] = tn[d] + a.dt * H;
+                    } else {
+                        xnew[d] = tn[d] + a.dt / (R)6 * (av[d] + H);
+                        a.theta_n[d * n + i] = xnew[d];
+                    }
                 }
             }
             if (mode != M_RHS) {
-                a.th_out[i] = xnew;
-                if (assigned) {
-                    double xk = (double)xnew;
 #pragma unroll
-                    for (int k = 0; k < P; k++) {
-                        pd[k] += xk;
-                        xk *= (double)xnew;
+                for (int d = 0; d < D; d++) {
+                    a.th_out[d * xs + i] = xnew[d];
+                    if (assigned) {
+                        double xk = (double)xnew[d];
+#pragma unroll
+                        for (int k = 0; k < P; k++) {
+                            pd[d][k] += xk;
+                            xk *= (double)xnew[d];
+                        }
                     }
                 }
             }
@@ -1034,17 +1106,22 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
     if (mode == M_RHS || !assigned) return;
     // ---- unit moments of the next stage: fixed-order block reduction ----
 #pragma unroll
-    for (int k = 0; k < P; k++) {
-        double v = pd[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) red[wid][k] = v;
-    }
+    for (int d = 0; d < D; d++)
+#pragma unroll
+        for (int k = 0; k < P; k++) {
+            double v = pd[d][k];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) red[wid][d][k] = v;
+        }
     __syncthreads();
     if (tid == 0)
         for (int k = 0; k < P; k++) {
-            double v = red[0][k];
-            for (int w = 1; w < NW; w++) v += red[w][k];
-            a.q_out[(size_t)Un.qslot * P + k] = make_double2(v, 0.0);
+            double v[D];
+            for (int d = 0; d < D; d++) {
+                v[d] = red[0][d][k];
+                for (int w = 1; w < NW; w++) v[d] += red[w][d][k];
+            }
+            a.q_out[(size_t)Un.qslot * P + k] = make_double2(v[0], D == 2 ? v[D - 1] : 0.0);
         }
 }
 
@@ -1437,7 +1514,9 @@ struct PhaseState {
     void *gen = nullptr;     // general coupling coefficients on the device (R), or NULL
     double *pgen = nullptr;  // polynomial model: general coupling coefficients, or NULL
     int pq = -1;             // degree of the local polynomial f (-1: none)
+    int pdim = 1;            // polynomial model: state components per node (1 or 2)
     double ph[PMAX + 1] = {0}, pf[PMAX + 1] = {0};   // coefficients of h and f
+    double pf2[32] = {0};    // two components: local polynomials F[d][i][j]
     double K2n = 0;
     uint64_t tri_seed = 0, tri_thr = 0;
     TriBlock *tri_blocks = nullptr;   // direct triadic: (community, centres) blocks
@@ -1922,6 +2001,20 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         }
         for (int k = 0; k <= c->poly_q; k++)
             if (!std::isfinite(c->poly_f[k])) return set_error(CIA_EINVAL, "coupling.poly_f must be finite");
+        if (c->poly_dim < 0 || c->poly_dim > 2)
+            return set_error(CIA_EINVAL, "coupling.poly_dim = %d; supported 0..2", c->poly_dim);
+        if (c->poly_dim == 2) {
+            if (c->poly_g || c->poly_q >= 0)
+                return set_error(CIA_EUNSUPPORTED, "two components: poly_g and poly_f/poly_q are not supported");
+            if (bs) return set_error(CIA_EUNSUPPORTED, "two components: batched ensembles are not supported");
+            if (g->kind != CIA_GRAPH_CSR) return set_error(CIA_EUNSUPPORTED, "two components need a CSR graph");
+            if (c->poly_f2)
+                for (int k = 0; k < 32; k++) {
+                    if (!std::isfinite(c->poly_f2[k])) return set_error(CIA_EINVAL, "coupling.poly_f2 must be finite");
+                    s->pf2[k] = c->poly_f2[k];
+                }
+            s->pdim = 2;
+        }
         if (g->kind == CIA_GRAPH_COMPLETE && o->method == CIA_METHOD_DIRECT)
             return set_error(CIA_EUNSUPPORTED, "polynomial model: the direct method needs an explicit CSR graph");
         s->poly = true;
@@ -2015,7 +2108,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     const int64_t n = g->n;
     const size_t rs = f64 ? sizeof(double) : sizeof(float);
     // bytes per staged value: z for the phase models, x for the polynomial one
-    const int64_t zbytes = s->poly ? (int64_t)rs : (f64 ? 16 : 8);
+    const int64_t zbytes = s->poly ? (int64_t)rs * s->pdim : (f64 ? 16 : 8);
 
     // LDS staging capacity (community z values, plus one zero slot); uint16
     // local indices also bound it (the padding index lambda must fit)
@@ -2181,8 +2274,15 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         // out.
         double idx = 2.0 * (double)nnz_neg_staged + 4.0 * (double)(nnz_neg - nnz_neg_staged) + 4.0 * (double)nnz_pos;
         double zb = s->poly ? (double)rs : 2.0 * rs;   // staged and gathered value: z, or x
-        inf.bytes_per_rhs = (3.0 * rs + 2.0 * zb) * (double)n + idx;
-        inf.bytes_per_stage = (4.0 * rs + 2.0 * zb) * (double)n + idx;
+        if (s->poly && s->pdim == 2) {
+            // two components: every per-node stream and every gathered value doubles
+            // (omega, counts and indices do not)
+            inf.bytes_per_rhs = 2.0 * (2.0 * rs + 2.0 * zb) * (double)n + rs * (double)n + idx;
+            inf.bytes_per_stage = 2.0 * (3.0 * rs + 2.0 * zb) * (double)n + rs * (double)n + idx;
+        } else {
+            inf.bytes_per_rhs = (3.0 * rs + 2.0 * zb) * (double)n + idx;
+            inf.bytes_per_stage = (4.0 * rs + 2.0 * zb) * (double)n + idx;
+        }
         if (s->complete_direct) inf.bytes_per_rhs = inf.bytes_per_stage = (double)n * (2 * zb + 2 * rs);
     }
 
@@ -2221,18 +2321,20 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         }
     }
     unsigned char *raw;
-    CIA_TRY(dalloc(p, &raw, rs * n));
+    const int64_t nd = s->pdim;   // state components per node
+    CIA_TRY(dalloc(p, &raw, rs * n * nd));
     s->theta_n = raw;
-    CIA_TRY(dalloc(p, &raw, rs * n));
+    CIA_TRY(dalloc(p, &raw, rs * n * nd));
     s->acc = raw;
     for (int b = 0; b < 2; b++) {
         // z arrays carry one extra zero slot at position n (the padding target)
         CIA_TRY(dalloc(p, &raw, 2 * rs * (n + 1)));
         CIA_HIP(hipMemset(raw + 2 * rs * n, 0, 2 * rs));
         s->cs[b] = raw;
-        // stage theta (random S-pos gathers and the FP64 path), with a zero slot
-        CIA_TRY(dalloc(p, &raw, rs * (n + 1)));
-        CIA_HIP(hipMemset(raw + rs * n, 0, rs));
+        // stage theta (random S-pos gathers and the FP64 path), with a zero
+        // slot at the end of every component
+        CIA_TRY(dalloc(p, &raw, rs * (n + 1) * nd));
+        for (int64_t d = 0; d < nd; d++) CIA_HIP(hipMemset(raw + rs * ((n + 1) * d + n), 0, rs));
         s->th[b] = raw;
         CIA_TRY(dalloc(p, &s->q[b], (size_t)std::max(1, nslots) * s->P));
     }
@@ -2340,6 +2442,7 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
         a.pf[k] = s->pf[k];
     }
     a.pq = s->pq;
+    for (int k = 0; k < 32; k++) a.pf2[k] = s->pf2[k];
     a.gen = static_cast<const R *>(s->gen);
     a.pgen = s->pgen;
     a.cnt = s->cnt;
@@ -2365,8 +2468,13 @@ template <typename R, int P, int BLOCK>
 static void launch_stage_v(PhaseState *s, const PhaseArgs<R> &a, hipStream_t st) {
     const dim3 g(s->nunits), b(BLOCK);
     if (s->poly) {
-        if (s->direct) hipLaunchKernelGGL((poly_stage_kernel<R, P, BLOCK, true>), g, b, s->smem, st, a);
-        else hipLaunchKernelGGL((poly_stage_kernel<R, P, BLOCK, false>), g, b, s->smem, st, a);
+        if (s->pdim == 2) {
+            if (s->direct) hipLaunchKernelGGL((poly_stage_kernel<R, P, BLOCK, true, 2>), g, b, s->smem, st, a);
+            else hipLaunchKernelGGL((poly_stage_kernel<R, P, BLOCK, false, 2>), g, b, s->smem, st, a);
+        } else {
+            if (s->direct) hipLaunchKernelGGL((poly_stage_kernel<R, P, BLOCK, true, 1>), g, b, s->smem, st, a);
+            else hipLaunchKernelGGL((poly_stage_kernel<R, P, BLOCK, false, 1>), g, b, s->smem, st, a);
+        }
         return;
     }
     if (s->tri) {
@@ -2723,8 +2831,9 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         // the last step's r(t) (its partials were left by the final stage)
         if (fold) CIA_TRY(launch_order<R>(p, s, ws, nullptr, steps, stride, nullptr, true));
         CIA_TRY(timing_begin(p, ws, KK_AUX));
-        hipLaunchKernelGGL((permute_out_kernel<R>), dim3(grid), dim3(256), 0, ws, n, s->perm,
-                           static_cast<const R *>(s->theta_n), static_cast<R *>(state));
+        for (int d = 0; d < s->pdim; d++)
+            hipLaunchKernelGGL((permute_out_kernel<R>), dim3(grid), dim3(256), 0, ws, n, s->perm,
+                               static_cast<const R *>(s->theta_n) + d * n, static_cast<R *>(state) + d * n);
         CIA_HIP(hipGetLastError());
         CIA_TRY(timing_end(p, ws));
         if (replay) {
@@ -2742,8 +2851,9 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         return CIA_OK;
     }
     CIA_TRY(timing_begin(p, st, KK_AUX));
-    hipLaunchKernelGGL((permute_out_kernel<R>), dim3(grid), dim3(256), 0, st, n, s->perm,
-                       static_cast<const R *>(s->theta_n), static_cast<R *>(state));
+    for (int d = 0; d < s->pdim; d++)
+        hipLaunchKernelGGL((permute_out_kernel<R>), dim3(grid), dim3(256), 0, st, n, s->perm,
+                           static_cast<const R *>(s->theta_n) + d * n, static_cast<R *>(state) + d * n);
     CIA_HIP(hipGetLastError());
     CIA_TRY(timing_end(p, st));
     if (want_r) {
@@ -2803,10 +2913,10 @@ static cia_status tune_impl(cia_plan *p, PhaseState *s, hipStream_t st, cia_tune
     const int64_t n = p->n;
     if (!s->tune_in) {
         unsigned char *raw;
-        CIA_TRY(dalloc(p, &raw, sizeof(R) * n));
-        CIA_HIP(hipMemset(raw, 0, sizeof(R) * n));
+        CIA_TRY(dalloc(p, &raw, sizeof(R) * n * s->pdim));
+        CIA_HIP(hipMemset(raw, 0, sizeof(R) * n * s->pdim));
         s->tune_in = raw;
-        CIA_TRY(dalloc(p, &raw, sizeof(R) * n));
+        CIA_TRY(dalloc(p, &raw, sizeof(R) * n * s->pdim));
         s->tune_out = raw;
     }
     hipEvent_t e0, e1;

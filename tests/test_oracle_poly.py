@@ -183,3 +183,21 @@ def test_osc2_components_match_the_one_component_oracle():
     got = oracle.osc2_rhs(n, rp, col, None, 3.0, h, np.zeros((2, 4, 4)), x)
     for d in range(2):
         assert rel(got[d], oracle.poly_rhs(n, rp, col, None, 3.0, h, None, x[d])) < 1e-13
+
+
+@pytest.mark.parametrize("stepper", ["rk4", "euler"])
+def test_osc2_integrate_is_the_stepper_map_of_the_harmonic_oscillator(stepper):
+    """Uncoupled linear local terms f = (v, -u): every node follows x <- M x
+    with M the stepper's matrix polynomial of dt A, A = [[0, 1], [-1, 0]]
+    (RK4: the degree-4 Taylor polynomial; Euler: I + dt A)."""
+    n, dt, steps = 5, 0.1, 30
+    F = np.zeros((2, 4, 4))
+    F[0, 0, 1] = 1.0
+    F[1, 1, 0] = -1.0
+    x0 = np.random.default_rng(65).normal(size=(2, n))
+    got = oracle.osc2_integrate(n, np.zeros(n + 1, np.int64), np.zeros(0, np.int32), None, 0.0, [0.0, 1.0], F, x0,
+                                dt, steps, stepper=stepper)
+    B = dt * np.array([[0.0, 1.0], [-1.0, 0.0]])
+    M = np.eye(2) + B if stepper == "euler" else np.eye(2) + B + B @ B / 2 + B @ B @ B / 6 + B @ B @ B @ B / 24
+    want = np.linalg.matrix_power(M, steps) @ x0
+    assert rel(got, want) < 1e-13
