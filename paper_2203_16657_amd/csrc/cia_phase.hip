@@ -38,6 +38,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <type_traits>
 
 #include "fastmath.h"
 #include "plan.h"
@@ -787,12 +788,40 @@ __device__ __forceinline__ void acc_pow(R (&T)[P], R x, R sign) {
     }
 }
 
+// The D values of one node, from an array of D-vectors (index v) or from
+// LDS at a byte offset: one 4/8/16-byte load.
+template <typename R, int D>
+__device__ __forceinline__ void ldv(const R *p, uint32_t v, R (&out)[D]) {
+    if constexpr (D == 1) {
+        out[0] = p[v];
+    } else {
+        using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+        const V2 t = reinterpret_cast<const V2 *>(p)[v];
+        out[0] = t.x;
+        out[1] = t.y;
+    }
+}
+
+template <typename R, int D>
+__device__ __forceinline__ void ldsv(const R *xsh, uint32_t byte_off, R (&out)[D]) {
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(xsh) + byte_off;
+    if constexpr (D == 1) {
+        out[0] = *reinterpret_cast<const R *>(b);
+    } else {
+        using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+        const V2 t = *reinterpret_cast<const V2 *>(b);
+        out[0] = t.x;
+        out[1] = t.y;
+    }
+}
+
 // D state components (1, or 2 for the two-component oscillators of the
-// paper's Table 1): component d of position i lives at d * n + i
-// (theta_n, acc) and d * (n + 1) + i (stage values, zero slot at n); LDS
-// holds the community's values interleaved, [lambda + 1][D], so one byte
-// offset of the S-neg stream reaches every component; the unit moments of
-// component d go to the .x (d = 0) and .y (d = 1) halves of the partials.
+// paper's Table 1): component d of position i lives at d * n + i in theta_n
+// and acc, and the stage values are D-vectors, [n + 1][D] with a zero vector
+// at n, so one load gathers every component of a partner; LDS holds the
+// community's values the same way, [lambda + 1][D], and one byte offset of
+// the S-neg stream reaches the whole vector; the unit moments of component d
+// go to the .x (d = 0) and .y (d = 1) halves of the partials.
 template <typename R, int P, int BLOCK, bool DIRECT, int D>
 __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
     constexpr int NW = BLOCK / 64;
@@ -809,14 +838,11 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
     const bool gather = mode != M_PREP;
     const int off = Un.off, lam = Un.lam;
     const int64_t n = a.pad_pos;          // nodes; stage arrays have a zero slot at n
-    const int64_t xs = n + 1;             // stride of a component in the stage arrays
 
     // ---- unit start: the community's values in LDS and its moments ----
     if (gather && assigned) {
         if (staged) {
-            for (int j = tid; j < lam; j += BLOCK)
-#pragma unroll
-                for (int d = 0; d < D; d++) xsh[j * D + d] = a.th_in[d * xs + off + j];
+            for (int j = tid; j < lam * D; j += BLOCK) xsh[j] = a.th_in[(int64_t)off * D + j];
             if (tid < D) xsh[lam * D + tid] = (R)0;
         }
         if (wid == NW - 1) {
@@ -875,8 +901,9 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                 for (int d = 0; d < D; d++) {
                     if (mode != M_RHS) tn[d] = a.theta_n[d * n + i];
                     if (mode == M_RK4 && a.stage > 0) av[d] = a.acc[d * n + i];
-                    xm[d] = staged ? xsh[(i - off) * D + d] : a.th_in[d * xs + i];
                 }
+                if (staged) ldv<R, D>(xsh, (uint32_t)(i - off), xm);
+                else ldv<R, D>(a.th_in, (uint32_t)i, xm);
             }
         }
         R T[D][P];
@@ -914,12 +941,16 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                         for (int u = 0; u < UN; u++) {
                             const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-                            for (int q = 0; q < 4; q++)
+                            for (int q = 0; q < 4; q++) {
+                                R xa[D], xb[D];
+                                ldsv<R, D>(xsh, q4[q] & 0xffffu, xa);
+                                ldsv<R, D>(xsh, q4[q] >> 16, xb);
 #pragma unroll
                                 for (int d = 0; d < D; d++) {
-                                    acc_pow<R, P>(T[d], xat(xsh, (q4[q] & 0xffffu) + d * (uint32_t)sizeof(R)), (R)-1);
-                                    acc_pow<R, P>(T[d], xat(xsh, (q4[q] >> 16) + d * (uint32_t)sizeof(R)), (R)-1);
+                                    acc_pow<R, P>(T[d], xa[d], (R)-1);
+                                    acc_pow<R, P>(T[d], xb[d], (R)-1);
                                 }
+                            }
                         }
                     }
                 } else {
@@ -928,21 +959,20 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                         uint4 v[UGL];
 #pragma unroll
                         for (int u = 0; u < UGL; u++) v[u] = k + u < S.w[0] ? ld_stream(col + (size_t)(k + u) * SLICE) : padp;
+                        R xl[UGL][4][D];
 #pragma unroll
-                        for (int d = 0; d < D; d++) {
-                            R xl[UGL][4];
-#pragma unroll
-                            for (int u = 0; u < UGL; u++) {
-                                xl[u][0] = a.th_in[d * xs + v[u].x];
-                                xl[u][1] = a.th_in[d * xs + v[u].y];
-                                xl[u][2] = a.th_in[d * xs + v[u].z];
-                                xl[u][3] = a.th_in[d * xs + v[u].w];
-                            }
-#pragma unroll
-                            for (int u = 0; u < UGL; u++)
-#pragma unroll
-                                for (int q = 0; q < 4; q++) acc_pow<R, P>(T[d], xl[u][q], (R)-1);
+                        for (int u = 0; u < UGL; u++) {
+                            ldv<R, D>(a.th_in, v[u].x, xl[u][0]);
+                            ldv<R, D>(a.th_in, v[u].y, xl[u][1]);
+                            ldv<R, D>(a.th_in, v[u].z, xl[u][2]);
+                            ldv<R, D>(a.th_in, v[u].w, xl[u][3]);
                         }
+#pragma unroll
+                        for (int u = 0; u < UGL; u++)
+#pragma unroll
+                            for (int q = 0; q < 4; q++)
+#pragma unroll
+                                for (int d = 0; d < D; d++) acc_pow<R, P>(T[d], xl[u][q][d], (R)-1);
                     }
                 }
             }
@@ -953,16 +983,16 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                 uint4 v[UGP];
 #pragma unroll
                 for (int u = 0; u < UGP; u++) v[u] = k + u < S.w[1] ? ld_stream(col + (size_t)(k + u) * SLICE) : padp;
+                R xl[UGP][4][D];   // the padding position holds 0
+#pragma unroll
+                for (int u = 0; u < UGP; u++) {
+                    ldv<R, D>(a.th_in, v[u].x, xl[u][0]);
+                    ldv<R, D>(a.th_in, v[u].y, xl[u][1]);
+                    ldv<R, D>(a.th_in, v[u].z, xl[u][2]);
+                    ldv<R, D>(a.th_in, v[u].w, xl[u][3]);
+                }
 #pragma unroll
                 for (int d = 0; d < D; d++) {
-                    R xl[UGP][4];
-#pragma unroll
-                    for (int u = 0; u < UGP; u++) {
-                        xl[u][0] = a.th_in[d * xs + v[u].x];   // the padding position holds 0
-                        xl[u][1] = a.th_in[d * xs + v[u].y];
-                        xl[u][2] = a.th_in[d * xs + v[u].z];
-                        xl[u][3] = a.th_in[d * xs + v[u].w];
-                    }
 #pragma unroll
                     for (int u = 0; u < UGP; u++) {
                         const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
@@ -974,9 +1004,9 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                                     if (D == 1 && a.pgen) {
                                         hv = Bg[P];
 #pragma unroll
-                                        for (int e = P - 1; e >= 0; e--) hv = hv * xl[u][q] + Bg[e];
+                                        for (int e = P - 1; e >= 0; e--) hv = hv * xl[u][q][d] + Bg[e];
                                     } else {
-                                        const R dd = xl[u][q] - xm[d];
+                                        const R dd = xl[u][q][d] - xm[d];
                                         hv = (R)a.ph[P];
 #pragma unroll
                                         for (int e = P - 1; e >= 0; e--) hv = hv * dd + (R)a.ph[e];
@@ -984,7 +1014,7 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                                     Eh[d] += (double)hv;
                                 }
                             } else {
-                                acc_pow<R, P>(T[d], xl[u][q], (R)1);
+                                acc_pow<R, P>(T[d], xl[u][q][d], (R)1);
                             }
                         }
                     }
@@ -1088,9 +1118,17 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                 }
             }
             if (mode != M_RHS) {
+                if constexpr (D == 1) {
+                    a.th_out[i] = xnew[0];
+                } else {
+                    using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+                    V2 t;
+                    t.x = xnew[0];
+                    t.y = xnew[D - 1];
+                    reinterpret_cast<V2 *>(a.th_out)[i] = t;
+                }
 #pragma unroll
                 for (int d = 0; d < D; d++) {
-                    a.th_out[d * xs + i] = xnew[d];
                     if (assigned) {
                         double xk = (double)xnew[d];
 #pragma unroll
@@ -2331,10 +2369,10 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         CIA_TRY(dalloc(p, &raw, 2 * rs * (n + 1)));
         CIA_HIP(hipMemset(raw + 2 * rs * n, 0, 2 * rs));
         s->cs[b] = raw;
-        // stage theta (random S-pos gathers and the FP64 path), with a zero
-        // slot at the end of every component
+        // stage theta (random S-pos gathers and the FP64 path): nd values per
+        // node, node-major, and a zero entry at node n
         CIA_TRY(dalloc(p, &raw, rs * (n + 1) * nd));
-        for (int64_t d = 0; d < nd; d++) CIA_HIP(hipMemset(raw + rs * ((n + 1) * d + n), 0, rs));
+        CIA_HIP(hipMemset(raw + rs * n * nd, 0, rs * nd));
         s->th[b] = raw;
         CIA_TRY(dalloc(p, &s->q[b], (size_t)std::max(1, nslots) * s->P));
     }
