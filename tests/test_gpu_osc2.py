@@ -188,3 +188,39 @@ def test_osc2_full_size_sampled_rows(env):
         # rounding of the stored right-hand side (a few units in the last place)
         assert np.all(err <= 1e-5 * np.abs(c).max() + 4 * 2.0 ** -24 * np.abs(want))
         plan.close()
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_osc2_edge_cases(env, method, precision):
+    """A single node without edges, every node outside any community, and one
+    clique that is a single community (E1 alone)."""
+    cia, torch = env
+    tol = 1e-11 if precision else 1e-5
+    F = fhn_F(0.08, 0.7, 0.8, 0.5)
+    for labels in (np.zeros(1, np.int32), None):
+        plan = cia.Plan.poly(1, np.zeros(2, np.int64), np.zeros(0, np.int32), labels, np.array([0.2]), K=2.0,
+                             h=[0.0, 1.0], dim=2, f2=F, method=method, precision=precision)
+        got, xr = gpu_rhs(env, plan, np.array([[0.4], [-0.3]]), precision)
+        want = local_terms(F, xr, np.array([0.2]))
+        assert np.abs(got - want).max() < tol * max(1.0, np.abs(want).max())
+        plan.close()
+    P = W.random_phase_problem(800, 0, seed=4, p_out=0.02, unassigned=800)
+    g = P.graph
+    x = np.random.default_rng(75).uniform(-1, 1, (2, g.n))
+    plan = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, None, K=2.0, h=[0.0, 1.0], dim=2, f2=F, method=method,
+                         precision=precision)
+    got, xr = gpu_rhs(env, plan, x, precision)
+    want = oracle.osc2_rhs(g.n, g.row_ptr, g.col, None, 2.0, [0.0, 1.0], F, xr)
+    assert coupling_err(got, want, local_terms(F, xr, None)) < tol
+    plan.close()
+    n = 300
+    col = np.array([j for i in range(n) for j in range(n) if j != i], np.int32)
+    rp = np.arange(n + 1, dtype=np.int64) * (n - 1)
+    x = np.random.default_rng(76).uniform(-1, 1, (2, n))
+    plan = cia.Plan.poly(n, rp, col, np.zeros(n, np.int32), None, K=1.5, h=[0.1, 1.0, 0.3], dim=2, f2=vdp_F(0.3),
+                         method=method, precision=precision)
+    got, xr = gpu_rhs(env, plan, x, precision)
+    want = oracle.osc2_rhs(n, rp, col, None, 1.5, [0.1, 1.0, 0.3], vdp_F(0.3), xr)
+    assert coupling_err(got, want, local_terms(vdp_F(0.3), xr, None)) < tol
+    plan.close()

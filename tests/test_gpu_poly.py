@@ -207,3 +207,47 @@ def test_poly_graph_replay_and_autotune(env):
     b, _ = gpu_rhs(env, plan, x0, 0)
     assert rep.best_us <= rep.default_us and np.abs(a - b).max() <= 1e-6 * np.abs(a).max()
     plan.close()
+
+
+def clique(n):
+    col = np.array([j for i in range(n) for j in range(n) if j != i], np.int32)
+    return np.arange(n + 1, dtype=np.int64) * (n - 1), col
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_poly_edge_cases(env, method, precision):
+    """A single node without edges (labelled or not), every node outside any
+    community, and one clique that is a single community (E1 alone, empty
+    S-neg and S-pos)."""
+    cia, torch = env
+    tol = 1e-12 if precision else 1e-5
+    for labels in (np.zeros(1, np.int32), None):
+        om = np.array([0.3])
+        plan = cia.Plan.poly(1, np.zeros(2, np.int64), np.zeros(0, np.int32), labels, om, K=2.0, h=[0.1, 1.0],
+                             f=DZ_F, method=method, precision=precision)
+        x = np.array([0.7])
+        got, xr = gpu_rhs(env, plan, x, precision)
+        assert abs(got[0] - (0.3 + xr[0] - xr[0] ** 3)) < tol
+        plan.close()
+    P = W.random_phase_problem(800, 0, seed=4, p_out=0.02, unassigned=800)
+    g = P.graph
+    x = np.random.default_rng(60).uniform(-1, 1, g.n)
+    plan = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, None, K=2.0, h=[0.0, 1.0, 0.0, -0.3], method=method,
+                         precision=precision)
+    assert plan.info().n_unassigned == g.n
+    got, xr = gpu_rhs(env, plan, x, precision)
+    want = oracle.poly_rhs(g.n, g.row_ptr, g.col, None, 2.0, [0.0, 1.0, 0.0, -0.3], None, xr)
+    assert coupling_err(got, want, 0.0) < tol
+    plan.close()
+    n = 300
+    rp, col = clique(n)
+    x = np.random.default_rng(61).uniform(-1, 1, n)
+    plan = cia.Plan.poly(n, rp, col, np.zeros(n, np.int32), None, K=1.5, h=[0.2, 1.0, 0.5], f=DZ_F, method=method,
+                         precision=precision)
+    info = plan.info()
+    assert method == 1 or (info.nnz_neg == 0 and info.nnz_pos == 0 and info.ncomm == 1)
+    got, xr = gpu_rhs(env, plan, x, precision)
+    want = oracle.poly_rhs(n, rp, col, None, 1.5, [0.2, 1.0, 0.5], DZ_F, xr)
+    assert coupling_err(got, want, xr - xr ** 3) < tol
+    plan.close()
