@@ -100,7 +100,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(communities would shard across GPUs with one halo exchange of z per RK stage)",
               file=sys.stderr)
         sys.exit(2)

@@ -46,7 +46,7 @@ typedef enum cia_status {
     CIA_EINVAL = -1,        /* invalid argument or malformed graph */
     CIA_ENOMEM = -2,        /* host or device allocation failed */
     CIA_EHIP = -3,          /* a HIP runtime call failed */
-    CIA_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+    CIA_EUNSUPPORTED = -4,  /* valid request the library does not implement */
     CIA_ENONFINITE = -5     /* the integrated state contains NaN or Inf */
 } cia_status;
 
