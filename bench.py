@@ -213,6 +213,19 @@ def main():
                "sample": "%d FP64 RK4 step(s) (%d RHS evaluations) of the full workload, %.1f s" % (
                    csteps, rhs_per_step * csteps, ct)}
         log("cpu oracle: %.3e RHS node-updates/s on %d threads" % (cpu["value"], cpu["cores"]))
+        # the same oracle on one thread, over a sample of rows of one RHS
+        nt = oracle.num_threads()
+        oracle.set_num_threads(1)
+        try:
+            rows = np.sort(np.random.default_rng(0).choice(n, min(n, 50000), replace=False)).astype(np.int64)
+            t0 = time.time()
+            oracle.phase_rhs(g.n, g.row_ptr, g.col, P.omega, P.K, [0, 1], [0, 0], th, rows=rows)
+            c1 = time.time() - t0
+        finally:
+            oracle.set_num_threads(nt)
+        cpu["single_thread"] = {"value": len(rows) / c1, "unit": "RHS node-updates/s", "cores": 1,
+                                "sample": "%d sampled rows of one FP64 right-hand side, %.1f s" % (len(rows), c1)}
+        log("cpu oracle, one thread: %.3e RHS node-updates/s" % cpu["single_thread"]["value"])
 
     res = {
         "metric": "RHS node-updates/s, CIA vs direct, 1 MI355X, N=1e6, <=1e-5 rel err vs FP64",
