@@ -1,0 +1,91 @@
+"""Degenerate integrate calls on every model family, against what the
+definitions fix: zero steps return the state bit for bit and give r(t_0)
+alone; dt = 0 leaves it unchanged for any number of steps (phases reduced
+to [0, 2 pi) at every step end), with a constant r(t)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2203_16657_amd as cia
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cia.load()
+    return cia, torch
+
+
+def circ(a, b):
+    return float(np.abs(np.remainder(a - b + np.pi, 2 * np.pi) - np.pi).max())
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("stepper", [0, 1])
+def test_phase_zero_steps_and_zero_dt(env, method, precision, stepper):
+    cia, torch = env
+    P = W.random_phase_problem(3000, 7, seed=90, p_in=0.85, p_out=0.01, unassigned=37)
+    g = P.graph
+    dt_t = torch.float64 if precision else torch.float32
+    theta = np.random.default_rng(91).uniform(-3.0, 9.0, g.n)   # outside [0, 2 pi) on purpose
+    tol = 1e-12 if precision else 4e-6
+    for flags in (0, cia.CIA_FLAG_HIPGRAPH):
+        plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=2.0, method=method, precision=precision,
+                              stepper=stepper, flags=flags)
+        th = torch.as_tensor(theta, dtype=dt_t, device="cuda")
+        th0 = th.cpu().numpy()
+        r = np.full(1, -1.0)
+        plan.integrate(th, 0.01, 0, r)
+        assert np.array_equal(th.cpu().numpy(), th0)
+        assert abs(r[0] - oracle.order_parameter(th0.astype(np.float64))) < tol
+        r = np.full(6, -1.0)
+        plan.integrate(th, 0.0, 5, r)
+        got = th.cpu().numpy().astype(np.float64)
+        assert circ(got, th0.astype(np.float64)) < tol
+        assert np.all((got >= 0) & (got < 2 * np.pi))
+        assert np.abs(r - oracle.order_parameter(th0.astype(np.float64))).max() < tol
+        plan.close()
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_poly_zero_steps_and_zero_dt(env, dim):
+    cia, torch = env
+    g = W.kuramoto_small().graph
+    x0 = np.random.default_rng(92).uniform(-1, 1, (dim, g.n)).reshape(-1) if dim == 2 else \
+        np.random.default_rng(92).uniform(-1, 1, g.n)
+    kw = dict(dim=2, f2=np.ones((2, 4, 4)) * 0.1) if dim == 2 else dict(f=[0.0, 1.0, 0.0, -1.0])
+    for method in (0, 1):
+        plan = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, None, K=2.0, h=[0.0, 1.0], method=method,
+                             precision=1, **kw)
+        x = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
+        plan.integrate(x, 0.01, 0)
+        assert np.array_equal(x.cpu().numpy(), x0)
+        plan.integrate(x, 0.0, 4)
+        assert np.array_equal(x.cpu().numpy(), x0)
+        plan.close()
+
+
+@pytest.mark.parametrize("kind", ["rank1", "ring"])
+def test_structured_zero_steps_and_zero_dt(env, kind):
+    cia, torch = env
+    n = 5000
+    theta = np.random.default_rng(93).uniform(0, 2 * np.pi, n)
+    for method in (0, 1):
+        ab = dict(alpha=np.linspace(0.5, 1.5, n), beta=np.linspace(1.2, 0.7, n)) if kind == "rank1" else {}
+        plan = cia.Plan.structured(n, kind, K=1.5, ring_k=40, method=method, precision=1, **ab)
+        th = torch.as_tensor(theta, device="cuda")
+        r = np.full(1, -1.0)
+        plan.integrate(th, 0.01, 0, r)
+        assert circ(th.cpu().numpy(), theta) < 1e-12
+        assert abs(r[0] - oracle.order_parameter(theta)) < 1e-12
+        r = np.full(4, -1.0)
+        plan.integrate(th, 0.0, 3, r)
+        assert circ(th.cpu().numpy(), theta) < 1e-12
+        assert np.abs(r - oracle.order_parameter(theta)).max() < 1e-12
+        plan.close()
