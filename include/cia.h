@@ -165,7 +165,7 @@ typedef struct cia_coupling {
        2-D Fourier series of App. A.2 (eq. FourierRealExpansion):
          g = sum_{a,b=0..p} c11[a][b] cos(a theta_l) cos(b theta_m) + c12[a][b] cos(a theta_l) sin(b theta_m)
                           + c21[a][b] sin(a theta_l) cos(b theta_m) + c22[a][b] sin(a theta_l) sin(b theta_m);
-       host [(p+1)*(p+1)] each (p = 1..4), row a, column b.  All four set: they define the
+       host [(p+1)*(p+1)] each (p = 1..8), row a, column b.  All four set: they define the
        coupling and d_sin/d_cos are ignored; all NULL: the difference form.
        CSR or complete graphs, CIA or direct (not the all-to-all direct kernel),
        not batched. */

@@ -48,7 +48,7 @@ namespace cia {
 constexpr int PMAX = 8;
 constexpr double WIDE_COMMUNITY = 1e5;   // FP64 observables above this size
 constexpr size_t LDS_BYTES = 64 * 1024;  // dynamic LDS budget of a stage block
-constexpr int GEN_PMAX = 4;              // largest order of the general (non-difference) coupling
+constexpr int GEN_PMAX = 8;              // largest order of the general (non-difference) coupling
 constexpr int SLICE = 64;                // rows per slice = lanes per wavefront
 
 // unit flag bits

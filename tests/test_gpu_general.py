@@ -1,6 +1,6 @@
 """GPU parity of the general (non-difference) phase coupling g(theta_l,
 theta_m), the real 2-D Fourier series of App. A.2, against the FP64 oracle:
-community graphs with nodes outside every community, orders 1..4, both
+community graphs with nodes outside every community, orders 1..8, both
 methods and precisions, the complete graph (one community, also above 1e5
 nodes on the FP64 observable path), the difference form as a special case,
 and an RK4 trajectory."""
@@ -45,7 +45,7 @@ def gpu_rhs(torch, plan, th, precision):
 
 
 @pytest.mark.parametrize("graph", ["config1", "config2_scaled"])
-@pytest.mark.parametrize("p", [1, 2, 4])
+@pytest.mark.parametrize("p", [1, 2, 4, 6, 8])
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_general_rhs(env, graph, p, method, precision):
@@ -138,7 +138,7 @@ def test_general_rejections(env):
     P = W.kuramoto_small()
     g = P.graph
     with pytest.raises(cia.CIAError):
-        cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, None, gen=coeffs(5, 1))      # order above 4
+        cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, None, gen=coeffs(9, 1))      # order above 8
     with pytest.raises(cia.CIAError):
         cia.Plan.phase(1000, complete=True, gen=coeffs(1, 2), method=1)              # all-to-all direct kernel
 
