@@ -181,7 +181,8 @@ typedef struct cia_coupling {
          v_m' =           f_1(u_m, v_m) + (K/N) sum_l a_ml h(v_l - v_m),
          f_d(u, v) = sum_{i,j=0..3} poly_f2[16 d + 4 i + j] u^i v^j.
        Two components: the state arrays are [2][n] (all u, then all v), poly_f2 is host
-       [2][4][4] (NULL = no local term), poly_f/poly_q and poly_g are not allowed, CSR graphs. */
+       [2][4][4] (NULL = no local term), poly_f/poly_q and poly_g are not allowed, CSR graphs
+       (both methods) or the complete graph (CIA method). */
     int32_t poly_dim;
     int32_t reserved3;
     const double *poly_f2;

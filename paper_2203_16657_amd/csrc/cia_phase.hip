@@ -2045,7 +2045,6 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
             if (c->poly_g || c->poly_q >= 0)
                 return set_error(CIA_EUNSUPPORTED, "two components: poly_g and poly_f/poly_q are not supported");
             if (bs) return set_error(CIA_EUNSUPPORTED, "two components: batched ensembles are not supported");
-            if (g->kind != CIA_GRAPH_CSR) return set_error(CIA_EUNSUPPORTED, "two components need a CSR graph");
             if (c->poly_f2)
                 for (int k = 0; k < 32; k++) {
                     if (!std::isfinite(c->poly_f2[k])) return set_error(CIA_EINVAL, "coupling.poly_f2 must be finite");

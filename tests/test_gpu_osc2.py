@@ -163,7 +163,7 @@ def test_osc2_rejects_unsupported(env):
     with pytest.raises(cia.CIAError):
         cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, None, dim=2, g=np.eye(2))
     with pytest.raises(cia.CIAError):
-        cia.Plan.poly(1000, complete=True, h=[0.0, 1.0], dim=2)
+        cia.Plan.poly(1000, complete=True, h=[0.0, 1.0], dim=2, method=1)   # all-to-all needs the CIA method
     with pytest.raises(cia.CIAError):
         cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, None, h=[0.0, 1.0], dim=3)
 
@@ -224,3 +224,37 @@ def test_osc2_edge_cases(env, method, precision):
     want = oracle.osc2_rhs(n, rp, col, None, 1.5, [0.1, 1.0, 0.3], vdp_F(0.3), xr)
     assert coupling_err(got, want, local_terms(vdp_F(0.3), xr, None)) < tol
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_osc2_complete_graph(env, precision):
+    """All-to-all coupled van der Pol and FitzHugh-Nagumo oscillators (one
+    community, E1 alone) against the oracle's pair sum, one RHS and an RK4
+    trajectory."""
+    cia, torch = env
+    n = 3000
+    rng = np.random.default_rng(77)
+    x = rng.uniform(-2, 2, (2, n))
+    om = 0.3 * rng.normal(size=n)
+    for F, h in ((vdp_F(0.4), [0.0, 1.0]), (fhn_F(0.08, 0.7, 0.8, 0.5), [0.0, 1.0, 0.0, -0.1])):
+        plan = cia.Plan.poly(n, complete=True, omega=om, K=1.5, h=h, dim=2, f2=F, precision=precision)
+        got, xr = gpu_rhs(env, plan, x, precision)
+        want = oracle.osc2_rhs(n, None, None, om, 1.5, h, F, xr, complete=True)
+        err = coupling_err(got, want, local_terms(F, xr, om))
+        say("complete prec", precision, "coupling rel_inf", err)
+        assert err < (1e-12 if precision else 1e-5)
+        plan.close()
+    if precision:
+        n = 400
+        x0 = rng.uniform(-2, 2, (2, n))
+        F = vdp_F(0.4)
+        rp = np.arange(n + 1, dtype=np.int64) * (n - 1)
+        col = np.array([j for i in range(n) for j in range(n) if j != i], np.int32)
+        want = oracle.osc2_integrate(n, rp, col, None, 1.5, [0.0, 1.0], F, x0, 0.01, 50)
+        plan = cia.Plan.poly(n, complete=True, K=1.5, h=[0.0, 1.0], dim=2, f2=F, precision=1)
+        xt = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
+        plan.integrate(xt, 0.01, 50)
+        d = float(np.abs(xt.cpu().numpy() - want).max())
+        say("complete trajectory max |dx|", d)
+        assert d < 1e-11
+        plan.close()
