@@ -68,7 +68,10 @@ typedef enum cia_status {
 #define CIA_MODEL_POLY 3     /* polynomial difference coupling (App. A.3; Desai-Zwanzig, App. A.5):
                                 x_m' = omega_m + sum_{j<=poly_q} f_j x_m^j
                                        + (K/N) sum_l a_ml h(x_l - x_m),
-                                h(x) = sum_{a<=p} h_a x^a; no phase wrapping, no r(t) */
+                                h(x) = sum_{a<=p} h_a x^a; no phase wrapping, no r(t).
+                                Variants: a general coupling g(x_l, x_m) (poly_g) and two
+                                state components per node (poly_dim = 2: van der Pol /
+                                FitzHugh-Nagumo of Table 1), see cia_coupling */
 #define CIA_MODEL_FLOCK 2    /* Cucker-Smale in 3-D (App. A.6): s_m' = v_m,
                                 v_m' = (1/N) sum_l a_ml w(|s_l - s_m|) (v_l - v_m),
                                 w(r) = cs_K / (cs_sigma^2 + r^2)^cs_beta */
