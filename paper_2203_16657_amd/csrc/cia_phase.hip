@@ -452,7 +452,17 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     //      fixed order over the units of the community) ----
     if (gather && assigned) {
         if (staged) {
-            for (int j = tid; j < lam; j += BLOCK) zsh[j] = a.cs_in[off + j];
+            // eight loads in flight per thread before the LDS writes
+            constexpr int US = 8;
+            for (int j0 = tid; j0 < lam; j0 += BLOCK * US) {
+                cx<R> v[US];
+#pragma unroll
+                for (int u = 0; u < US; u++)
+                    if (j0 + u * BLOCK < lam) v[u] = a.cs_in[off + j0 + u * BLOCK];
+#pragma unroll
+                for (int u = 0; u < US; u++)
+                    if (j0 + u * BLOCK < lam) zsh[j0 + u * BLOCK] = v[u];
+            }
             if (tid == 0) zsh[lam] = cx<R>{(R)0, (R)0};   // slot of the padding index
         }
         if (wid == NW - 1) {
@@ -842,7 +852,17 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
     // ---- unit start: the community's values in LDS and its moments ----
     if (gather && assigned) {
         if (staged) {
-            for (int j = tid; j < lam * D; j += BLOCK) xsh[j] = a.th_in[(int64_t)off * D + j];
+            constexpr int US = 8;   // loads in flight per thread before the LDS writes
+            const int nv = lam * D;
+            for (int j0 = tid; j0 < nv; j0 += BLOCK * US) {
+                R v[US];
+#pragma unroll
+                for (int u = 0; u < US; u++)
+                    if (j0 + u * BLOCK < nv) v[u] = a.th_in[(int64_t)off * D + j0 + u * BLOCK];
+#pragma unroll
+                for (int u = 0; u < US; u++)
+                    if (j0 + u * BLOCK < nv) xsh[j0 + u * BLOCK] = v[u];
+            }
             if (tid < D) xsh[lam * D + tid] = (R)0;
         }
         if (wid == NW - 1) {
