@@ -227,12 +227,24 @@ __device__ __forceinline__ void ring_windows(const SArgs<R> &a, int64_t a0, cons
             if (st - q * n < 0) q -= 1;
             const int64_t sp = st - q * n;   // in [0, n)
             const int64_t tl = sp / STILE;
-            // sum of z^k over the start tile up to sp
+            // sum of z^k over the start tile up to sp (at most SNPT per thread,
+            // loads issued together)
             double2 pt = make_double2(0.0, 0.0);
-            for (int64_t i = tl * STILE + t; i < sp; i += SB) {
-                const zc<R> z = zpow(a.z_in[i], k);
-                pt.x += (double)z.x;
-                pt.y += (double)z.y;
+            {
+                zc<R> zt[SNPT];
+#pragma unroll
+                for (int u = 0; u < SNPT; u++) {
+                    const int64_t i = tl * STILE + t + (int64_t)u * SB;
+                    zt[u] = i < sp ? a.z_in[i] : zc<R>{(R)0, (R)0};
+                }
+#pragma unroll
+                for (int u = 0; u < SNPT; u++) {
+                    if (tl * STILE + t + (int64_t)u * SB < sp) {
+                        const zc<R> z = zpow(zt[u], k);
+                        pt.x += (double)z.x;
+                        pt.y += (double)z.y;
+                    }
+                }
             }
             pt = block_sum<SB>(pt, sh);
             const double2 o = off[tl * P + (k - 1)];
@@ -240,10 +252,12 @@ __device__ __forceinline__ void ring_windows(const SArgs<R> &a, int64_t a0, cons
             // this thread's positions st + SNPT t + e, then a block scan
             zc<R> v[SNPT];
             double2 ts = make_double2(0.0, 0.0);
+            int64_t x0 = (st + (int64_t)SNPT * t) % n;   // one division per thread
+            if (x0 < 0) x0 += n;
 #pragma unroll
             for (int e = 0; e < SNPT; e++) {
-                int64_t x = (st + (int64_t)SNPT * t + e) % n;
-                if (x < 0) x += n;
+                int64_t x = x0 + e;
+                while (x >= n) x -= n;
                 v[e] = zpow(a.z_in[x], k);
                 ts.x += (double)v[e].x;
                 ts.y += (double)v[e].y;
