@@ -390,12 +390,35 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
     float *sY = lds;                       // [6][lam]
     float *sF = lds + ((6 * lam + 3) & ~3);  // [lam][Rp], 16-byte aligned
     if (staged) {
-        for (int q = threadIdx.x; q < 6 * lam; q += blockDim.x) {
-            const int d = q / lam, j = q - d * lam;
-            sY[q] = a.Ys[d * n + c0 + j];
+        // eight loads in flight per thread before the LDS writes
+        constexpr int US = 8;
+        const int ny = 6 * lam;
+        for (int q0 = threadIdx.x; q0 < ny; q0 += FBLOCK * US) {
+            float v[US];
+#pragma unroll
+            for (int u = 0; u < US; u++) {
+                const int q = q0 + u * FBLOCK;
+                if (q < ny) {
+                    const int d = q / lam, j = q - d * lam;
+                    v[u] = a.Ys[d * n + c0 + j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < US; u++)
+                if (q0 + u * FBLOCK < ny) sY[q0 + u * FBLOCK] = v[u];
         }
-        if (!fb)
-            for (int q = threadIdx.x; q < lam * Rp; q += blockDim.x) sF[q] = a.F[c0 * Rp + q];
+        if (!fb) {
+            const int nf = lam * Rp;
+            for (int q0 = threadIdx.x; q0 < nf; q0 += FBLOCK * US) {
+                float v[US];
+#pragma unroll
+                for (int u = 0; u < US; u++)
+                    if (q0 + u * FBLOCK < nf) v[u] = a.F[c0 * Rp + q0 + u * FBLOCK];
+#pragma unroll
+                for (int u = 0; u < US; u++)
+                    if (q0 + u * FBLOCK < nf) sF[q0 + u * FBLOCK] = v[u];
+            }
+        }
     }
     __syncthreads();
     // TPR consecutive lanes share a row (a row's group never straddles a
