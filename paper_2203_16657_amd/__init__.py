@@ -180,6 +180,34 @@ def _dev_ptr(t):
     return t.data_ptr()
 
 
+def _need_len(name, a, n):
+    """The C side reads exactly n entries of a host array: check before the call."""
+    if a is not None and (a.ndim != 1 or a.shape[0] != n):
+        raise ValueError("%s: expected %d entries, got shape %s" % (name, n, tuple(a.shape)))
+
+
+def _check_csr(n, row_ptr, col):
+    if row_ptr is None or col is None:
+        raise ValueError("row_ptr and col are required for a CSR graph")
+    _need_len("row_ptr", row_ptr, n + 1)
+    if row_ptr[0] != 0 or (n and row_ptr[-1] > col.shape[0]):
+        raise ValueError("row_ptr must start at 0 and end at most at len(col) = %d" % col.shape[0])
+
+
+def _check_state(plan, t, name):
+    """A device tensor of plan.n * plan.dim values in the plan's precision
+    (the kernels read and write exactly that many)."""
+    import torch
+    if isinstance(t, int):
+        return
+    want = torch.float64 if plan.precision == CIA_F64 else torch.float32
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if t.dtype != want or not t.is_contiguous() or t.numel() != plan.n * plan.dim:
+        raise ValueError("%s: expected a contiguous %s tensor of %d values, got %s with %d" % (
+            name, want, plan.n * plan.dim, t.dtype, t.numel()))
+
+
 def _stream_ptr(stream):
     if stream is None:
         return None
@@ -215,6 +243,8 @@ def cia_build(graph: cia_graph, labels, coupling: cia_coupling, omega, options: 
     lib = load()
     lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
     om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
+    _need_len("labels", lab, graph.n)
+    _need_len("omega", om, graph.n)
     out = _vp()
     st = lib.cia_build(_c.byref(graph), _np_ptr(lab), _c.byref(coupling), _np_ptr(om),
                        None if options is None else _c.byref(options), _c.byref(out))
@@ -324,6 +354,7 @@ def cia_build_batch(graphs, labels, couplings, omegas, options: cia_options | No
         for b, l in enumerate(labels):
             if l is not None:
                 a = np.ascontiguousarray(l, dtype=np.int32)
+                _need_len("labels[%d]" % b, a, graphs[b].n)
                 keep.append(a)
                 lab_arr[b] = a.ctypes.data
     om_arr = None
@@ -332,6 +363,7 @@ def cia_build_batch(graphs, labels, couplings, omegas, options: cia_options | No
         for b, w in enumerate(omegas):
             if w is not None:
                 a = np.ascontiguousarray(w, dtype=np.float64)
+                _need_len("omega[%d]" % b, a, graphs[b].n)
                 keep.append(a)
                 om_arr[b] = a.ctypes.data
     out = _vp()
@@ -421,6 +453,8 @@ class Plan:
         load()
         rp = None if complete else np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = None if complete else np.ascontiguousarray(col, dtype=np.int32)
+        if not complete:
+            _check_csr(int(n), rp, cl)
         g = cia_graph(n=int(n), kind=CIA_GRAPH_COMPLETE if complete else CIA_GRAPH_CSR, reserved=0,
                       row_ptr=_np_ptr(rp), col=_np_ptr(cl))
         ds = np.ascontiguousarray(d_sin, dtype=np.float64)
@@ -455,6 +489,8 @@ class Plan:
         load()
         rp = None if complete else np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = None if complete else np.ascontiguousarray(col, dtype=np.int32)
+        if not complete:
+            _check_csr(int(n), rp, cl)
         graph = cia_graph(n=int(n), kind=CIA_GRAPH_COMPLETE if complete else CIA_GRAPH_CSR, reserved=0,
                           row_ptr=_np_ptr(rp), col=_np_ptr(cl))
         hc = np.ascontiguousarray(h, dtype=np.float64)
@@ -493,8 +529,12 @@ class Plan:
         load()
         al = be = None
         if kind == "rank1":
+            if alpha is None or beta is None:
+                raise ValueError("rank1 needs alpha and beta")
             al = np.ascontiguousarray(alpha, dtype=np.float64)
             be = np.ascontiguousarray(beta, dtype=np.float64)
+            _need_len("alpha", al, int(n))
+            _need_len("beta", be, int(n))
             gk = CIA_GRAPH_RANK1
         elif kind == "ring":
             gk = CIA_GRAPH_RING
@@ -525,6 +565,7 @@ class Plan:
         load()
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = np.ascontiguousarray(col, dtype=np.int32)
+        _check_csr(int(n), rp, cl)
         g = cia_graph(n=int(n), kind=CIA_GRAPH_CSR, reserved=0, row_ptr=_np_ptr(rp), col=_np_ptr(cl))
         tri = np.ascontiguousarray(np.zeros((0, 3)) if cross_tri is None else cross_tri, dtype=np.int32)
         h = cia_hypergraph(seed=int(tri_seed) & 0xFFFFFFFFFFFFFFFF, p_intra=float(p_tri), ntri=len(tri),
@@ -552,6 +593,7 @@ class Plan:
         for (n, row_ptr, col, labels, omega, K) in problems:
             rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
             cl = np.ascontiguousarray(col, dtype=np.int32)
+            _check_csr(int(n), rp, cl)
             keep += [rp, cl]
             graphs.append(cia_graph(n=int(n), kind=CIA_GRAPH_CSR, reserved=0, row_ptr=_np_ptr(rp), col=_np_ptr(cl)))
             c = cia_coupling_default()
@@ -579,6 +621,7 @@ class Plan:
         load()
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = np.ascontiguousarray(col, dtype=np.int32)
+        _check_csr(int(n), rp, cl)
         g = cia_graph(n=int(n), kind=CIA_GRAPH_CSR, reserved=0, row_ptr=_np_ptr(rp), col=_np_ptr(cl))
         c = cia_coupling_default()
         c.model = CIA_MODEL_FLOCK
@@ -611,9 +654,12 @@ class Plan:
         return np.float64 if self.precision == CIA_F64 else np.float32
 
     def rhs(self, state, dstate, stream=None):
+        _check_state(self, state, "state")
+        _check_state(self, dstate, "dstate")
         cia_rhs(self.handle, state, dstate, stream)
 
     def integrate(self, state, dt, steps, r_trace=None, stream=None):
+        _check_state(self, state, "state")
         cia_integrate(self.handle, state, dt, steps, r_trace, stream)
 
     def info(self) -> cia_plan_info:

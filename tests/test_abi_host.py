@@ -223,3 +223,21 @@ def test_fourier_coeffs_converge_for_smooth_coupling(cia):
         approx = dc[0] + sum(ds[k] * np.sin(k * xs) + dc[k] * np.cos(k * xs) for k in range(1, p + 1))
         errs.append(np.abs(approx - np.exp(np.cos(xs)) * np.sin(xs)).max())
     assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-6
+
+
+def test_binding_rejects_wrong_lengths(cia):
+    """The binding checks host array lengths before any call reads them."""
+    rp = np.array([0, 1, 2], np.int64)
+    col = np.array([1, 0], np.int32)
+    with pytest.raises(ValueError):
+        cia.Plan.phase(2, rp, col, np.zeros(3, np.int32))          # labels too long
+    with pytest.raises(ValueError):
+        cia.Plan.phase(2, rp, col, None, np.zeros(1))                # omega too short
+    with pytest.raises(ValueError):
+        cia.Plan.phase(3, rp, col)                                   # row_ptr of the wrong length
+    with pytest.raises(ValueError):
+        cia.Plan.poly(2, np.array([0, 1, 5], np.int64), col)         # row_ptr beyond col
+    with pytest.raises(ValueError):
+        cia.Plan.structured(4, "rank1", alpha=np.ones(4))            # beta missing
+    with pytest.raises(ValueError):
+        cia.Plan.structured(4, "rank1", alpha=np.ones(3), beta=np.ones(4))

@@ -89,3 +89,24 @@ def test_structured_zero_steps_and_zero_dt(env, kind):
         assert circ(th.cpu().numpy(), theta) < 1e-12
         assert np.abs(r - oracle.order_parameter(theta)).max() < 1e-12
         plan.close()
+
+
+def test_binding_rejects_wrong_state_tensors(env):
+    """A state of the wrong size, precision or device never reaches the kernels."""
+    cia, torch = env
+    g = W.kuramoto_small().graph
+    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, precision=cia.CIA_F32)
+    good = torch.zeros(g.n, dtype=torch.float32, device="cuda")
+    for bad in (torch.zeros(g.n - 1, dtype=torch.float32, device="cuda"),
+                torch.zeros(g.n, dtype=torch.float64, device="cuda"),
+                torch.zeros(g.n, dtype=torch.float32),
+                torch.zeros(2 * g.n, dtype=torch.float32, device="cuda")[::2]):
+        with pytest.raises(ValueError):
+            plan.integrate(bad, 0.01, 1)
+        with pytest.raises(ValueError):
+            plan.rhs(good, bad)
+    plan.close()
+    osc = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, h=[0.0, 1.0], dim=2)
+    with pytest.raises(ValueError):
+        osc.integrate(torch.zeros(g.n, dtype=torch.float32, device="cuda"), 0.01, 1)   # needs [2, n]
+    osc.close()
