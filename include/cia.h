@@ -245,7 +245,7 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream);
  * cia_integrate -- `steps` steps of the plan's stepper with step size dt,
  * every stage evaluated as in cia_rhs.
  *  state   : device, user order, updated in place.  Phase states are returned
- *            wrapped into [0, 2 pi).
+ *            wrapped into [0, 2 pi) (steps = 0 returns the state as given).
  *  r_trace : optional host [steps+1]; receives the global order parameter
  *            r(t_n) = |(1/N) sum_m exp(i theta_m)| (App. A.4) accumulated in
  *            FP64 (phase models only; NULL = not computed; plans of

@@ -110,3 +110,26 @@ def test_binding_rejects_wrong_state_tensors(env):
     with pytest.raises(ValueError):
         osc.integrate(torch.zeros(g.n, dtype=torch.float32, device="cuda"), 0.01, 1)   # needs [2, n]
     osc.close()
+
+
+def test_non_finite_state_is_reported(env):
+    """A NaN in the state surfaces as CIA_ENONFINITE when r(t) is traced
+    (phase model on a graph, both methods and precisions, and the ring)."""
+    cia, torch = env
+    g = W.kuramoto_small().graph
+    theta = np.random.default_rng(94).uniform(0, 2 * np.pi, g.n)
+    theta[17] = np.nan
+    for method in (0, 1):
+        for precision in (0, 1):
+            plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, K=2.0, method=method, precision=precision)
+            th = torch.as_tensor(theta, dtype=torch.float64 if precision else torch.float32, device="cuda")
+            with pytest.raises(cia.CIAError) as e:
+                plan.integrate(th, 0.01, 3, np.zeros(4))
+            assert e.value.status == cia.CIA_ENONFINITE
+            plan.close()
+    plan = cia.Plan.structured(1000, "ring", K=1.0, ring_k=10, precision=1)
+    th = torch.as_tensor(np.where(np.arange(1000) == 3, np.nan, 1.0), device="cuda")
+    with pytest.raises(cia.CIAError) as e:
+        plan.integrate(th, 0.01, 2, np.zeros(3))
+    assert e.value.status == cia.CIA_ENONFINITE
+    plan.close()
