@@ -126,3 +126,69 @@ def test_sweep(env, seed):
     say("   coupling rel_inf", err, "ncomm", info.ncomm, "unassigned", info.n_unassigned, "units", info.nunits)
     assert ok, (seed, err)
     plan.close()
+
+
+@pytest.mark.parametrize("flags", [0x200, 0x400, 0x600])
+@pytest.mark.parametrize("model", ["phase", "general", "poly", "osc2"])
+def test_global_gather_paths(env, flags, model):
+    """S-neg as int32 positions (FORCE_NEG32) and without LDS staging
+    (NO_LDS): the global-gather paths that communities too large for LDS
+    take, forced on a community graph, for every model on the stage kernels."""
+    cia, torch = env
+    P = W.random_phase_problem(3000, 6, seed=3000 + flags, p_in=0.8, p_out=0.01, unassigned=40)
+    g = P.graph
+    rng = np.random.default_rng(flags)
+    for precision in (0, 1):
+        dt = torch.float64 if precision else torch.float32
+        om = P.omega if precision else P.omega.astype(np.float32).astype(np.float64)
+        if model in ("phase", "general"):
+            th = rng.uniform(0, 2 * np.pi, g.n)
+            if model == "phase":
+                ds, dc = [0.0, 1.0, -0.4], [0.3, 0.2, 0.1]
+                plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=2.0, d_sin=ds, d_cos=dc,
+                                      precision=precision, flags=flags)
+            else:
+                cs = [rng.normal(size=(3, 3)) / 3 for _ in range(4)]
+                plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=2.0, gen=cs,
+                                      precision=precision, flags=flags)
+            t = torch.as_tensor(th, dtype=dt, device="cuda")
+            out = torch.empty_like(t)
+            plan.rhs(t, out)
+            torch.cuda.synchronize()
+            got, thr = out.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+            want = (oracle.phase_rhs(g.n, g.row_ptr, g.col, om, 2.0, ds, dc, thr) if model == "phase" else
+                    oracle.phase_rhs_general(g.n, g.row_ptr, g.col, om, 2.0, *cs, thr))
+            ok, err = within(got, want, om, precision)
+        elif model == "poly":
+            h = [0.1, 1.0, 0.0, -0.3]
+            x = rng.uniform(-1, 1, g.n)
+            plan = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, P.omega, K=2.0, h=h, precision=precision,
+                                 flags=flags)
+            t = torch.as_tensor(x, dtype=dt, device="cuda")
+            out = torch.empty_like(t)
+            plan.rhs(t, out)
+            torch.cuda.synchronize()
+            got, xr = out.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+            want = oracle.poly_rhs(g.n, g.row_ptr, g.col, om, 2.0, h, None, xr)
+            ok, err = within(got, want, om, precision)
+        else:
+            F = rng.normal(size=(2, 4, 4)) / 4.0
+            x = rng.uniform(-1, 1, (2, g.n))
+            plan = cia.Plan.poly(g.n, g.row_ptr, g.col, g.labels, P.omega, K=2.0, h=[0.0, 1.0], dim=2, f2=F,
+                                 precision=precision, flags=flags)
+            t = torch.as_tensor(x, dtype=dt, device="cuda")
+            out = torch.empty_like(t)
+            plan.rhs(t, out)
+            torch.cuda.synchronize()
+            got, xr = out.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+            want = oracle.osc2_rhs(g.n, g.row_ptr, g.col, om, 2.0, [0.0, 1.0], F, xr)
+            base = np.zeros_like(xr)
+            for d in range(2):
+                for i in range(4):
+                    for j in range(4):
+                        base[d] += F[d, i, j] * xr[0] ** i * xr[1] ** j
+            base[0] += om
+            ok, err = within(got, want, base, precision)
+        say("flags", hex(flags), model, "prec", precision, "coupling rel_inf", err, "ncomm", plan.info().ncomm)
+        assert ok, (flags, model, precision, err)
+        plan.close()
