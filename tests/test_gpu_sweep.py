@@ -128,12 +128,14 @@ def test_sweep(env, seed):
     plan.close()
 
 
-@pytest.mark.parametrize("flags", [0x200, 0x400, 0x600])
+@pytest.mark.parametrize("flags", [0x100, 0x200, 0x400, 0x600, 0x700])
 @pytest.mark.parametrize("model", ["phase", "general", "poly", "osc2"])
 def test_global_gather_paths(env, flags, model):
     """S-neg as int32 positions (FORCE_NEG32) and without LDS staging
     (NO_LDS): the global-gather paths that communities too large for LDS
-    take, forced on a community graph, for every model on the stage kernels."""
+    take, forced on a community graph, for every model on the stage kernels;
+    with FORCE_WIDE the FP64-observable variants of the phase models (the
+    polynomial models are FP64 in their moments anyway)."""
     cia, torch = env
     P = W.random_phase_problem(3000, 6, seed=3000 + flags, p_in=0.8, p_out=0.01, unassigned=40)
     g = P.graph
