@@ -31,12 +31,14 @@ def env():
 
 
 def within(got, want, base, precision):
-    """Coupling part C = want - base to a relative 1e-11 (FP64) or 2e-5
-    (FP32) of its largest value, plus the rounding of the stored total (a
-    few units in the last place of the kernel's precision)."""
+    """Coupling part C = want - base to a relative 1e-11 (FP64) or 1e-5
+    (FP32) of its largest value, plus the rounding of the stored total: the
+    kernel returns base + C in its own precision, and forming and storing that
+    sum rounds it by a few units in the last place of |base + C| whatever the
+    accuracy of C."""
     c = want - base
     e = np.abs((got - base) - c)
-    tol, ulp = (1e-11, 2.0 ** -52) if precision else (2e-5, 2.0 ** -23)
+    tol, ulp = (1e-11, 2.0 ** -52) if precision else (1e-5, 2.0 ** -23)
     ok = bool(np.all(e <= tol * np.abs(c).max() + 4 * ulp * np.abs(want)))
     return ok, float(e.max() / max(np.abs(c).max(), 1e-300))
 
