@@ -29,9 +29,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic():
+def profiled_traffic(workload):
     """HBM bytes per stage-kernel launch from the committed rocprofv3 counter
-    summary, valid only while the kernel sources are the ones profiled."""
+    summary, valid only for the workload it was measured on and while the
+    kernel sources are the ones profiled."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "phase_stage_kernel_kuramoto_n1e6.md")
     srcs = [os.path.join(ROOT, "paper_2203_16657_amd", "csrc", f) for f in ("cia_phase.hip", "plan.h", "fastmath.h")]
@@ -40,37 +41,48 @@ def profiled_traffic():
         h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
     except OSError:
         return None
-    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_bytes", "source_sha")))
-    if vals.get("source_sha256", "").strip() != h:
+    keys = ("traffic_bytes", "source_sha", "workload")
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(keys))
+    if vals.get("source_sha256", "").strip() != h or vals.get("workload", "").strip() != workload:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
 
-def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True, timing_every=0):
+def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True, timing_every=0, reps=5):
+    """Warm up with `warmup` steps, then time `reps` calls of exactly `steps`
+    steps, each from the same initial state and bracketed by HIP events on
+    the launch stream after a device synchronisation.  Returns the median
+    call's milliseconds, the library's kernel timing over all timed calls,
+    the last call's r(t) and every call's milliseconds."""
     import numpy as np
     tdt = torch.float64 if plan.precision == 1 else torch.float32
-    th = torch.as_tensor(theta0, dtype=tdt, device="cuda")
-    if warmup:
-        plan.integrate(th, dt, warmup, np.zeros(warmup + 1) if with_r else None)
-    torch.cuda.synchronize()
-    th = torch.as_tensor(theta0, dtype=tdt, device="cuda")
+    th0 = torch.as_tensor(theta0, dtype=tdt, device="cuda")
+    th = th0.clone()
+    # the warm-up passes the timed calls' trace, so the library sizes its
+    # device trace buffer before the timed region
     r = np.zeros(steps + 1) if with_r else None
+    if warmup:
+        plan.integrate(th, dt, warmup, r)
+    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     # kernel durations: HIP events around one stage launch in `timing_every`
     # (17: coprime with the 4 stages, so every stage is sampled), on the
     # launch stream, inside the timed region
     plan.set_timing(timing_every)
     plan.timing(reset=True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    plan.integrate(th, dt, steps, r, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    times = []
+    for _ in range(reps):
+        th.copy_(th0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        plan.integrate(th, dt, steps, r, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
     t = plan.timing(reset=True)
-    return ms, t, r
+    return float(np.median(times)), t, r, times
 
 
 def main():
@@ -85,6 +97,8 @@ def main():
     ap.add_argument("--triadic-n", type=int, default=6000, help="triadic: network size (sizes U[200, 2000])")
     ap.add_argument("--train-iters", type=int, default=3000, help="flock: optimiser steps of the basis")
     ap.add_argument("--ensemble-nmax", type=float, default=2e4, help="ensemble: largest instance size")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed calls of --steps steps each; the median call is reported")
     ap.add_argument("--direct-steps", type=int, default=100,
                     help="RK4 steps timed for the direct method")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -163,7 +177,8 @@ def main():
     log("cia plan: units=%d ncomm=%d nnz_neg=%d nnz_pos=%d unassigned=%d bytes/stage=%.3e (%.1fs)" % (
         info.nunits, info.ncomm, info.nnz_neg, info.nnz_pos, info.n_unassigned, info.bytes_per_stage,
         time.time() - t0))
-    ms, tim, r = time_integrate(plan, torch, P.theta0, P.dt, args.steps, args.warmup, timing_every=every)
+    ms, tim, r, calls = time_integrate(plan, torch, P.theta0, P.dt, args.steps, args.warmup, timing_every=every,
+                                       reps=args.reps)
     n = g.n
     rhs_per_step = 4
     value = n * rhs_per_step * args.steps / (ms / 1e3)
@@ -173,7 +188,7 @@ def main():
     if stage_avg_ms:
         achieved = info.bytes_per_stage / (stage_avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(P.name),
                 "kernel": "phase_stage_kernel", "avg_launch_us": round(stage_avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": info.bytes_per_stage, "timed_launches": tim.stage_launches}
         log("stage kernel avg %.2f us, %.1f GB/s algorithmic (%.1f%% of 8 TB/s)" % (
@@ -187,12 +202,13 @@ def main():
     dinfo = dplan.info()
     log("direct plan: units=%d nnz=%d (%.1fs)" % (dinfo.nunits, dinfo.nnz_pos, time.time() - t0))
     dsteps = min(args.direct_steps, args.steps)
-    dms, dtim, _ = time_integrate(dplan, torch, P.theta0, P.dt, dsteps, min(args.warmup, 5),
-                                  timing_every=0 if args.no_timing else 1)
+    dms, dtim, _, dcalls = time_integrate(dplan, torch, P.theta0, P.dt, dsteps, min(args.warmup, 5),
+                                          timing_every=0 if args.no_timing else 1, reps=args.reps)
     dvalue = n * rhs_per_step * dsteps / (dms / 1e3)
     d_stage_ms = dtim.stage_ms / max(dtim.stage_launches, 1) if dtim.stage_launches else None
     log("direct: %.3f ms/step, %.3e RHS node-updates/s" % (dms / dsteps, dvalue))
-    direct = {"value": dvalue, "ms_per_step": dms / dsteps, "steps": dsteps}
+    direct = {"value": dvalue, "ms_per_step": dms / dsteps, "steps": dsteps,
+              "ms_per_call": [round(x, 4) for x in dcalls]}
     if d_stage_ms:
         dach = dinfo.bytes_per_stage / (d_stage_ms / 1e3) / 1e9
         direct.update(avg_launch_us=round(d_stage_ms * 1e3, 2), achieved_gbs=round(dach, 1),
@@ -235,6 +251,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "timed_calls": {"count": len(calls), "statistic": "median",
+                        "ms_per_call": [round(x, 4) for x in calls]},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -256,11 +256,28 @@ def cia_rhs(plan, state, dstate, stream=None) -> None:
     _check(load().cia_rhs(plan, _dev_ptr(state), _dev_ptr(dstate), _stream_ptr(stream)))
 
 
+def _trace_ptr(plan, r_trace, steps: int):
+    """Host pointer of an r(t) trace after checking it can hold what the
+    library writes: (steps + 1) doubles per instance of the plan."""
+    if r_trace is None:
+        return None
+    if not isinstance(r_trace, np.ndarray) or r_trace.dtype != np.float64:
+        raise ValueError("r_trace must be a float64 numpy array")
+    if not (r_trace.flags.c_contiguous and r_trace.flags.writeable):
+        raise ValueError("r_trace must be C-contiguous and writeable")
+    if int(steps) < 0:
+        raise ValueError("steps must be >= 0")
+    cnt = _c.c_int32(0)
+    _check(load().cia_batch_offsets(plan, _c.byref(cnt), None))
+    need = int(cnt.value) * (int(steps) + 1)
+    if r_trace.size < need:
+        raise ValueError("r_trace holds %d values; this plan writes %d (%d instance(s) x %d steps + 1)" % (
+            r_trace.size, need, cnt.value, int(steps)))
+    return _np_ptr(r_trace)
+
+
 def cia_integrate(plan, state, dt: float, steps: int, r_trace=None, stream=None) -> None:
-    rt = None
-    if r_trace is not None:
-        assert r_trace.dtype == np.float64 and r_trace.flags.c_contiguous and len(r_trace) >= steps + 1
-        rt = _np_ptr(r_trace)
+    rt = _trace_ptr(plan, r_trace, steps)
     _check(load().cia_integrate(plan, _dev_ptr(state), float(dt), int(steps), rt, _stream_ptr(stream)))
 
 

@@ -2762,14 +2762,17 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
     const int64_t nr = s->batch > 0 ? s->batch : 1;   // traces
     const int64_t stride = steps + 1;
     if (want_r && s->r_cap < nr * stride) {
+        // at least 4096 slots per trace, and at least double the old size, so
+        // calls of up to 4095 steps never reallocate after the first one
+        const int64_t cap = std::max(nr * stride, std::max(2 * s->r_cap, nr * (int64_t)4096));
         if (s->r_dev) {
             CIA_HIP(hipFree(s->r_dev));
             for (auto &q : p->dev_allocs)
                 if (q == s->r_dev) q = nullptr;
             s->r_dev = nullptr;
         }
-        CIA_TRY(dalloc(p, &s->r_dev, (size_t)(nr * stride)));
-        s->r_cap = nr * stride;
+        CIA_TRY(dalloc(p, &s->r_dev, (size_t)cap));
+        s->r_cap = cap;
     }
     const bool rk4 = p->stepper == CIA_RK4;
     const int64_t grid = (n + 255) / 256;

@@ -217,3 +217,22 @@ def test_ensemble_256_instances(env):
     plan.integrate(th, 0.01, 10, r)
     r = r.reshape(256, 11)
     assert np.all(np.isfinite(r)) and np.all((r >= 0) & (r <= 1 + 1e-12))
+
+
+def test_trace_shorter_than_the_plan_writes_is_rejected(env):
+    """A batch plan writes (steps + 1) values of r per instance; a trace sized
+    for one network, a float32 trace or a strided one is refused on the host
+    before any device work, and a trace of the right size is accepted."""
+    cia, torch = env
+    ens = ensemble(4, 300, 800)
+    plan = cia.Plan.batch(problems(ens))
+    th = torch.as_tensor(np.concatenate([P.theta0 for P in ens]).astype(np.float32), device="cuda")
+    steps = 3
+    for bad in (np.zeros(steps + 1), np.zeros(4 * (steps + 1) - 1), np.zeros(4 * (steps + 1), dtype=np.float32),
+                np.zeros(8 * (steps + 1))[::2]):
+        with pytest.raises(ValueError):
+            plan.integrate(th, 0.01, steps, bad)
+    r = np.zeros(4 * (steps + 1))
+    plan.integrate(th, 0.01, steps, r)
+    assert np.all(np.isfinite(r)) and np.all(r > 0)
+    plan.close()
