@@ -23,6 +23,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # published FP32 vector peak (256 CUs at 2.4 GHz)
+FLOPS_PER_PAIR = 22        # flock pair evaluation, see bench_flock
 
 
 def log(*a):
@@ -60,7 +62,8 @@ def time_integrate(plan, torch, theta0, dt, steps, warmup, with_r=True, timing_e
     th = th0.clone()
     # the warm-up passes the timed calls' trace, so the library sizes its
     # device trace buffer before the timed region
-    r = np.zeros(steps + 1) if with_r else None
+    count = len(getattr(plan, "offsets", (0, 0))) - 1   # instances of a batched plan
+    r = np.zeros(count * (steps + 1)) if with_r else None
     if warmup:
         plan.integrate(th, dt, warmup, r)
     torch.cuda.synchronize()
@@ -96,7 +99,11 @@ def main():
                          "not the bench line)")
     ap.add_argument("--triadic-n", type=int, default=6000, help="triadic: network size (sizes U[200, 2000])")
     ap.add_argument("--train-iters", type=int, default=3000, help="flock: optimiser steps of the basis")
-    ap.add_argument("--ensemble-nmax", type=float, default=2e4, help="ensemble: largest instance size")
+    ap.add_argument("--ensemble-nmax", type=float, default=2e5, help="ensemble: largest instance size")
+    ap.add_argument("--ensemble-oracle-share", type=float, default=0.01,
+                    help="ensemble: share of every instance's rows the CPU oracle evaluates")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="ensemble: skip the 256 single-network plans")
     ap.add_argument("--reps", type=int, default=5,
                     help="timed calls of --steps steps each; the median call is reported")
     ap.add_argument("--direct-steps", type=int, default=100,
@@ -372,80 +379,132 @@ def bench_flock(args, cia, W, torch, np):
                   "loss_last": float(lt[-100:].mean())},
         "gain_vs_fourier": errs["fourier_p1"] / errs["learned_no_judge"],
     }
+    # roofline of the line's dominant kernel, flock_stage_kernel.  A community
+    # on the exact path evaluates w(|x_j - x_i|)(v_j - v_i) on all of its
+    # lambda (lambda - 1) ordered pairs, and every row its S-neg and S-pos
+    # entries: FLOPS_PER_PAIR FP32 operations each (3 differences, |d|^2 in 5,
+    # s^2 + r^2, log2, scale, exp2, times K, 3 differences and 3 FMAs of the
+    # velocity sum; a transcendental counts as one).  Those pair evaluations,
+    # not the 4-byte index streams, bound the kernel.
+    info = learned.info()
+    sizes = np.bincount(g.labels[g.labels >= 0])
+    fb_pairs = float((sizes * (sizes - 1)).sum()) * min(1.0, fallbacks / max(g.ncomm, 1))
+    pairs = fb_pairs + float(info.nnz_neg + info.nnz_pos)
+    st_us = res["learned_judged"]["stage_us"]
+    if st_us > 0:
+        tflops = pairs * FLOPS_PER_PAIR / (st_us * 1e-6) / 1e12
+        gbs = info.bytes_per_stage / (st_us * 1e-6) / 1e9
+        out["roofline"] = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                           "kernel": "flock_stage_kernel", "avg_launch_us": st_us,
+                           "pairs_per_launch": pairs, "flops_per_pair": FLOPS_PER_PAIR,
+                           "algorithmic_bytes_per_launch": info.bytes_per_stage,
+                           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log("flock stage kernel %.1f us: %.2f TFLOP/s (%.1f%% of FP32 vector peak), %.1f GB/s algorithmic" % (
+            st_us, tflops, 100 * tflops / FP32_PEAK_TFLOPS, gbs))
+    else:
+        out["roofline"] = None
     out["cpu_baseline"] = oracle_baseline(args, lambda r_: oracle.cs_rhs(
         n, g.row_ptr, g.col, F.K, F.sigma, F.beta, s64[:3], s64[3:], rows=r_), n, "flock_n200000 exact sum")
     print(json.dumps(out), flush=True)
 
 
 def bench_ensemble(args, cia, W, torch, np):
-    """The 256-instance ensemble (N log-uniform up to --ensemble-nmax, 4..500
-    communities, K swept over [0, 6]): one batched plan (plain and with the
-    replayed step graph) against 256 sequential single-network integrations."""
+    """The 256-instance ensemble: N log-uniform in [1e3, --ensemble-nmax]
+    (default 2e5, about 9.6e6 nodes in total), 4..500 communities, p_in in
+    [0.7, 0.95], p_out log-uniform in [1e-4, 1e-2], K swept over [0, 6].
+
+    Instances are generated one at a time and added to an incremental batch
+    build, so host memory holds one instance's adjacency at a time.  While an
+    instance's graph is in hand, the FP64 oracle evaluates a sample of its rows
+    (the cpu_baseline, and the reference of a sampled-row parity check of the
+    batched plan) and, unless --no-sequential, a single-network plan of it is
+    built, warmed up, timed over the same steps with HIP events and destroyed;
+    the sum of those 256 timings is the sequential comparison."""
+    import oracle
     count = 256
-    ens = [W.ensemble_member(b, n_hi=args.ensemble_nmax, count=count) for b in range(count)]
-    probs = [(P.graph.n, P.graph.row_ptr, P.graph.col, P.graph.labels, P.omega, P.K) for P in ens]
-    ntot = sum(P.graph.n for P in ens)
-    th0 = np.concatenate([P.theta0 for P in ens]).astype(np.float32)
-    steps = min(args.steps, 100)
-    log("ensemble: %d instances, N total %d" % (count, ntot))
-    res = {}
-    for name, flags in (("batched", cia.CIA_FLAG_AUTOTUNE), ("batched_graph", cia.CIA_FLAG_AUTOTUNE | cia.CIA_FLAG_HIPGRAPH)):
-        plan = cia.Plan.batch(probs, flags=flags)
-        th = torch.as_tensor(th0, device="cuda")
-        plan.integrate(th, 0.01, 2, np.zeros(count * 3))
-        th = torch.as_tensor(th0, device="cuda")
-        r = np.zeros(count * (steps + 1))
-        ms = timed(torch, lambda s: plan.integrate(th, 0.01, steps, r, stream=s))
-        res[name] = {"value": ntot * 4 * steps / (ms / 1e3), "ms_per_step": ms / steps, "units": plan.info().nunits}
-        log("%-14s %.3f ms/step" % (name, ms / steps))
-        plan.close()
-    plans = [cia.Plan.phase(*q[:5], K=q[5]) for q in probs]
-    ths = [torch.as_tensor(P.theta0.astype(np.float32), device="cuda") for P in ens]
-    rs = [np.zeros(steps + 1) for _ in ens]
-    for pl, t in zip(plans, ths):
-        pl.integrate(t, 0.01, 2, np.zeros(3))
-    ths = [torch.as_tensor(P.theta0.astype(np.float32), device="cuda") for P in ens]
-
-    def seq(s):
-        for pl, t, r in zip(plans, ths, rs):
-            pl.integrate(t, 0.01, steps, r, stream=s)
-
-    ms = timed(torch, seq)
-    res["sequential"] = {"value": ntot * 4 * steps / (ms / 1e3), "ms_per_step": ms / steps}
-    log("%-14s %.3f ms/step" % ("sequential", ms / steps))
+    steps = max(1, min(args.steps, 100))
+    share = args.ensemble_oracle_share
+    bb = cia.BatchBuilder(flags=cia.CIA_FLAG_AUTOTUNE)
+    rng = np.random.default_rng(23)
+    th_parts = []
+    seq_ms, cpu_s, cpu_rows, nnz = 0.0, 0.0, 0, 0
+    t0 = time.time()
+    for b in range(count):
+        P = W.ensemble_member(b, n_hi=args.ensemble_nmax, count=count)
+        g = P.graph
+        nnz += g.nnz
+        th32 = P.theta0.astype(np.float32)
+        bb.add(g.n, g.row_ptr, g.col, g.labels, P.omega, P.K)
+        if not args.no_cpu:
+            rows = np.sort(rng.choice(g.n, max(1, int(round(g.n * share))), replace=False)).astype(np.int64)
+            tc = time.time()
+            oracle.phase_rhs(g.n, g.row_ptr, g.col, P.omega, P.K, [0, 1], [0, 0], th32.astype(np.float64),
+                             rows=rows)
+            cpu_s += time.time() - tc
+            cpu_rows += len(rows)
+        if not args.no_sequential:
+            pl = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K,
+                                flags=cia.CIA_FLAG_NO_VALIDATE)
+            t = torch.as_tensor(th32, device="cuda")
+            rr = np.zeros(steps + 1)
+            pl.integrate(t, 0.01, 2, rr[:3])
+            t.copy_(torch.as_tensor(th32, device="cuda"))
+            seq_ms += timed(torch, lambda st: pl.integrate(t, 0.01, steps, rr, stream=st))
+            pl.close()
+            del t
+        th_parts.append(th32)
+        del P, g
+        if b % 32 == 31:
+            log("ensemble: %d instances added, N %d, nnz %d (%.0f s)" % (b + 1, bb.n, nnz, time.time() - t0))
+    tb = time.time()
+    plan = bb.finish()
+    info = plan.info()
+    off = plan.offsets
+    ntot = int(off[-1])
+    log("ensemble plan: N %d nnz %d units %d nnz_neg %d nnz_pos %d bytes/stage %.3e (finish %.0f s, all %.0f s)" % (
+        ntot, info.nnz_graph, info.nunits, info.nnz_neg, info.nnz_pos, info.bytes_per_stage, time.time() - tb,
+        time.time() - t0))
+    th0 = np.concatenate(th_parts)
+    del th_parts
+    every = 0 if args.no_timing else max(1, args.timing_every)
+    ms, tim, r, calls = time_integrate(plan, torch, th0, 0.01, steps, 2, timing_every=every, reps=args.reps)
+    value = ntot * 4 * steps / (ms / 1e3)
+    log("batched: %.3f ms/step, %.3e RHS node-updates/s" % (ms / steps, value))
+    roof = None
+    stage_avg_ms = tim.stage_ms / max(tim.stage_launches, 1) if tim.stage_launches else None
+    if stage_avg_ms:
+        achieved = info.bytes_per_stage / (stage_avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "phase_stage_kernel",
+                "avg_launch_us": round(stage_avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": info.bytes_per_stage, "timed_launches": tim.stage_launches}
+        log("ensemble stage kernel avg %.2f us, %.1f GB/s algorithmic (%.1f%% of 8 TB/s)" % (
+            stage_avg_ms * 1e3, achieved, 100 * achieved / HBM_PEAK_GBS))
+    res = {"batched": {"value": value, "ms_per_step": ms / steps, "units": info.nunits,
+                       "ms_per_call": [round(x, 4) for x in calls]}}
+    if not args.no_sequential:
+        res["sequential"] = {"value": ntot * 4 * steps / (seq_ms / 1e3), "ms_per_step": seq_ms / steps,
+                             "how": "sum over the 256 instances of one timed cia_integrate call each"}
+        log("sequential: %.3f ms/step" % (seq_ms / steps))
+    plan.close()
     out = {
         "metric": "ensemble RHS node-updates/s (256 instances, one batched plan), 1 MI355X",
-        "value": res["batched"]["value"], "unit": "RHS node-updates/s", "n_gpus": 1, "steps": steps, "warmup": 2,
-        "ms_per_step": res["batched"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "value": value, "unit": "RHS node-updates/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+        "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "ensemble_256", "n_total": ntot, "n_max": args.ensemble_nmax, "stepper": "rk4",
-                   "dt": 0.01},
-        "methods": res, "speedup_vs_sequential": res["batched"]["value"] / res["sequential"]["value"],
+        "config": {"workload": "ensemble_256", "n_total": ntot, "n_max": args.ensemble_nmax,
+                   "nnz_graph": int(info.nnz_graph), "nnz_neg": int(info.nnz_neg), "nnz_pos": int(info.nnz_pos),
+                   "stepper": "rk4", "dt": 0.01, "units": info.nunits},
+        "methods": res,
+        "speedup_vs_sequential": (res["batched"]["value"] / res["sequential"]["value"]
+                                  if "sequential" in res else None),
+        "roofline": roof,
+        "cpu_baseline": None if args.no_cpu else {
+            "value": cpu_rows / cpu_s, "unit": "RHS node-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": "%.1f%% of the rows of every instance (%d rows), one FP64 right-hand "
+            "side, %.1f s" % (100 * share, cpu_rows, cpu_s)},
     }
-    # the oracle over every instance, a bounded share of each one's rows
-    import oracle
-    share = 1.0
-    if not args.no_cpu:
-        t0 = time.time()
-        P0 = ens[0]
-        oracle.phase_rhs(P0.graph.n, P0.graph.row_ptr, P0.graph.col, P0.omega, P0.K, [0, 1], [0, 0],
-                         P0.theta0, rows=np.arange(min(256, P0.graph.n), dtype=np.int64))
-        share = min(1.0, max(0.002, 6.0 / max((time.time() - t0) * ntot / min(256, P0.graph.n), 1e-9)))
-    def ens_rows(_rows):
-        for P in ens:
-            m = max(1, int(P.graph.n * share))
-            oracle.phase_rhs(P.graph.n, P.graph.row_ptr, P.graph.col, P.omega, P.K, [0, 1], [0, 0], P.theta0,
-                             rows=np.arange(m, dtype=np.int64))
-    if not args.no_cpu:
-        t0 = time.time()
-        ens_rows(None)
-        ct = time.time() - t0
-        done = sum(max(1, int(P.graph.n * share)) for P in ens)
-        out["cpu_baseline"] = {"value": done / ct, "unit": "RHS node-updates/s", "cores": oracle.num_threads(),
-                               "kind": "oracle", "sample": "the first %.1f%% of the rows of every instance, "
-                               "one FP64 right-hand side, %.1f s" % (100 * share, ct)}
-    else:
-        out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 

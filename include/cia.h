@@ -291,6 +291,35 @@ cia_status cia_build_batch(int32_t count, const cia_graph *graphs, const int32_t
                            const cia_coupling *couplings, const double *const *omegas,
                            const cia_options *o, cia_plan **out);
 
+/*
+ * Incremental form of cia_build_batch for ensembles whose graphs do not fit in
+ * host memory together: the same plan, built one instance at a time.
+ *
+ * cia_batch_begin -- start an empty ensemble with options `o` (NULL = the
+ *   defaults; copied).  *out receives a handle owned by the caller until
+ *   cia_batch_finish or cia_batch_abort.
+ * cia_batch_add -- append instance b = (number of instances added so far):
+ *   steps P1 and P2 of Sec. 3.1 on this graph alone (eq. 2.1 with its own N_b
+ *   and K_b).  Arguments as one entry of cia_build_batch's arrays; every
+ *   pointer is borrowed for the call only, so the caller may free the graph,
+ *   labels and omega when it returns.  Host memory then holds the instance's
+ *   remainder lists (S-neg and S-pos, 4 bytes per entry) rather than its
+ *   adjacency.  CIA_EINVAL / CIA_EUNSUPPORTED leave the handle as it was
+ *   (the instance is not added); after CIA_ENOMEM every later add and finish
+ *   fails with CIA_EINVAL and only cia_batch_abort is left.
+ * cia_batch_finish -- join the instances in the order they were added and
+ *   build the plan: the result is the plan cia_build_batch gives for the same
+ *   instances (same layout, same kernels, bitwise the same results).  The
+ *   handle is released whatever the outcome; on error *out is NULL.
+ * cia_batch_abort -- release a handle without building (NULL is a no-op).
+ */
+typedef struct cia_batch cia_batch;
+cia_status cia_batch_begin(const cia_options *o, cia_batch **out);
+cia_status cia_batch_add(cia_batch *b, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
+                         const double *omega);
+cia_status cia_batch_finish(cia_batch *b, cia_plan **out);
+void cia_batch_abort(cia_batch *b);
+
 /* Instances of a plan and their offsets in the state (host [count+1], may be
    NULL to query the count).  A plan built by cia_build reports one instance. */
 cia_status cia_batch_offsets(const cia_plan *p, int32_t *count, int64_t *offsets);

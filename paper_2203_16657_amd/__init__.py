@@ -86,7 +86,8 @@ EXPORTS = ["cia_build", "cia_rhs", "cia_integrate", "cia_destroy", "cia_last_err
            "cia_fourier_coeffs", "cia_p1_build", "cia_p1_sizes", "cia_p1_export", "cia_p1_free",
            "cia_abi_sizeof", "cia_basis_param_count", "cia_basis_set_params", "cia_basis_get_params",
            "cia_basis_train", "cia_basis_loss_grad", "cia_basis_features", "cia_build_batch",
-           "cia_batch_offsets", "cia_autotune", "cia_plan_set_timing", "cia_detect_communities"]
+           "cia_batch_offsets", "cia_autotune", "cia_plan_set_timing", "cia_detect_communities",
+           "cia_batch_begin", "cia_batch_add", "cia_batch_finish", "cia_batch_abort"]
 
 _lib = None
 
@@ -152,6 +153,14 @@ def load():
     lib.cia_basis_features.argtypes = [_vp, _vp, _c.c_int64, _vp, _vp]
     lib.cia_build_batch.restype = _c.c_int
     lib.cia_build_batch.argtypes = [_c.c_int32, _vp, _vp, _vp, _vp, P(cia_options), P(_vp)]
+    lib.cia_batch_begin.restype = _c.c_int
+    lib.cia_batch_begin.argtypes = [P(cia_options), P(_vp)]
+    lib.cia_batch_add.restype = _c.c_int
+    lib.cia_batch_add.argtypes = [_vp, P(cia_graph), _vp, P(cia_coupling), _vp]
+    lib.cia_batch_finish.restype = _c.c_int
+    lib.cia_batch_finish.argtypes = [_vp, P(_vp)]
+    lib.cia_batch_abort.restype = None
+    lib.cia_batch_abort.argtypes = [_vp]
     lib.cia_batch_offsets.restype = _c.c_int
     lib.cia_batch_offsets.argtypes = [_vp, _vp, _vp]
     lib.cia_plan_set_timing.restype = _c.c_int
@@ -448,6 +457,68 @@ def cia_basis_loss_grad(plan, a, b, t, grad, stream=None) -> float:
 
 def cia_basis_features(plan, x, out, stream=None) -> None:
     _check(load().cia_basis_features(plan, _dev_ptr(x), int(x.shape[1]), _dev_ptr(out), _stream_ptr(stream)))
+
+
+class BatchBuilder:
+    """Incremental ensemble build (cia_batch_begin / _add / _finish): instances
+    are added one at a time, each running P1 on its own graph, so the caller
+    can generate an instance, add it and drop its graph before the next.
+    finish() returns the same Plan that Plan.batch builds from the full list."""
+
+    def __init__(self, method=CIA_METHOD_CIA, precision=CIA_F32, stepper=CIA_RK4, flags=0, unit_work=0,
+                 block=0, device=-1):
+        lib = load()
+        o = cia_options_default()
+        o.method, o.precision, o.stepper, o.flags = method, precision, stepper, flags
+        o.unit_work, o.block, o.device = unit_work, block, device
+        h = _vp()
+        _check(lib.cia_batch_begin(_c.byref(o), _c.byref(h)))
+        self.handle = h.value
+        self.precision = precision
+        self.n = 0
+        self.count = 0
+        self._ds = np.array([0.0, 1.0])
+        self._dc = np.array([0.0, 0.0])
+
+    def add(self, n, row_ptr, col, labels=None, omega=None, K=1.0):
+        """Append one phase-model instance with h = sin (arrays borrowed for the call)."""
+        if self.handle is None:
+            raise ValueError("batch already finished or aborted")
+        n = int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        _check_csr(n, rp, cl)
+        lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
+        om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
+        _need_len("labels", lab, n)
+        _need_len("omega", om, n)
+        g = cia_graph(n=n, kind=CIA_GRAPH_CSR, reserved=0, row_ptr=_np_ptr(rp), col=_np_ptr(cl))
+        c = cia_coupling_default()
+        c.model, c.p, c.d_sin, c.d_cos, c.K = CIA_MODEL_PHASE, 1, _np_ptr(self._ds), _np_ptr(self._dc), float(K)
+        _check(load().cia_batch_add(self.handle, _c.byref(g), _np_ptr(lab), _c.byref(c), _np_ptr(om)))
+        self.n += n
+        self.count += 1
+
+    def finish(self):
+        if self.handle is None:
+            raise ValueError("batch already finished or aborted")
+        h, self.handle = self.handle, None
+        out = _vp()
+        _check(load().cia_batch_finish(h, _c.byref(out)))
+        plan = Plan(out.value, self.n, self.precision, CIA_MODEL_PHASE)
+        plan.offsets = cia_batch_offsets(out.value)
+        return plan
+
+    def abort(self):
+        if self.handle is not None:
+            load().cia_batch_abort(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.abort()
+        except Exception:
+            pass
 
 
 class Plan:

@@ -4,6 +4,8 @@
 #include <cstring>
 #include <new>
 
+#include <memory>
+
 #include "plan.h"
 
 namespace cia {
@@ -157,6 +159,23 @@ cia_status cia_build(const cia_graph *g, const int32_t *labels, const cia_coupli
     });
 }
 
+cia_status cia_batch_finish(cia_batch *b, cia_plan **out) {
+    clear_error();
+    if (!out) {
+        delete b;
+        return set_error(CIA_EINVAL, "out is NULL");
+    }
+    *out = nullptr;
+    if (!b) return set_error(CIA_EINVAL, "batch is NULL");
+    std::unique_ptr<cia_batch> own(b);
+    if (b->acc.failed) return set_error(CIA_EINVAL, "batch: an earlier add ran out of host memory");
+    if (b->acc.ncn.empty()) return set_error(CIA_EINVAL, "batch: no instance was added");
+    const cia_options o = b->acc.o;
+    return make_plan(&o, b->acc.off.back(), CIA_MODEL_PHASE, out, [&](cia_plan *p) -> cia_status {
+        return batch_finish(p, b->acc);
+    });
+}
+
 cia_status cia_build_batch(int32_t count, const cia_graph *graphs, const int32_t *const *labels,
                            const cia_coupling *couplings, const double *const *omegas, const cia_options *o,
                            cia_plan **out) {
@@ -165,14 +184,17 @@ cia_status cia_build_batch(int32_t count, const cia_graph *graphs, const int32_t
     *out = nullptr;
     if (count < 1) return set_error(CIA_EINVAL, "count = %d", count);
     if (!graphs || !couplings) return set_error(CIA_EINVAL, "graphs/couplings is NULL");
-    cia_options def;
-    cia_options_default(&def);
-    if (!o) o = &def;
-    int64_t n = 0;
-    for (int32_t b = 0; b < count; b++) n += graphs[b].n > 0 ? graphs[b].n : 0;
-    return make_plan(o, n, CIA_MODEL_PHASE, out, [&](cia_plan *p) -> cia_status {
-        return batch_build(p, count, graphs, labels, couplings, omegas, o);
-    });
+    cia_batch *b = nullptr;
+    CIA_TRY(cia_batch_begin(o, &b));
+    for (int32_t k = 0; k < count; k++) {
+        cia_status st = cia_batch_add(b, &graphs[k], labels ? labels[k] : nullptr, &couplings[k],
+                                      omegas ? omegas[k] : nullptr);
+        if (st != CIA_OK) {
+            cia_batch_abort(b);
+            return st;
+        }
+    }
+    return cia_batch_finish(b, out);
 }
 
 cia_status cia_batch_offsets(const cia_plan *p, int32_t *count, int64_t *offsets) {

@@ -511,8 +511,13 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     const uint4 padp = make_uint4(a.pad_pos, a.pad_pos, a.pad_pos, a.pad_pos);
 
     // ---- 2. slices, one wavefront each, one row per lane ----
+    // each slice's descriptor is loaded one slice ahead, so its scalar load is
+    // in flight while the previous slice is gathered
+    Slice Snext;
+    if (Un.s0 + wid < Un.s1) Snext = a.slices[Un.s0 + wid];
     for (int sl = Un.s0 + wid; sl < Un.s1; sl += NW) {
-        const Slice S = a.slices[sl];
+        const Slice S = Snext;
+        if (sl + NW < Un.s1) Snext = a.slices[sl + NW];
         const bool mine = lane < S.rows;
         const int i = S.row0 + lane;
         // operands of the combine / stage update, loaded before the gather
@@ -2035,7 +2040,7 @@ static cia_status tri_build_missing(cia_plan *p, PhaseState *s, const std::vecto
 }
 
 cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
-                       const double *omega, const cia_options *o, const BatchSpec *bs) {
+                       const double *omega, const cia_options *o, const BatchSpec *bs, P1 *pre) {
     PhaseState *s = new (std::nothrow) PhaseState();
     if (!s) return set_error(CIA_ENOMEM, "host allocation failed");
     p->phase = s;
@@ -2183,7 +2188,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         std::vector<int32_t> xval;
         if (!s->direct) {
             // triadic hyperedges are defined on the given communities: keep them all
-            CIA_TRY(p1_build(g, labels, o->dense_alpha, keep || s->tri, validate, true, p1));
+            if (pre) p1 = std::move(*pre);   // batched ensembles: P1 of every instance, joined
+            else CIA_TRY(p1_build(g, labels, o->dense_alpha, keep || s->tri, validate, true, p1));
             nnz_neg = (int64_t)p1.neg_local.size();
             nnz_pos = (int64_t)p1.pos.size();
             comm_staged.assign(p1.ncomm, 0);
@@ -2218,13 +2224,20 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         } else {
             // direct method: community order for locality, no remainder split;
             // every node is "outside" and its whole row is the +1 list
-            CIA_TRY(p1_build(g, labels, o->dense_alpha, true, validate, false, p1));
+            if (!pre) CIA_TRY(p1_build(g, labels, o->dense_alpha, true, validate, false, p1));
             if (g->kind == CIA_GRAPH_COMPLETE) {
                 s->complete_direct = true;
             } else {
                 std::vector<int64_t> arp;
                 std::vector<int32_t> acol;
-                CIA_TRY(p1_permuted_adjacency(g, p1, arp, acol));
+                if (pre) {
+                    // batched ensembles: the joined permuted adjacency is the +1 list
+                    p1 = std::move(*pre);
+                    arp.swap(p1.posptr);
+                    acol.swap(p1.pos);
+                } else {
+                    CIA_TRY(p1_permuted_adjacency(g, p1, arp, acol));
+                }
                 nnz_pos = arp[n];
                 // rows sorted by degree inside each community segment
                 StreamIn S[4];
@@ -2712,15 +2725,15 @@ static cia_status rhs_impl(cia_plan *p, PhaseState *s, const void *state, void *
 // or per instance for batched ensembles.  slot: index in the trace; ctr:
 // slot counter of replayed graphs (then `slot` is the base).
 template <typename R>
-static cia_status launch_order(cia_plan *p, PhaseState *s, hipStream_t st, const void *cs, int64_t slot,
+static cia_status launch_order(cia_plan *p, PhaseState *s, hipStream_t st, double *rb, const void *cs, int64_t slot,
                                int64_t stride, const int64_t *ctr, bool timed) {
     if (timed) CIA_TRY(timing_begin(p, st, KK_AUX));
     if (s->batch > 0) {
         hipLaunchKernelGGL((order_grouped_kernel<R>), dim3(s->batch), dim3(256), 0, st,
-                           static_cast<const cx<R> *>(cs), s->grp_idx, s->grp_off, s->r_dev, stride, slot, ctr);
+                           static_cast<const cx<R> *>(cs), s->grp_idx, s->grp_off, rb, stride, slot, ctr);
     } else {
         hipLaunchKernelGGL(order_reduce_kernel, dim3(1), dim3(64), 0, st, s->r_part, s->nunits,
-                           1.0 / (double)p->n, s->r_dev + slot, ctr);
+                           1.0 / (double)p->n, rb + slot, ctr);
     }
     CIA_HIP(hipGetLastError());
     return timed ? timing_end(p, st) : CIA_OK;
@@ -2774,6 +2787,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         CIA_TRY(dalloc(p, &s->r_dev, (size_t)cap));
         s->r_cap = cap;
     }
+    double *const rb = s->r_dev;   // device trace of r(t)
     const bool rk4 = p->stepper == CIA_RK4;
     const int64_t grid = (n + 255) / 256;
     int cur = 0;
@@ -2790,7 +2804,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         int np = 0;
         if (want_r) {
             CIA_TRY(launch_order_partial<R>(p, s, st, s->cs[0], &np));
-            CIA_TRY(launch_order_reduce(p, s, st, np, s->r_dev));
+            CIA_TRY(launch_order_reduce(p, s, st, np, rb));
         }
         for (int64_t k = 0; k < steps; k++) {
             const int nst = rk4 ? 4 : 1;
@@ -2807,7 +2821,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
             }
             if (want_r) {
                 CIA_TRY(launch_order_partial<R>(p, s, st, s->cs[cur], &np));
-                CIA_TRY(launch_order_reduce(p, s, st, np, s->r_dev + k + 1));
+                CIA_TRY(launch_order_reduce(p, s, st, np, rb + k + 1));
             }
         }
     } else {
@@ -2837,7 +2851,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         // r(t_0): with RK4 on single networks it is folded into the first
         // stage of the first step (or reduced below when steps == 0)
         const bool fold = part_r && rk4;
-        if (want_r && !fold) CIA_TRY(launch_order<R>(p, s, ws, s->cs[0], 0, stride, nullptr, true));
+        if (want_r && !fold) CIA_TRY(launch_order<R>(p, s, ws, rb, s->cs[0], 0, stride, nullptr, true));
         if (replay) {
             // one RK4 step (four stage launches, r(t) and its slot counter) as a
             // graph, instantiated once per (dt, trace) and replayed every step
@@ -2850,13 +2864,13 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
                 CIA_HIP(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
                 for (int q = 0; q < 4; q++) {
                     PhaseArgs<R> b = stage_args<R>(p, s, true, q, dt, q & 1, part_r && q == 3);
-                    if (fold && q == 0) fold_order<R>(s, b, s->r_dev, s->r_ctr);
+                    if (fold && q == 0) fold_order<R>(s, b, rb, s->r_ctr);
                     if (s->nunits > 0) launch_tri_aux<R>(s, b, ws);
                     if (s->block == 512) launch_stage_v_any<R, 512>(s, b, ws);
                     else launch_stage_v_any<R, 256>(s, b, ws);
                 }
                 if (want_r) {
-                    if (!fold) CIA_TRY(launch_order<R>(p, s, ws, s->cs[0], 1, stride, s->r_ctr, false));
+                    if (!fold) CIA_TRY(launch_order<R>(p, s, ws, rb, s->cs[0], 1, stride, s->r_ctr, false));
                     hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, ws, s->r_ctr, (int64_t)1, 1);
                 }
                 hipGraph_t gr = nullptr;
@@ -2881,15 +2895,15 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
                 const int nst = rk4 ? 4 : 1;
                 for (int q = 0; q < nst; q++) {
                     a = stage_args<R>(p, s, rk4, q, dt, cur, part_r && q == nst - 1);
-                    if (fold && q == 0) fold_order<R>(s, a, s->r_dev + k, nullptr);
+                    if (fold && q == 0) fold_order<R>(s, a, rb + k, nullptr);
                     CIA_TRY(launch_stage<R>(p, s, a, ws, KK_STAGE));
                     cur ^= 1;
                 }
-                if (want_r && !fold) CIA_TRY(launch_order<R>(p, s, ws, s->cs[cur], k + 1, stride, nullptr, true));
+                if (want_r && !fold) CIA_TRY(launch_order<R>(p, s, ws, rb, s->cs[cur], k + 1, stride, nullptr, true));
             }
         }
         // the last step's r(t) (its partials were left by the final stage)
-        if (fold) CIA_TRY(launch_order<R>(p, s, ws, nullptr, steps, stride, nullptr, true));
+        if (fold) CIA_TRY(launch_order<R>(p, s, ws, rb, nullptr, steps, stride, nullptr, true));
         CIA_TRY(timing_begin(p, ws, KK_AUX));
         for (int d = 0; d < s->pdim; d++)
             hipLaunchKernelGGL((permute_out_kernel<R>), dim3(grid), dim3(256), 0, ws, n, s->perm,
@@ -2901,7 +2915,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
             CIA_HIP(hipStreamWaitEvent(st, s->gev[1], 0));
         }
         if (want_r) {
-            CIA_HIP(hipMemcpyAsync(r_trace, s->r_dev, sizeof(double) * nr * stride, hipMemcpyDeviceToHost, st));
+            CIA_HIP(hipMemcpyAsync(r_trace, rb, sizeof(double) * nr * stride, hipMemcpyDeviceToHost, st));
             CIA_HIP(hipStreamSynchronize(st));
             for (int64_t k = 0; k < nr * stride; k++)
                 if (!std::isfinite(r_trace[k]))
@@ -2917,7 +2931,7 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
     CIA_HIP(hipGetLastError());
     CIA_TRY(timing_end(p, st));
     if (want_r) {
-        CIA_HIP(hipMemcpyAsync(r_trace, s->r_dev, sizeof(double) * (steps + 1), hipMemcpyDeviceToHost, st));
+        CIA_HIP(hipMemcpyAsync(r_trace, rb, sizeof(double) * (steps + 1), hipMemcpyDeviceToHost, st));
         CIA_HIP(hipStreamSynchronize(st));
         for (int64_t k = 0; k <= steps; k++)
             if (!std::isfinite(r_trace[k]))

@@ -88,11 +88,38 @@ struct BatchSpec {
 };
 
 // model entry points (phase model: cia_phase.hip)
+// pre: P1 computed by the caller (batched ensembles), moved from; else P1 of g
 cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
-                       const double *omega, const cia_options *o, const BatchSpec *bs = nullptr);
+                       const double *omega, const cia_options *o, const BatchSpec *bs = nullptr,
+                       P1 *pre = nullptr);
 cia_status phase_autotune(cia_plan *p, hipStream_t s, cia_tune_report *rep);
-cia_status batch_build(cia_plan *p, int32_t count, const cia_graph *graphs, const int32_t *const *labels,
-                       const cia_coupling *couplings, const double *const *omegas, const cia_options *o);
+// Accumulator of an incremental batch build (cia_batch.cpp).  Rows of the
+// union in P1 order are the community rows of instance 0, 1, ... followed by
+// the outside rows of instance 0, 1, ...; partner positions stay
+// instance-local until the union's layout is known.
+struct BatchAcc {
+    cia_options o{};
+    int32_t p = -1;
+    std::vector<double> dsin, dcos;
+    std::vector<int64_t> off{0};        // [count+1] user-id offsets
+    std::vector<int64_t> ncn;           // community rows per instance
+    std::vector<int32_t> comm_size;     // kept communities in union order
+    std::vector<int32_t> perm_c, perm_u;    // global user id of community / outside rows
+    std::vector<int64_t> negptr_c{0};   // community rows: S-neg lists (community-local)
+    std::vector<int32_t> neg;
+    std::vector<int64_t> posptr_c{0}, posptr_u{0};   // S-pos lists (direct: whole rows)
+    std::vector<int32_t> pos_c, pos_u;
+    std::vector<double> omega, kn;      // per user id of the union
+    bool any_omega = false;
+    bool failed = false;                // an allocation failed part-way through an add
+    int64_t nnz_graph = 0;
+};
+
+// incremental batch build (cia_batch.cpp): P1 of each added instance appended
+// to the accumulator; batch_finish builds the joined plan from it
+cia_status batch_add(BatchAcc &A, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
+                     const double *omega);
+cia_status batch_finish(cia_plan *p, BatchAcc &A);
 cia_status phase_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t s);
 cia_status phase_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
                            hipStream_t s);
@@ -123,3 +150,8 @@ cia_status flock_basis_loss_grad(cia_plan *p, const float *a, const float *b, co
 int64_t flock_param_count(int32_t rank);
 
 }  // namespace cia
+
+// opaque handle of the cia_batch_* calls
+struct cia_batch {
+    cia::BatchAcc acc;
+};

@@ -241,3 +241,39 @@ def test_binding_rejects_wrong_lengths(cia):
         cia.Plan.structured(4, "rank1", alpha=np.ones(4))            # beta missing
     with pytest.raises(ValueError):
         cia.Plan.structured(4, "rank1", alpha=np.ones(3), beta=np.ones(4))
+
+
+def test_incremental_batch_host_checks(cia):
+    """cia_batch_add runs P1 on the host, so its argument checks need no GPU:
+    a mismatched coupling function, a non-CSR graph, a bad label or a
+    non-finite frequency is refused with the instance number and the handle
+    stays usable; abort releases it."""
+    bb = cia.BatchBuilder()
+    P = W.ensemble_member(3, n_lo=200, n_hi=600)
+    g = P.graph
+    bb.add(g.n, g.row_ptr, g.col, g.labels, P.omega, P.K)
+    assert bb.count == 1 and bb.n == g.n
+    lib = cia.load()
+    # another coupling function (p = 2) is refused
+    ds, dc = np.array([0.0, 1.0, 0.5]), np.zeros(3)
+    c = cia.cia_coupling_default()
+    c.p, c.d_sin, c.d_cos, c.K = 2, ds.ctypes.data_as(ctypes.c_void_p), dc.ctypes.data_as(ctypes.c_void_p), 1.0
+    rp, cl = g.row_ptr, g.col
+    gg = cia.cia_graph(n=g.n, kind=cia.CIA_GRAPH_CSR, reserved=0, row_ptr=rp.ctypes.data_as(ctypes.c_void_p),
+                       col=cl.ctypes.data_as(ctypes.c_void_p))
+    st = lib.cia_batch_add(bb.handle, ctypes.byref(gg), None, ctypes.byref(c), None)
+    assert st == cia.CIA_EINVAL and "instance 1" in cia.cia_last_error()
+    bad = g.labels.copy()
+    bad[0] = -7
+    with pytest.raises(cia.CIAError):
+        bb.add(g.n, g.row_ptr, g.col, bad, None, 1.0)
+    om = P.omega.copy()
+    om[5] = np.nan
+    with pytest.raises(cia.CIAError):
+        bb.add(g.n, g.row_ptr, g.col, g.labels, om, 1.0)
+    # the handle still takes a valid instance after the refusals
+    bb.add(g.n, g.row_ptr, g.col, g.labels, None, 2.0)
+    assert bb.count == 2
+    bb.abort()
+    with pytest.raises(ValueError):
+        bb.add(g.n, g.row_ptr, g.col, g.labels, None, 2.0)

@@ -236,3 +236,95 @@ def test_trace_shorter_than_the_plan_writes_is_rejected(env):
     plan.integrate(th, 0.01, steps, r)
     assert np.all(np.isfinite(r)) and np.all(r > 0)
     plan.close()
+
+
+def test_ensemble_256_instances_full_size(env):
+    """The ensemble recipe at its stated sizes: 256 instances with N
+    log-uniform in [1e3, 2e5] (about 9.6e6 nodes and 1.7e10 adjacency entries
+    in total), generated one at a time and added to an incremental batch build
+    (cia_batch_begin / _add / _finish), so host memory holds one instance's
+    adjacency at a time.  Sampled rows of every instance against the FP64
+    oracle (evaluated while that instance's graph is in hand), r_b(0) of every
+    instance against its definition, and a short integration."""
+    import time
+    cia, torch = env
+    count = 256
+    bb = cia.BatchBuilder(flags=cia.CIA_FLAG_NO_VALIDATE)
+    rng = np.random.default_rng(19)
+    th_parts, refs = [], []
+    t0 = time.time()
+    nnz = 0
+    for b in range(count):
+        P = W.ensemble_member(b, count=count)
+        g = P.graph
+        nnz += g.nnz
+        th32 = P.theta0.astype(np.float32)
+        bb.add(g.n, g.row_ptr, g.col, g.labels, None, P.K)
+        rows = np.sort(rng.choice(g.n, min(24, g.n), replace=False)).astype(np.int64)
+        want = oracle.phase_rhs(g.n, g.row_ptr, g.col, None, P.K, [0, 1], [0, 0], th32.astype(np.float64),
+                                rows=rows)
+        th_parts.append(th32)
+        refs.append((rows, want, P.K, oracle.order_parameter(th32.astype(np.float64))))
+        del P, g
+        if b % 32 == 31:
+            say("   added %d instances, N %d, nnz %d (%.0f s)" % (b + 1, bb.n, nnz, time.time() - t0))
+    plan = bb.finish()
+    info = plan.info()
+    off = plan.offsets
+    say("full-size ensemble: N", off[-1], "nnz", info.nnz_graph, "units", info.nunits, "nnz_neg", info.nnz_neg,
+        "nnz_pos", info.nnz_pos, "build %.0f s" % (time.time() - t0))
+    assert len(off) == count + 1 and off[-1] > 5e6 and info.nnz_graph == nnz
+    th = torch.as_tensor(np.concatenate(th_parts), device="cuda")
+    del th_parts
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for b, (rows, want, K, _) in enumerate(refs):
+        cg = got[off[b] + rows]
+        if K == 0.0:
+            assert np.abs(cg).max() < 1e-6
+            continue
+        worst = max(worst, np.abs(cg - want).max() / np.abs(want).max())
+    say("   worst sampled coupling rel_inf over 256 instances", worst)
+    assert worst < 1e-5
+    steps = 5
+    r = np.zeros(count * (steps + 1))
+    plan.integrate(th, 0.01, steps, r)
+    r = r.reshape(count, steps + 1)
+    r0 = np.array([q[3] for q in refs])
+    say("   max |r_b(0) - oracle|", np.abs(r[:, 0] - r0).max())
+    assert np.abs(r[:, 0] - r0).max() < 1e-6
+    assert np.all(np.isfinite(r)) and np.all((r >= 0) & (r <= 1 + 1e-12))
+    plan.close()
+
+
+def test_incremental_batch_equals_list_build(env):
+    """cia_batch_add one instance at a time gives the plan cia_build_batch
+    gives for the whole list: bitwise the same RHS and trajectory, with and
+    without frequencies, for the CIA and direct methods."""
+    cia, torch = env
+    ens = ensemble(10, 300, 4000)
+    th0 = np.concatenate([P.theta0 for P in ens]).astype(np.float32)
+    for method in (0, 1):
+        for with_omega in (False, True):
+            a = cia.Plan.batch(problems(ens, with_omega=with_omega), method=method)
+            bb = cia.BatchBuilder(method=method)
+            for P in ens:
+                bb.add(P.graph.n, P.graph.row_ptr, P.graph.col, P.graph.labels, P.omega if with_omega else None, P.K)
+            c = bb.finish()
+            assert list(a.offsets) == list(c.offsets)
+            outs = []
+            for pl in (a, c):
+                th = torch.as_tensor(th0, device="cuda")
+                o = torch.empty_like(th)
+                pl.rhs(th, o)
+                r = np.zeros(len(ens) * 6)
+                pl.integrate(th, 0.01, 5, r)
+                torch.cuda.synchronize()
+                outs.append((o.cpu().numpy(), th.cpu().numpy(), r))
+            for u, v in zip(outs[0], outs[1]):
+                assert np.array_equal(u, v), (method, with_omega)
+            a.close()
+            c.close()
