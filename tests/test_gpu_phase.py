@@ -299,3 +299,43 @@ def test_plan_from_detected_communities(env):
     say("detected communities", plan.info().ncomm, "work", work, "rel_inf", err)
     assert plan.info().ncomm == len(np.unique(lab[lab >= 0])) and err < TOL32
     plan.close()
+
+
+def test_order_parameter_ten_time_units_config2_sizes(env):
+    """Power-law recipe at N = 30000 with communities up to 4929 nodes (LDS
+    staged, several work units each), FP32 RK4 dt 0.01 for 1000 steps on the
+    GPU, CIA and direct: r(t) within 1e-3 of the FP64 oracle at every step
+    and every community's r_c within 1e-3 at t = 10.  The oracle trajectory
+    is stored by tests/golden/make_order_parameter_config2.py (it takes a
+    quarter of an hour on the host cores)."""
+    from conftest import load_golden
+    cia, torch = env
+    ref = load_golden("order_parameter_config2_n30000.json")
+    rc = ref["recipe"]
+    P = W.scaled_kuramoto(rc["n"], seed=rc["seed"], hi=rc["hi"])
+    g = P.graph
+    # the stored trajectory belongs to exactly this input
+    assert g.nnz == ref["check"]["nnz"] and g.ncomm == ref["check"]["ncomm"]
+    assert abs(P.omega.sum() - ref["check"]["sum_omega"]) < 1e-6 * max(1.0, abs(ref["check"]["sum_omega"]))
+    assert abs(P.theta0.sum() - ref["check"]["sum_theta0"]) < 1e-9 * abs(ref["check"]["sum_theta0"])
+    steps = rc["steps"]
+    want_r = np.array(ref["r"])
+    want_rc = np.array(ref["r_c"])
+    comms = [np.flatnonzero(g.labels == c) for c in ref["communities"]]
+    assert max(len(m) for m in comms) > 4000
+    for method in (0, 1):
+        plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, P.omega, K=P.K, method=method)
+        info = plan.info()
+        if method == 0:
+            assert info.nunits > info.ncomm   # large communities span several units
+        th = torch.as_tensor(P.theta0, dtype=torch.float32, device="cuda")
+        r = np.zeros(steps + 1)
+        plan.integrate(th, P.dt, steps, r)
+        got = th.cpu().numpy().astype(np.float64)
+        got_rc = np.array([np.abs(np.exp(1j * got[m]).mean()) for m in comms])
+        dr = np.abs(r - want_r).max()
+        drc = np.abs(got_rc - want_rc).max()
+        say("r(t) config-2 sizes: n", g.n, "method", method, "units", info.nunits, "max |dr|", dr,
+            "max |dr_c| at t=10", drc, "largest community", max(len(m) for m in comms))
+        assert dr <= 1e-3 and drc <= 1e-3
+        plan.close()
