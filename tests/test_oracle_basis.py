@@ -208,3 +208,41 @@ def test_fd_pin_catches_planted_gradient_mistakes(slip):
     idx = np.concatenate([np.arange(0, o2, 7), o2 + rng.choice(4096, 150, replace=False),
                           np.arange(o2 + 4096, len(p) - R, 5)])
     assert _fd_ok(p, R, lo, hi, a, b, t, bad, idx) > 1e-3
+
+
+def test_rank64_separable_floor_on_flock_communities():
+    """What any rank-R separable basis w~(x, y) = sum_r s_r phi_r(x) phi_r(y)
+    can reach on the flocking communities (400 x 500 points in [0, 10]^3,
+    w(r) = (1 + r^2)^(-1/4)): by Eckart-Young the truncated SVD of each
+    community's weight matrix is the best rank-R approximation in Frobenius
+    and spectral norm, so its errors are a floor for every basis, learned or
+    Fourier.  The diagonal keeps w(0), the smooth choice (it multiplies
+    v_i - v_i = 0 in the coupling).  Measured on 20 communities with the
+    workload's own velocities: the coupling error
+    ||C~ - C||_inf / ||C||_inf of the community sum stays at or above 1e-3 on
+    average at rank 64 and clearly above it at rank 32, and the largest
+    per-pair relative weight error stays above 1e-1.  A per-pair judge at
+    1e-3 therefore sends every community to the exact path at rank <= 64."""
+    F = W.flock()
+    g = F.graph
+    cpl = {32: [], 64: [], 128: []}
+    pair = {32: [], 64: [], 128: []}
+    for c in range(0, 400, 20):
+        m = np.flatnonzero(g.labels == c)
+        X, V = F.x0[:, m].T, F.v0[:, m].T
+        Wm = (1.0 + ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)) ** -0.25
+        U, s, Vt = np.linalg.svd(Wm)
+        C = Wm @ V - Wm.sum(1)[:, None] * V
+        off = ~np.eye(len(m), dtype=bool)
+        for R in cpl:
+            E = (U[:, :R] * s[:R]) @ Vt[:R] - Wm
+            Ce = E @ V - E.sum(1)[:, None] * V
+            cpl[R].append(np.abs(Ce).max() / np.abs(C).max())
+            pair[R].append((np.abs(E[off]) / Wm[off]).max())
+    mean = {R: float(np.mean(v)) for R, v in cpl.items()}
+    # the floor falls with rank (a sanity check of the measurement itself)
+    assert mean[32] > mean[64] > mean[128]
+    assert mean[32] > 1.5e-3 and mean[64] > 1.0e-3
+    assert min(pair[64]) > 1e-1
+    # rank 128 (outside the 16..64 range of the basis) would reach 1e-3
+    assert mean[128] < 1e-3
