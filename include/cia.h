@@ -258,6 +258,29 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream);
 cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
                          void *stream);
 
+/*
+ * cia_integrate_noalloc -- cia_integrate for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels, steps and results (bitwise), but
+ * the call allocates nothing.  cia_integrate keeps r(t) in a device buffer
+ * that it grows on demand; this variant accumulates r(t) in a file-scope
+ * static device array of CIA_NOALLOC_R_MAX doubles (1 MiB) that every GPU the
+ * library runs on holds until the process ends.  Its device address is
+ * resolved once per GPU, at the first plan build on that GPU.
+ *  Arguments as cia_integrate; phase-model plans only (CIA_MODEL_PHASE and
+ *  CIA_MODEL_TRIADIC, single or batched), else CIA_EUNSUPPORTED.
+ *  r_trace : optional host [count][steps+1]; CIA_EINVAL before any device
+ *            work if count * (steps + 1) > CIA_NOALLOC_R_MAX.
+ *  The plan's replayed step graph (CIA_FLAG_HIPGRAPH) is not used (building
+ *  it allocates) and per-launch timing is off for the call.  Every call on a
+ *  GPU shares that GPU's array and writes every trace value it returns before
+ *  reading it; calls that overlap on one GPU (several streams or threads)
+ *  race on the array and must be serialised by the caller.
+ */
+#define CIA_NOALLOC_R_MAX (1 << 17)
+cia_status cia_integrate_noalloc(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
+                                 void *stream);
+
 /* Release every host and device resource of the plan (NULL is a no-op). */
 cia_status cia_destroy(cia_plan *p);
 

@@ -87,7 +87,8 @@ EXPORTS = ["cia_build", "cia_rhs", "cia_integrate", "cia_destroy", "cia_last_err
            "cia_abi_sizeof", "cia_basis_param_count", "cia_basis_set_params", "cia_basis_get_params",
            "cia_basis_train", "cia_basis_loss_grad", "cia_basis_features", "cia_build_batch",
            "cia_batch_offsets", "cia_autotune", "cia_plan_set_timing", "cia_detect_communities",
-           "cia_batch_begin", "cia_batch_add", "cia_batch_finish", "cia_batch_abort"]
+           "cia_batch_begin", "cia_batch_add", "cia_batch_finish", "cia_batch_abort", "cia_integrate_noalloc"]
+CIA_NOALLOC_R_MAX = 1 << 17   # r(t) values the allocation-free entry point can return
 
 _lib = None
 
@@ -113,6 +114,8 @@ def load():
     lib.cia_rhs.argtypes = [_vp, _vp, _vp, _vp]
     lib.cia_integrate.restype = _c.c_int
     lib.cia_integrate.argtypes = [_vp, _vp, _c.c_double, _c.c_int64, _vp, _vp]
+    lib.cia_integrate_noalloc.restype = _c.c_int
+    lib.cia_integrate_noalloc.argtypes = [_vp, _vp, _c.c_double, _c.c_int64, _vp, _vp]
     lib.cia_destroy.restype = _c.c_int
     lib.cia_destroy.argtypes = [_vp]
     lib.cia_last_error.restype = _c.c_char_p
@@ -288,6 +291,13 @@ def _trace_ptr(plan, r_trace, steps: int):
 def cia_integrate(plan, state, dt: float, steps: int, r_trace=None, stream=None) -> None:
     rt = _trace_ptr(plan, r_trace, steps)
     _check(load().cia_integrate(plan, _dev_ptr(state), float(dt), int(steps), rt, _stream_ptr(stream)))
+
+
+def cia_integrate_noalloc(plan, state, dt: float, steps: int, r_trace=None, stream=None) -> None:
+    """cia_integrate without any device allocation (r(t) in the library's
+    static scratch array of CIA_NOALLOC_R_MAX values)."""
+    rt = _trace_ptr(plan, r_trace, steps)
+    _check(load().cia_integrate_noalloc(plan, _dev_ptr(state), float(dt), int(steps), rt, _stream_ptr(stream)))
 
 
 def cia_destroy(plan) -> None:

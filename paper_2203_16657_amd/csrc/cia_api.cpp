@@ -270,6 +270,19 @@ cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, dou
     return st;
 }
 
+cia_status cia_integrate_noalloc(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
+                                 void *stream) {
+    clear_error();
+    if (!p) return set_error(CIA_EINVAL, "plan is NULL");
+    if (!state) return set_error(CIA_EINVAL, "state is NULL");
+    if (steps < 0) return set_error(CIA_EINVAL, "steps = %lld < 0", (long long)steps);
+    if (!std::isfinite(dt)) return set_error(CIA_EINVAL, "dt is not finite");
+    if (p->structd || !p->phase || (p->model != CIA_MODEL_PHASE && p->model != CIA_MODEL_TRIADIC))
+        return set_error(CIA_EUNSUPPORTED, "allocation-free integration: phase-model plans only");
+    CIA_TRY(select_device(p));
+    return phase_integrate_noalloc(p, state, dt, steps, r_trace, static_cast<hipStream_t>(stream));
+}
+
 cia_status cia_destroy(cia_plan *p) {
     clear_error();
     free_plan(p);

@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <type_traits>
 
@@ -2482,6 +2483,10 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
             s->coef = d;
         }
     }
+    // device address of this GPU's scratch array for the allocation-free
+    // entry point, resolved at set-up with the plan's device current
+    double *scr = nullptr;
+    CIA_TRY(noalloc_scratch(p->device, &scr));
     CIA_HIP(hipDeviceSynchronize());
     return CIA_OK;
 }
@@ -2769,12 +2774,12 @@ static void fold_order(PhaseState *s, PhaseArgs<R> &a, double *slot, const int64
 
 template <typename R>
 static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double dt, int64_t steps,
-                                 double *r_trace, hipStream_t st) {
+                                 double *r_trace, hipStream_t st, double *r_ext = nullptr) {
     const int64_t n = p->n;
     const bool want_r = r_trace != nullptr;
     const int64_t nr = s->batch > 0 ? s->batch : 1;   // traces
     const int64_t stride = steps + 1;
-    if (want_r && s->r_cap < nr * stride) {
+    if (want_r && !r_ext && s->r_cap < nr * stride) {
         // at least 4096 slots per trace, and at least double the old size, so
         // calls of up to 4095 steps never reallocate after the first one
         const int64_t cap = std::max(nr * stride, std::max(2 * s->r_cap, nr * (int64_t)4096));
@@ -2787,7 +2792,9 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         CIA_TRY(dalloc(p, &s->r_dev, (size_t)cap));
         s->r_cap = cap;
     }
-    double *const rb = s->r_dev;   // device trace of r(t)
+    // device trace of r(t): the plan's own buffer, or the caller-provided one
+    // of the allocation-free entry point
+    double *const rb = r_ext ? r_ext : s->r_dev;
     const bool rk4 = p->stepper == CIA_RK4;
     const int64_t grid = (n + 255) / 256;
     int cur = 0;
@@ -2826,7 +2833,8 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
         }
     } else {
         // (the direct triadic path launches an extra kernel per stage: no graph)
-        const bool replay = (p->flags & CIA_FLAG_HIPGRAPH) && rk4 && steps > 0 && !(s->tri && s->direct);
+        // (the allocation-free entry point never builds a graph: its set-up allocates)
+        const bool replay = (p->flags & CIA_FLAG_HIPGRAPH) && rk4 && steps > 0 && !(s->tri && s->direct) && !r_ext;
         hipStream_t ws = st;   // stream the steps run on
         if (replay) {
             if (!s->gstream) {
@@ -3087,6 +3095,59 @@ cia_status phase_integrate(cia_plan *p, void *state, double dt, int64_t steps, d
     PhaseState *s = p->phase;
     return s->f64 ? integrate_impl<double>(p, s, state, dt, steps, r_trace, st)
                   : integrate_impl<float>(p, s, state, dt, steps, r_trace, st);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free integration: the r(t) trace in a static device array
+// ---------------------------------------------------------------------------
+// One copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (in host code it only names the symbol); it uses
+// the device address that hipGetSymbolAddress returns with that GPU current.
+static __device__ __align__(256) double scratch[NOALLOC_R_MAX];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of this GPU's scratch array; the caller has made `dev`
+// current.  Resolved once per device (at plan build, or at the first
+// allocation-free call on the device).
+cia_status noalloc_scratch(int dev, double **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= MAX_DEVICES) return set_error(CIA_EUNSUPPORTED, "device %d: above %d devices", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *q = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q) {
+            (void)hipGetLastError();
+            return set_error(CIA_EHIP, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+        }
+        g_scratch[dev] = static_cast<double *>(q);
+    }
+    *out = g_scratch[dev];
+    return CIA_OK;
+}
+
+cia_status phase_integrate_noalloc(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
+                                   hipStream_t st) {
+    PhaseState *s = p->phase;
+    const int64_t nr = s->batch > 0 ? s->batch : 1;
+    if (r_trace && (steps + 1) > NOALLOC_R_MAX / nr)
+        return set_error(CIA_EINVAL, "allocation-free integration: %lld trace values (%lld instances x %lld) exceed "
+                         "the %lld-value scratch array", (long long)(nr * (steps + 1)), (long long)nr,
+                         (long long)(steps + 1), (long long)NOALLOC_R_MAX);
+    double *rb = nullptr;
+    CIA_TRY(noalloc_scratch(p->device, &rb));
+    // per-launch timing creates events: off for this call
+    const int32_t every = p->timing_every;
+    p->timing_every = 0;
+    const cia_status r = s->f64 ? integrate_impl<double>(p, s, state, dt, steps, r_trace, st, rb)
+                                : integrate_impl<float>(p, s, state, dt, steps, r_trace, st, rb);
+    p->timing_every = every;
+    return r;
 }
 
 }  // namespace cia

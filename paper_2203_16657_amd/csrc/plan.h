@@ -123,6 +123,14 @@ cia_status batch_finish(cia_plan *p, BatchAcc &A);
 cia_status phase_rhs(cia_plan *p, const void *state, void *dstate, hipStream_t s);
 cia_status phase_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
                            hipStream_t s);
+// allocation-free integration (r(t) in the library's static device array of
+// NOALLOC_R_MAX doubles per GPU); noalloc_scratch resolves that array's
+// device address on the current device
+constexpr int64_t NOALLOC_R_MAX = 1 << 17;
+static_assert(NOALLOC_R_MAX == CIA_NOALLOC_R_MAX, "scratch size of the allocation-free entry point");
+cia_status phase_integrate_noalloc(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
+                                   hipStream_t s);
+cia_status noalloc_scratch(int dev, double **out);
 void phase_free(cia_plan *p);
 
 // Phase model on the structured adjacencies of App. B (rank one, ring).
