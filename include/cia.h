@@ -435,7 +435,8 @@ typedef struct cia_plan_info {
                                  missing intra-community triples, three per triple) */
     int32_t judge_fallbacks;  /* flock: communities currently on the exact fallback (read
                                  from the device; synchronises it) */
-    int32_t reserved;
+    int32_t tiled_comms;      /* FP32 phase plans: communities above the LDS cap whose z
+                                 values are staged one column tile at a time */
     double bytes_aux;         /* algorithmic HBM bytes of the auxiliary launch before each
                                  stage (triadic pair sums: the missing-pair lists, 16 B per
                                  chunk, and the sums written), 0 if there is none */

@@ -56,6 +56,7 @@ constexpr int SLICE = 64;                // rows per slice = lanes per wavefront
 constexpr int UF_STAGED = 1;   // community z staged in LDS, S-neg as uint16 local indices
 constexpr int UF_WIDE = 2;     // FP64 observables and combine (F32 plans)
 constexpr int UF_ASSIGNED = 4; // rows of a dense community (E1 applies)
+constexpr int UF_TILED = 8;    // community above the LDS cap: z staged tile by tile, S-neg per tile
 
 // 64 rows of one community; chunk k of lane l of stream q sits at
 // beg[q] + 64 k + l.  Streams: 0 = S-neg, 1 = S-pos (pairwise remainder),
@@ -65,7 +66,8 @@ struct alignas(16) Slice {
     int32_t row0, rows;   // first row (community order), number of rows (1..64)
     uint32_t beg[4];      // first 16-byte chunk of each stream's block
     int32_t w[4];         // chunks per lane of each stream
-    int32_t pad0, pad1;   // keeps the descriptor at 48 bytes
+    int32_t tw;           // tiled communities: first entry of this slice's per-tile S-neg widths
+    int32_t pad1;         // keeps the descriptor at 48 bytes
 };
 
 // A work unit (one block): a run of slices of one community or of the rows
@@ -182,6 +184,8 @@ struct PhaseArgs {
     int32_t pq;
     int32_t stage, mode, want_r, lds_cap;
     uint32_t pad_pos;         // position whose z is 0 (= n): target of padded int32 entries
+    const int32_t *tile_w;    // tiled communities: S-neg chunks per lane of every (slice, tile)
+    int32_t tile_cap;         // largest tile of a tiled community (nodes)
 };
 
 // The remainder streams are read once per stage: non-temporal loads keep
@@ -347,6 +351,30 @@ __device__ __forceinline__ void gather_staged_rows(cx<R> (&T)[P], const uint4 *_
         gather_rows<R, P, UG, false>(T, pos + (size_t)UG * SLICE, wp - UG, cs, th, pad, (R)1, padp);
 }
 
+// S-neg chunks of one lane gathered from the staged z in LDS: 8 uint16 byte
+// offsets per chunk, UL chunks per batch (a tile of a tiled community).
+template <typename R, int P, int UL>
+__device__ __forceinline__ void gather_lds_rows(cx<R> (&T)[P], const uint4 *__restrict__ neg, int wn,
+                                                const cx<R> *zsh, uint4 padl) {
+    for (int k = 0; k < wn; k += UL) {
+        uint4 nv[UL];
+#pragma unroll
+        for (int u = 0; u < UL; u++) nv[u] = k + u < wn ? ld_stream(neg + (size_t)(k + u) * SLICE) : padl;
+#pragma unroll
+        for (int u = 0; u < UL; u++) {
+            const uint32_t q4[4] = {nv[u].x, nv[u].y, nv[u].z, nv[u].w};
+            cx<R> z[8];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                z[2 * q] = zat(zsh, q4[q] & 0xffffu);
+                z[2 * q + 1] = zat(zsh, q4[q] >> 16);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) acc_z<R, P>(T, z[q], (R)-1);
+        }
+    }
+}
+
 // Stream a lane's list of partner pairs (j, k) and return sum z_j z_k:
 // 2 pairs of int32 positions per chunk, gathered as z (GATHER_Z) or as
 // theta with z recomputed; the pad position contributes 0.
@@ -499,6 +527,53 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
         for (int k = 0; k < P; k++) qx[k] = qy[k] = (R)0, qdx[k] = qdy[k] = 0.0;
     }
 
+    // ---- 1b. communities above the LDS cap (WIDE instantiations only): the
+    //      S-neg sums of this wavefront's slices, the community's z staged
+    //      one column tile at a time ----
+    constexpr int SMAX = P <= 2 ? 4 : (P <= 4 ? 2 : 1);   // slices per wavefront of a tiled unit
+    const bool tiled = WIDE && gather && (Un.flags & UF_TILED) != 0;
+    cx<R> Tn[SMAX][P];
+#pragma unroll
+    for (int j = 0; j < SMAX; j++)
+#pragma unroll
+        for (int k = 0; k < P; k++) Tn[j][k].x = Tn[j][k].y = (R)0;
+    if (WIDE && tiled) {
+        const int nt = (lam + a.tile_cap - 1) / a.tile_cap;
+        const int ts = (lam + nt - 1) / nt;
+        const uint32_t tb = (uint32_t)ts * (uint32_t)sizeof(cx<R>);   // pad: the zero slot zsh[ts]
+        const uint4 padt = make_uint4(tb | (tb << 16), tb | (tb << 16), tb | (tb << 16), tb | (tb << 16));
+        int toff[SMAX];
+#pragma unroll
+        for (int j = 0; j < SMAX; j++) toff[j] = 0;
+        constexpr int ULT = P >= 4 ? 2 : 8 / P;
+        for (int t = 0; t < nt; t++) {
+            const int t0 = t * ts, len = min(ts, lam - t0);
+            if (t > 0) __syncthreads();   // the previous tile's gathers are done
+            for (int j0 = tid; j0 < len; j0 += BLOCK * 8) {
+                cx<R> v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (j0 + u * BLOCK < len) v[u] = a.cs_in[off + t0 + j0 + u * BLOCK];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (j0 + u * BLOCK < len) zsh[j0 + u * BLOCK] = v[u];
+            }
+            if (tid == 0) zsh[ts] = cx<R>{(R)0, (R)0};
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < SMAX; j++) {
+                const int sl = Un.s0 + wid + j * NW;
+                if (sl < Un.s1) {
+                    const Slice S = a.slices[sl];
+                    const int w = a.tile_w[S.tw + t];
+                    gather_lds_rows<R, P, ULT>(Tn[j], a.negdata + S.beg[0] + (size_t)toff[j] * SLICE + lane, w, zsh,
+                                               padt);
+                    toff[j] += w;
+                }
+            }
+        }
+    }
+
     // partial observables of the next stage
     float ps[2 * P], pc[2 * P];
     double pd[2 * P];
@@ -516,7 +591,8 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     // in flight while the previous slice is gathered
     Slice Snext;
     if (Un.s0 + wid < Un.s1) Snext = a.slices[Un.s0 + wid];
-    for (int sl = Un.s0 + wid; sl < Un.s1; sl += NW) {
+    int jsl = 0;   // this wavefront's slice count (tiled units: index into Tn)
+    for (int sl = Un.s0 + wid; sl < Un.s1; sl += NW, jsl++) {
         const Slice S = Snext;
         if (sl + NW < Un.s1) Snext = a.slices[sl + NW];
         const bool mine = lane < S.rows;
@@ -544,7 +620,14 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                 gather_staged_rows<R, P, UL, UG>(T, a.negdata + S.beg[0] + lane, S.w[0], a.posdata + S.beg[1] + lane,
                                                  S.w[1], zsh, a.cs_in, a.th_in, a.pad_pos, padl, padp);
             } else {
-                if (!DIRECT)
+                if (WIDE && tiled) {
+                    // S-neg summed tile by tile above (static indexing keeps Tn in registers)
+#pragma unroll
+                    for (int j = 0; j < SMAX; j++)
+                        if (j == jsl)
+#pragma unroll
+                            for (int k = 0; k < P; k++) T[k].x += Tn[j][k].x, T[k].y += Tn[j][k].y;
+                } else if (!DIRECT)
                     gather_rows<R, P, UG, false>(T, a.negdata + S.beg[0] + lane, S.w[0], a.cs_in, a.th_in, a.pad_pos, (R)-1, padp);
                 gather_rows<R, P, UG, DIRECT>(T, a.posdata + S.beg[1] + lane, S.w[1], a.cs_in, a.th_in, a.pad_pos, (R)1, padp);
             }
@@ -1572,7 +1655,7 @@ struct PhaseState {
     int P = 1;
     bool f64 = false, direct = false, complete_direct = false;
     int block = 256;
-    bool has_wide = false;   // F32 plan with at least one FP64-observable community
+    bool has_wide = false;   // F32 plan with a community beyond the LDS cap (FP64 observables or tiled)
     bool tri = false;        // triadic model
     bool poly = false;       // polynomial difference coupling
     void *gen = nullptr;     // general coupling coefficients on the device (R), or NULL
@@ -1602,6 +1685,8 @@ struct PhaseState {
     Unit *units = nullptr;
     Slice *slices = nullptr;
     uint4 *negdata = nullptr, *posdata = nullptr, *tposdata = nullptr;
+    int32_t *tile_w = nullptr;   // per (slice, tile) S-neg widths of tiled communities
+    int32_t tile_cap = 0;        // tile capacity (nodes) of tiled communities
     int32_t *cnt = nullptr, *perm = nullptr;
     void *omega = nullptr, *theta_n = nullptr, *acc = nullptr, *th[2] = {nullptr, nullptr};
     void *cs[2] = {nullptr, nullptr};
@@ -1651,6 +1736,7 @@ struct PhaseState {
 struct StreamIn {
     const std::vector<int64_t> *ptr = nullptr;   // [n+1] in entries (null: empty stream)
     const int32_t *val = nullptr;
+    int32_t *mut = nullptr;   // S-neg of tiled communities: val, rewritten in place by build_sell
     bool local = false;
     bool pair = false;
 };
@@ -1658,6 +1744,7 @@ struct StreamIn {
 struct Sell {
     std::vector<int32_t> newpos;          // old position -> new position
     std::vector<Slice> slices;
+    std::vector<int32_t> tile_w;          // tiled communities: S-neg width of every (slice, tile)
     std::vector<int32_t> seg_slice_off;   // segment -> first slice
     std::vector<uint4> data[4];
 };
@@ -1671,20 +1758,42 @@ struct Sell {
 // lambda), pre-multiplied by zscale = sizeof(z) so they are LDS byte
 // offsets; everything else as int32 new positions (4 per chunk, pairs 2 per
 // chunk, pad n).
+// Segments with seg_staged[c] == SEG_TILED hold a community above the LDS
+// cap: its S-neg (stream 0) is split by column tile (ntiles = ceil(lambda /
+// tile_cap) tiles of TS = ceil(lambda / ntiles) nodes), every tile stored as
+// its own sliced block of uint16 in-tile byte offsets (pad TS * zscale), the
+// blocks of a slice one after another; out.tile_w holds every (slice, tile)
+// width and Slice::tw the slice's first.
+constexpr char SEG_STAGED = 1, SEG_TILED = 2;
+static inline void tile_shape(int64_t lam, int64_t tile_cap, int64_t &nt, int64_t &ts) {
+    nt = (lam + tile_cap - 1) / tile_cap;
+    ts = (lam + nt - 1) / nt;
+}
+
 static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, int32_t ncomm,
                              const std::vector<char> &seg_staged, const StreamIn (&S)[4], uint32_t zscale,
-                             Sell &out) {
+                             Sell &out, int64_t tile_cap = 0) {
     const int32_t nseg = ncomm + 1;
     std::vector<int64_t> sb(nseg + 1);
     for (int32_t c = 0; c <= ncomm; c++) sb[c] = c < ncomm ? comm_off[c] : (ncomm ? comm_off[ncomm] : 0);
     sb[nseg] = n;
     auto len = [&](int q, int64_t i) -> int64_t { return S[q].ptr ? (*S[q].ptr)[i + 1] - (*S[q].ptr)[i] : 0; };
+    auto tiled = [&](int q, int32_t c) -> bool { return q == 0 && c < ncomm && seg_staged[c] == SEG_TILED; };
     // entries per 16-byte chunk of stream q in segment c
     auto per = [&](int q, int32_t c) -> int64_t {
         const bool st = c < ncomm && seg_staged[c] && S[q].local;
         const int64_t eb = (st ? 2 : 4) * (S[q].pair ? 2 : 1);
         return 16 / eb;
     };
+    // entries of row i (old position) of a tiled segment in column tile t:
+    // once rewritten to new local indices and sorted, each tile is one range
+    auto tile_range = [&](int32_t c, int64_t i, int64_t t, int64_t ts, int64_t &e0, int64_t &e1) {
+        const int32_t *v = S[0].val + (*S[0].ptr)[i];
+        const int64_t m = len(0, i);
+        e0 = std::lower_bound(v, v + m, (int32_t)(t * ts)) - v;
+        e1 = std::lower_bound(v, v + m, (int32_t)((t + 1) * ts)) - v;
+    };
+    // (for a tiled S-neg this is the untiled count: it only orders the rows)
     auto chunks = [&](int q, int32_t c, int64_t i) -> int64_t { return (len(q, i) + per(q, c) - 1) / per(q, c); };
     out.newpos.resize(n);
     std::vector<int32_t> oldpos(n);
@@ -1705,8 +1814,23 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
             out.newpos[b + idx[k]] = (int32_t)(b + k);
         }
     }
+    // tiled segments: S-neg entries rewritten to new local indices (the
+    // staging order) and sorted per row, so tiles are ranges of each row
+    for (int32_t c = 0; c < ncomm; c++) {
+        if (seg_staged[c] != SEG_TILED || !S[0].ptr) continue;
+        if (!S[0].mut) return set_error(CIA_EINVAL, "internal: tiled S-neg needs a writable list");
+        const int64_t b = sb[c], e = sb[c + 1];
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = b; i < e; i++) {
+            int32_t *v = S[0].mut + (*S[0].ptr)[i];
+            const int64_t m = len(0, i);
+            for (int64_t k = 0; k < m; k++) v[k] = out.newpos[b + v[k]] - (int32_t)b;
+            std::sort(v, v + m);
+        }
+    }
     // slices and their widths
     out.slices.clear();
+    out.tile_w.clear();
     out.seg_slice_off.assign(nseg + 1, 0);
     uint64_t tot[4] = {0, 0, 0, 0};
     for (int32_t c = 0; c < nseg; c++) {
@@ -1717,7 +1841,24 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
             Sl.rows = (int32_t)std::min<int64_t>(SLICE, sb[c + 1] - r);
             for (int q = 0; q < 4; q++) {
                 int64_t w = 0;
-                for (int l = 0; l < Sl.rows; l++) w = std::max(w, chunks(q, c, oldpos[r + l]));
+                if (tiled(q, c)) {
+                    // per-tile widths, the tile blocks one after another
+                    int64_t nt, ts;
+                    tile_shape(sb[c + 1] - sb[c], tile_cap, nt, ts);
+                    Sl.tw = (int32_t)out.tile_w.size();
+                    for (int64_t t = 0; t < nt; t++) {
+                        int64_t wt = 0;
+                        for (int l = 0; l < Sl.rows; l++) {
+                            int64_t e0, e1;
+                            tile_range(c, oldpos[r + l], t, ts, e0, e1);
+                            wt = std::max(wt, (e1 - e0 + 7) / 8);
+                        }
+                        out.tile_w.push_back((int32_t)wt);
+                        w += wt;
+                    }
+                } else {
+                    for (int l = 0; l < Sl.rows; l++) w = std::max(w, chunks(q, c, oldpos[r + l]));
+                }
                 Sl.beg[q] = (uint32_t)tot[q];
                 Sl.w[q] = (int32_t)w;
                 tot[q] += (uint64_t)w * SLICE;
@@ -1743,6 +1884,30 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
         const int64_t off = sb[c], lam = sb[c + 1] - sb[c];
         for (int q = 0; q < 4; q++) {
             if (!S[q].ptr || Sl.w[q] == 0) continue;
+            if (tiled(q, c)) {
+                // tile t's block: its width's chunks of in-tile offsets, pad TS
+                int64_t nt, ts;
+                tile_shape(lam, tile_cap, nt, ts);
+                uint16_t *w16 = reinterpret_cast<uint16_t *>(out.data[q].data() + Sl.beg[q]);
+                int64_t base = 0;   // chunks of the earlier tiles, per lane
+                for (int64_t t = 0; t < nt; t++) {
+                    const int64_t wt = out.tile_w[Sl.tw + t];
+                    for (int l = 0; l < SLICE; l++) {
+                        const int64_t o = l < Sl.rows ? oldpos[Sl.row0 + l] : -1;
+                        int64_t e0 = 0, e1 = 0;
+                        if (o >= 0) tile_range(c, o, t, ts, e0, e1);
+                        const int32_t *src = o >= 0 ? S[q].val + (*S[q].ptr)[o] : nullptr;
+                        for (int64_t e = 0; e < wt * 8; e++) {
+                            const int64_t chunk = base + e / 8, slot = e % 8;
+                            uint16_t v = (uint16_t)(ts * zscale);
+                            if (e < e1 - e0) v = (uint16_t)((src[e0 + e] - t * ts) * zscale);
+                            w16[(chunk * SLICE + l) * 8 + slot] = v;
+                        }
+                    }
+                    base += wt;
+                }
+                continue;
+            }
             const int64_t pc = per(q, c);
             const bool st16 = c < ncomm && seg_staged[c] && S[q].local;
             const int ne = S[q].pair ? 2 : 1;   // ints per entry
@@ -1776,6 +1941,16 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
     return CIA_OK;
 }
 
+// Slices a tiled community's unit may hold: SMAX per wavefront of the stage
+// kernel (SMAX = 4, 2, 1 for P <= 2, <= 4, above).
+static int tiled_slices(int P, int block) { return (P <= 2 ? 4 : (P <= 4 ? 2 : 1)) * (block / 64); }
+static cia_status check_tiled_units(const std::vector<Unit> &units, int P, int block) {
+    for (const Unit &u : units)
+        if ((u.flags & UF_TILED) && u.s1 - u.s0 > tiled_slices(P, block))
+            return set_error(CIA_EINVAL, "internal: tiled unit of %d slices", u.s1 - u.s0);
+    return CIA_OK;
+}
+
 // Build the work units and their launch order.
 //  - a unit is a run of slices of one community (or of the rows outside every
 //    community), sized by slice chunks;
@@ -1789,7 +1964,7 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
 //    fixed order.  Returns the number of slots.
 static int32_t make_units(const Sell &sell, const std::vector<int32_t> &comm_off, int32_t ncomm,
                           int64_t target_chunks, int min_slices, const std::vector<char> &comm_staged,
-                          uint32_t opt_flags, std::vector<Unit> &units) {
+                          uint32_t opt_flags, std::vector<Unit> &units, int max_tiled_slices = 16) {
     const int NX = 8;
     struct U2 {
         Unit u;
@@ -1806,10 +1981,14 @@ static int32_t make_units(const Sell &sell, const std::vector<int32_t> &comm_off
     auto make_group = [&](int32_t k0, int32_t k1, int32_t comm, int64_t off, int64_t lam) {
         std::vector<U2> g;
         int32_t k = k0;
+        // a tiled community's unit holds at most max_tiled_slices slices (its
+        // wavefronts keep the S-neg sums of every slice across the tiles)
+        const bool tl = comm >= 0 && comm_staged[comm] == SEG_TILED;
         while (k < k1) {
             int64_t w = 0;
             int32_t e = k;
-            while (e < k1 && (w < target_chunks || e - k < std::min(min_slices, k1 - k))) {
+            while (e < k1 && (w < target_chunks || e - k < std::min(min_slices, k1 - k)) &&
+                   (!tl || e - k < max_tiled_slices)) {
                 w += sw(e);
                 e++;
             }
@@ -1817,7 +1996,8 @@ static int32_t make_units(const Sell &sell, const std::vector<int32_t> &comm_off
             if (comm >= 0) {
                 flags |= UF_ASSIGNED;
                 if ((double)lam > WIDE_COMMUNITY || (opt_flags & CIA_FLAG_FORCE_WIDE)) flags |= UF_WIDE;
-                if (comm_staged[comm]) flags |= UF_STAGED;
+                if (comm_staged[comm] == SEG_STAGED) flags |= UF_STAGED;
+                if (tl) flags |= UF_TILED;
             }
             Unit u{k, e, flags, (int32_t)(comm >= 0 ? off : 0), (int32_t)(comm >= 0 ? lam : 0), 0, 0, 0};
             g.push_back({u, w, comm});
@@ -2198,12 +2378,16 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
                 int64_t lam = p1.comm_off[cc + 1] - p1.comm_off[cc];
                 bool wide = (double)lam > WIDE_COMMUNITY || (o->flags & CIA_FLAG_FORCE_WIDE);
                 if (s->tri && wide) return set_error(CIA_EUNSUPPORTED, "triadic model: community above 1e5 nodes");
-                comm_staged[cc] = lam <= cap && !wide;
+                // above the LDS cap, FP32 phase plans (difference coupling) stage
+                // the community's z tile by tile; other plans gather int32 positions
+                const bool tile_ok = !f64 && !s->poly && !s->tri && !gen && cap > 0;
+                comm_staged[cc] = wide ? 0 : (lam <= cap ? SEG_STAGED : (tile_ok ? SEG_TILED : 0));
                 if (comm_staged[cc]) nnz_neg_staged += p1.negptr[p1.comm_off[cc + 1]] - p1.negptr[p1.comm_off[cc]];
             }
             StreamIn S[4];
             S[0].ptr = &p1.negptr;
             S[0].val = p1.neg_local.data();
+            S[0].mut = p1.neg_local.data();
             S[0].local = true;
             S[1].ptr = &p1.posptr;
             S[1].val = p1.pos.data();
@@ -2213,7 +2397,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
                 S[3].val = xval.data();
                 S[3].pair = true;
             }
-            CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, S, (uint32_t)zbytes, sell));
+            CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, S, (uint32_t)zbytes, sell, cap));
+            s->tile_cap = (int32_t)cap;
             if (s->d0 != 0.0) {
                 // |S+| - |S-| per row (all zero for a complete graph)
                 cnt_old.resize(n);
@@ -2279,7 +2464,12 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     for (int32_t cc = 0; cc < p1.ncomm; cc++) {
         int64_t lam = p1.comm_off[cc + 1] - p1.comm_off[cc];
         maxlam = std::max<int64_t>(maxlam, lam);
-        if (!s->direct && comm_staged[cc]) maxstaged = std::max<int64_t>(maxstaged, lam);
+        if (!s->direct && comm_staged[cc] == SEG_STAGED) maxstaged = std::max<int64_t>(maxstaged, lam);
+        if (!s->direct && comm_staged[cc] == SEG_TILED) {
+            int64_t nt, ts;
+            tile_shape(lam, cap, nt, ts);
+            maxstaged = std::max<int64_t>(maxstaged, ts);
+        }
     }
     s->lds_cap = (int)maxstaged;
 
@@ -2305,7 +2495,9 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         Sell view;
         view.slices = s->h_slices;
         view.seg_slice_off = s->h_seg_off;
-        nslots = make_units(view, s->h_comm_off, s->h_ncomm, s->unit_work, 4, s->h_staged, s->h_flags, units);
+        nslots = make_units(view, s->h_comm_off, s->h_ncomm, s->unit_work, 4, s->h_staged, s->h_flags, units,
+                            tiled_slices(s->P, s->block));
+        CIA_TRY(check_tiled_units(units, s->P, s->block));
         s->ncomm = nc;
     }
     if (f64)
@@ -2313,7 +2505,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     if (s->poly)
         for (Unit &u : units) u.flags &= ~UF_WIDE;   // the polynomial moments are FP64 throughout
     for (const Unit &u : units)
-        if (u.flags & UF_WIDE) s->has_wide = true;
+        if (u.flags & (UF_WIDE | UF_TILED)) s->has_wide = true;
     s->nunits = (int32_t)units.size();
     s->smem = (size_t)zbytes * (s->lds_cap + 1);
     if (s->smem > LDS_BYTES) return set_error(CIA_EUNSUPPORTED, "LDS request too large");
@@ -2332,6 +2524,10 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     for (int32_t cc = 0; cc < p1.ncomm; cc++)
         if ((double)(p1.comm_off[cc + 1] - p1.comm_off[cc]) > WIDE_COMMUNITY) wide++;
     inf.wide_comms = s->direct ? 0 : wide;
+    int tiledc = 0;
+    for (int32_t cc = 0; cc < p1.ncomm; cc++)
+        if (!s->direct && comm_staged[cc] == SEG_TILED) tiledc++;
+    inf.tiled_comms = tiledc;
     inf.method = o->method;
     inf.precision = o->precision;
     inf.model = s->tri ? CIA_MODEL_TRIADIC : (s->poly ? CIA_MODEL_POLY : CIA_MODEL_PHASE);
@@ -2368,6 +2564,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         CIA_TRY(dupload(p, &s->negdata, sell.data[0].data(), sell.data[0].size()));
         CIA_TRY(dupload(p, &s->posdata, sell.data[1].data(), sell.data[1].size()));
         CIA_TRY(dupload(p, &s->tposdata, sell.data[3].data(), sell.data[3].size()));
+        if (sell.tile_w.empty()) sell.tile_w.push_back(0);
+        CIA_TRY(dupload(p, &s->tile_w, sell.tile_w.data(), sell.tile_w.size()));
         // the kernels read cnt[i] only when d_0 != 0, and then it holds n entries
         if (s->d0 != 0.0 && (int64_t)cnt.size() != n)
             return set_error(CIA_EINVAL, "internal: row counts missing for d_0 != 0");
@@ -2535,6 +2733,8 @@ static PhaseArgs<R> base_args(cia_plan *p, PhaseState *s) {
         a.dcos[k] = (R)s->dcos[k];
     }
     a.lds_cap = s->lds_cap;
+    a.tile_w = s->tile_w;
+    a.tile_cap = s->tile_cap;
     a.pad_pos = (uint32_t)p->n;
     return a;
 }
@@ -2960,7 +3160,9 @@ static cia_status apply_units(cia_plan *p, PhaseState *s, int64_t target) {
     view.slices = s->h_slices;
     view.seg_slice_off = s->h_seg_off;
     std::vector<Unit> units;
-    const int32_t nslots = make_units(view, s->h_comm_off, s->h_ncomm, target, 4, s->h_staged, s->h_flags, units);
+    const int32_t nslots = make_units(view, s->h_comm_off, s->h_ncomm, target, 4, s->h_staged, s->h_flags, units,
+                                      tiled_slices(s->P, s->block));
+    CIA_TRY(check_tiled_units(units, s->P, s->block));
     if (units.empty()) units.push_back(Unit{0, 0, 0, 0, 0, 0, 0, 0});
     if (units.size() > s->units_cap) {
         CIA_TRY(dalloc(p, &s->units, units.size()));
