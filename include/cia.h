@@ -111,6 +111,8 @@ typedef enum cia_status {
 #define CIA_FLAG_FORCE_WIDE 0x100u  /* FP64 observables/combine for every community */
 #define CIA_FLAG_FORCE_NEG32 0x200u /* S-neg as int32 positions for every community */
 #define CIA_FLAG_NO_LDS 0x400u      /* no LDS staging of community z values */
+#define CIA_FLAG_NO_RESIDENT 0x800u /* integrate small networks stage by stage, not in one
+                                       resident workgroup launch (see cia_integrate) */
 
 typedef struct cia_graph {
     int64_t n;                 /* number of nodes N >= 1 */
@@ -254,6 +256,15 @@ cia_status cia_rhs(cia_plan *p, const void *state, void *dstate, void *stream);
  *            CIA_ENONFINITE if the state became NaN or Inf.
  *  The flock model integrates positions and velocities (six planes); it
  *  takes no r_trace (CIA_EINVAL if given).
+ *  Small networks (phase model, difference coupling of order <= 4, CIA
+ *  method, single network, no community above the LDS staging cap, at most
+ *  128 slices of 64 rows (FP64: 64), at most 2^17 remainder entries and
+ *  their z values within one CU's LDS)
+ *  run the whole call in one launch of one 1024-thread workgroup:
+ *  every z of a stage in
+ *  LDS, stages separated by workgroup barriers (cia_plan_info.resident = 1;
+ *  CIA_FLAG_NO_RESIDENT keeps the stage-by-stage launches).  Results agree
+ *  with the stage-by-stage path up to the order of the community sums.
  */
 cia_status cia_integrate(cia_plan *p, void *state, double dt, int64_t steps, double *r_trace,
                          void *stream);
@@ -440,6 +451,9 @@ typedef struct cia_plan_info {
     double bytes_aux;         /* algorithmic HBM bytes of the auxiliary launch before each
                                  stage (triadic pair sums: the missing-pair lists, 16 B per
                                  chunk, and the sums written), 0 if there is none */
+    int32_t resident;         /* 1: cia_integrate runs the whole call in one resident
+                                 workgroup (small single networks, see cia_integrate) */
+    int32_t reserved;
 } cia_plan_info;
 
 cia_status cia_plan_get_info(const cia_plan *p, cia_plan_info *info);

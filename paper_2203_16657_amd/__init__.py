@@ -28,7 +28,7 @@ CIA_RK4, CIA_EULER = 0, 1
 CIA_BASIS_EXACT, CIA_BASIS_FOURIER, CIA_BASIS_LEARNED = 0, 1, 2
 CIA_FLAG_KEEP_LABELS, CIA_FLAG_TIMING, CIA_FLAG_NO_VALIDATE, CIA_FLAG_HIPGRAPH = 0x1, 0x2, 0x4, 0x8
 CIA_FLAG_NO_JUDGE, CIA_FLAG_AUTOTUNE = 0x10, 0x20
-CIA_FLAG_FORCE_WIDE, CIA_FLAG_FORCE_NEG32, CIA_FLAG_NO_LDS = 0x100, 0x200, 0x400
+CIA_FLAG_FORCE_WIDE, CIA_FLAG_FORCE_NEG32, CIA_FLAG_NO_LDS, CIA_FLAG_NO_RESIDENT = 0x100, 0x200, 0x400, 0x800
 
 _c = ctypes
 _vp = ctypes.c_void_p
@@ -68,7 +68,7 @@ class cia_plan_info(_c.Structure):
                 ("method", _c.c_int32), ("precision", _c.c_int32), ("model", _c.c_int32),
                 ("p", _c.c_int32), ("bytes_per_rhs", _c.c_double), ("bytes_per_stage", _c.c_double),
                 ("nnz_extra", _c.c_int64), ("judge_fallbacks", _c.c_int32), ("tiled_comms", _c.c_int32),
-                ("bytes_aux", _c.c_double)]
+                ("bytes_aux", _c.c_double), ("resident", _c.c_int32), ("reserved", _c.c_int32)]
 
 
 class cia_tune_report(_c.Structure):

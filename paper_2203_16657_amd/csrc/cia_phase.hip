@@ -858,6 +858,283 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
 }
 
 // ---------------------------------------------------------------------------
+// small networks: the whole integration in one launch of one workgroup
+// ---------------------------------------------------------------------------
+// For a network whose z values fit one workgroup's LDS, every step and stage
+// of cia_integrate runs inside one 1024-thread workgroup: all z of the
+// current stage sit in LDS, so the S-neg and S-pos partners of a row are both
+// LDS reads, stages are separated by workgroup barriers instead of kernel
+// launches, and theta_n, the RK4 accumulator and omega of a row stay in its
+// lane's registers for the whole call.  Same layout (slices, remainder
+// streams, padding) as the stage kernel; E1 observables and r(t) from
+// per-slice FP64 partials summed in a fixed order.
+constexpr int RES_PMAX = 4;
+constexpr size_t RES_LDS_BYTES = 160 * 1024;   // LDS of one CU
+constexpr int64_t RES_MAX_REMAINDER = 1 << 17; // S-neg + S-pos entries
+// 1024 threads (128 VGPRs per lane).  A lane keeps theta_n, the
+// accumulator, omega and H of one row per slice of its wavefront in
+// registers: 8 slices in FP32, 4 in FP64 (twice the registers per row), and
+// loads RES_UB (FP64: half as many) remainder chunks of each stream at once.
+template <typename R>
+__host__ __device__ constexpr int res_block() { return 1024; }
+template <typename R>
+__host__ __device__ constexpr int res_slices() { return sizeof(R) == 8 ? 4 : 8; }
+template <typename R>
+__host__ __device__ constexpr int res_ub() { return sizeof(R) == 8 ? 2 : 4; }
+
+template <typename R>
+struct ResArgs {
+    const Slice *slices;
+    const uint4 *negdata, *posdata;
+    const int32_t *slice_comm;   // [nslices] community of each slice, -1 = rows of no community
+    const int32_t *slice_flags;  // [nslices] UF_STAGED: S-neg as uint16 local byte offsets
+    const int32_t *comm_off;     // [ncomm + 1]
+    const int32_t *comm_slice0;  // [ncomm + 1] first slice of each community (slices of one community are contiguous)
+    const int32_t *cnt;          // [n] |S+| - |S-| (only when d0 != 0)
+    const int32_t *perm;
+    const R *omega;
+    const R *state_in;           // user order
+    R *state_out;                // user order
+    double *r_out;               // [steps + 1] or NULL
+    int32_t n, nslices, ncomm, mode;   // mode: M_RK4 or M_EULER
+    int64_t steps;
+    R dt, Kn, d0, hzero;
+    R dsin[PMAX + 1], dcos[PMAX + 1];
+};
+
+// LDS of the resident kernel: z of every node and the zero slot (rounded up
+// to 16 bytes), the slice partials and the community sums
+template <typename R>
+__host__ __device__ constexpr size_t res_zbytes(int64_t n) { return (sizeof(cx<R>) * (size_t)(n + 1) + 15) & ~(size_t)15; }
+template <typename R>
+__host__ __device__ constexpr size_t res_smem(int64_t n, int64_t nslices, int64_t ncomm, int P) {
+    // z | slice partials | community sums | slice descriptors | slice
+    // community and flags | community offsets and first slices | omega and
+    // |S+| - |S-| per row
+    // (the 8-byte omega array sits before the 4-byte arrays, so it stays aligned)
+    return res_zbytes<R>(n) + sizeof(double2) * (size_t)(nslices * (P + 1) + ncomm * P) +
+           sizeof(Slice) * (size_t)nslices + sizeof(R) * (size_t)n +
+           sizeof(int32_t) * (size_t)(2 * nslices + 2 * (ncomm + 1) + n);
+}
+
+template <typename R, int P>
+__global__ __launch_bounds__(res_block<R>()) void resident_integrate_kernel(ResArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<R> *zsh = reinterpret_cast<cx<R> *>(smem);                                   // [n + 1]
+    double2 *part = reinterpret_cast<double2 *>(smem + res_zbytes<R>(a.n));          // [nslices][P + 1]
+    double2 *Q = part + (size_t)a.nslices * (P + 1);                                 // [ncomm][P]
+    Slice *ssh = reinterpret_cast<Slice *>(Q + (size_t)a.ncomm * P);                 // [nslices]
+    R *om_sh = reinterpret_cast<R *>(ssh + a.nslices);                                // [n]
+    int32_t *scomm = reinterpret_cast<int32_t *>(om_sh + a.n);                        // [nslices]
+    int32_t *sflag = scomm + a.nslices;                                               // [nslices]
+    int32_t *coff = sflag + a.nslices;                                                // [ncomm + 1]
+    int32_t *cs0 = coff + (a.ncomm + 1);                                              // [ncomm + 1]
+    int32_t *cnt_sh = cs0 + (a.ncomm + 1);                                            // [n]
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nst = a.mode == M_RK4 ? 4 : 1;
+    constexpr int RES_BLOCK = res_block<R>();
+    constexpr int RES_WAVES = RES_BLOCK / 64;
+    constexpr int RES_SLICES = res_slices<R>();
+    constexpr int UB = res_ub<R>();   // remainder chunks per batch of loads (S-neg and S-pos issued together)
+
+    // descriptors read every stage: into LDS once
+    for (int t = threadIdx.x; t < a.nslices; t += RES_BLOCK) {
+        ssh[t] = a.slices[t];
+        scomm[t] = a.slice_comm[t];
+        sflag[t] = a.slice_flags[t];
+    }
+    for (int t = threadIdx.x; t <= a.ncomm; t += RES_BLOCK) {
+        coff[t] = a.comm_off[t];
+        cs0[t] = a.comm_slice0[t];
+    }
+    for (int i = threadIdx.x; i < a.n; i += RES_BLOCK) {
+        om_sh[i] = a.omega ? a.omega[i] : (R)0;
+        cnt_sh[i] = a.d0 != (R)0 ? a.cnt[i] : 0;
+    }
+    __syncthreads();
+
+    // this lane's rows: one per slice of its wavefront
+    R tn[RES_SLICES], acc[RES_SLICES], H[RES_SLICES];
+#pragma unroll
+    for (int j = 0; j < RES_SLICES; j++) {
+        tn[j] = acc[j] = H[j] = (R)0;
+        const int sl = wid + j * RES_WAVES;
+        if (sl < a.nslices) {
+            const Slice S = ssh[sl];
+            if (lane < S.rows) tn[j] = a.state_in[a.perm[S.row0 + lane]];
+        }
+    }
+    if (threadIdx.x == 0) zsh[a.n] = cx<R>{(R)0, (R)0};   // target of padded S-pos entries
+
+    // z of the stage state th, the slice partials of z^k (k = 1..P) and of z,
+    // then the community sums and r
+    auto publish = [&](const R (&th)[RES_SLICES], int64_t rslot) {
+#pragma unroll
+        for (int j = 0; j < RES_SLICES; j++) {
+            const int sl = wid + j * RES_WAVES;
+            if (sl >= a.nslices) continue;
+            const Slice S = ssh[sl];
+            double2 pk[P + 1];
+#pragma unroll
+            for (int k = 0; k <= P; k++) pk[k] = make_double2(0.0, 0.0);
+            if (lane < S.rows) {
+                R sn, c0;
+                dsincos(th[j], &sn, &c0);
+                const cx<R> z = {c0, sn};
+                zsh[S.row0 + lane] = z;
+                cx<R> zk = z;
+#pragma unroll
+                for (int k = 0; k < P; k++) {
+                    pk[k] = make_double2((double)zk.x, (double)zk.y);
+                    if (k + 1 < P) zk = cmul(zk, z);
+                }
+                pk[P] = make_double2((double)z.x, (double)z.y);
+            }
+#pragma unroll
+            for (int k = 0; k <= P; k++)
+                for (int o = 32; o > 0; o >>= 1) {
+                    pk[k].x += __shfl_xor(pk[k].x, o);
+                    pk[k].y += __shfl_xor(pk[k].y, o);
+                }
+            if (lane == 0)
+#pragma unroll
+                for (int k = 0; k <= P; k++) part[(size_t)sl * (P + 1) + k] = pk[k];
+        }
+        __syncthreads();
+        // community sums of z^k over their slices, in slice order; r over all slices
+        for (int t = threadIdx.x; t < a.ncomm * P + 1; t += RES_BLOCK) {
+            if (t < a.ncomm * P) {
+                const int c = t / P, k = t % P;
+                double2 q = make_double2(0.0, 0.0);
+                for (int sl = cs0[c]; sl < cs0[c + 1]; sl++) {
+                    const double2 v = part[(size_t)sl * (P + 1) + k];
+                    q.x += v.x;
+                    q.y += v.y;
+                }
+                Q[t] = q;
+            } else if (a.r_out && rslot >= 0) {
+                double x = 0.0, y = 0.0;
+                for (int sl = 0; sl < a.nslices; sl++) {
+                    const double2 v = part[(size_t)sl * (P + 1) + P];
+                    x += v.x;
+                    y += v.y;
+                }
+                a.r_out[rslot] = sqrt(x * x + y * y) / (double)a.n;
+            }
+        }
+        __syncthreads();
+    };
+
+    publish(tn, 0);
+    for (int64_t step = 0; step < a.steps; step++) {
+        for (int st = 0; st < nst; st++) {
+            // right-hand side of every row from the z values in LDS
+#pragma unroll
+            for (int j = 0; j < RES_SLICES; j++) {
+                const int sl = wid + j * RES_WAVES;
+                if (sl >= a.nslices) continue;
+                const Slice S = ssh[sl];
+                const int c = scomm[sl];
+                const bool st16 = (sflag[sl] & UF_STAGED) != 0;
+                const uint32_t cbase = c >= 0 ? (uint32_t)coff[c] * (uint32_t)sizeof(cx<R>) : 0u;
+                // staged pads are lambda * sizeof(z): the next community's first z
+                // (or the zero slot), skipped by value
+                const uint32_t padb = c >= 0 ? (uint32_t)(coff[c + 1] - coff[c]) * (uint32_t)sizeof(cx<R>) : 0u;
+                cx<R> T[P];
+#pragma unroll
+                for (int k = 0; k < P; k++) T[k].x = T[k].y = (R)0;
+                const uint4 *neg = a.negdata + S.beg[0] + lane;
+                const uint4 *pos = a.posdata + S.beg[1] + lane;
+                for (int q0 = 0; q0 < S.w[0] || q0 < S.w[1]; q0 += UB) {
+                    // both streams' next UB chunks in flight together
+                    uint4 nv[UB], pv[UB];
+#pragma unroll
+                    for (int u = 0; u < UB; u++) {
+                        nv[u] = q0 + u < S.w[0] ? neg[(size_t)(q0 + u) * SLICE] : make_uint4(padb | (padb << 16), padb | (padb << 16), padb | (padb << 16), padb | (padb << 16));
+                        pv[u] = q0 + u < S.w[1] ? pos[(size_t)(q0 + u) * SLICE] : make_uint4(a.n, a.n, a.n, a.n);
+                    }
+#pragma unroll
+                    for (int u = 0; u < UB; u++) {
+                        if (q0 + u >= S.w[0]) continue;
+                        const uint32_t q4[4] = {nv[u].x, nv[u].y, nv[u].z, nv[u].w};
+                        if (st16) {
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                const uint32_t lo = q4[e] & 0xffffu, hi = q4[e] >> 16;
+                                cx<R> z0 = zat(zsh, cbase + lo), z1 = zat(zsh, cbase + hi);
+                                if (lo == padb) z0 = cx<R>{(R)0, (R)0};
+                                if (hi == padb) z1 = cx<R>{(R)0, (R)0};
+                                acc_z<R, P>(T, z0, (R)-1);
+                                acc_z<R, P>(T, z1, (R)-1);
+                            }
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; e++) acc_z<R, P>(T, zsh[q4[e]], (R)-1);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < UB; u++) {
+                        acc_z<R, P>(T, zsh[pv[u].x], (R)1);
+                        acc_z<R, P>(T, zsh[pv[u].y], (R)1);
+                        acc_z<R, P>(T, zsh[pv[u].z], (R)1);
+                        acc_z<R, P>(T, zsh[pv[u].w], (R)1);
+                    }
+                }
+                if (lane < S.rows) {
+                    const int i = S.row0 + lane;
+                    const cx<R> z = zsh[i];
+                    const bool assigned = c >= 0;
+                    const R lam = assigned ? (R)(coff[c + 1] - coff[c]) : (R)0;
+                    R s = (R)0;
+                    if (a.d0 != (R)0) s = a.d0 * (lam + (R)cnt_sh[i]);
+                    if (assigned) s -= a.hzero;
+                    cx<R> zk = z;
+#pragma unroll
+                    for (int k = 0; k < P; k++) {
+                        const double2 q = assigned ? Q[c * P + k] : make_double2(0.0, 0.0);
+                        const cx<R> A = {(R)q.x + T[k].x, (R)q.y + T[k].y};
+                        const cx<R> B = cmul(A, cx<R>{zk.x, -zk.y});
+                        s += a.dcos[k + 1] * B.x + a.dsin[k + 1] * B.y;
+                        if (k + 1 < P) zk = cmul(zk, z);
+                    }
+                    H[j] = om_sh[i] + a.Kn * s;
+                }
+            }
+            __syncthreads();   // every z of this stage has been read
+            // stage update and the next stage's z
+            R th[RES_SLICES];
+#pragma unroll
+            for (int j = 0; j < RES_SLICES; j++) {
+                if (a.mode == M_EULER) {
+                    tn[j] = wrap_2pi<R>(tn[j] + a.dt * H[j]);
+                    th[j] = tn[j];
+                } else if (st == 0) {
+                    acc[j] = H[j];
+                    th[j] = tn[j] + (R)0.5 * a.dt * H[j];
+                } else if (st == 1) {
+                    acc[j] += (R)2 * H[j];
+                    th[j] = tn[j] + (R)0.5 * a.dt * H[j];
+                } else if (st == 2) {
+                    acc[j] += (R)2 * H[j];
+                    th[j] = tn[j] + a.dt * H[j];
+                } else {
+                    tn[j] = wrap_2pi<R>(tn[j] + a.dt / (R)6 * (acc[j] + H[j]));
+                    th[j] = tn[j];
+                }
+            }
+            publish(th, st == nst - 1 ? step + 1 : -1);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RES_SLICES; j++) {
+        const int sl = wid + j * RES_WAVES;
+        if (sl >= a.nslices) continue;
+        const Slice S = ssh[sl];
+        if (lane < S.rows) a.state_out[a.perm[S.row0 + lane]] = tn[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // polynomial difference coupling (App. A.3; Desai-Zwanzig, App. A.5)
 // ---------------------------------------------------------------------------
 // The stage kernel of the polynomial model on the same units, slices and
@@ -1687,6 +1964,11 @@ struct PhaseState {
     uint4 *negdata = nullptr, *posdata = nullptr, *tposdata = nullptr;
     int32_t *tile_w = nullptr;   // per (slice, tile) S-neg widths of tiled communities
     int32_t tile_cap = 0;        // tile capacity (nodes) of tiled communities
+    // small networks: the whole integration in one resident workgroup
+    bool resident = false;
+    size_t res_smem = 0;
+    int32_t nslices = 0;
+    int32_t *res_slice_comm = nullptr, *res_slice_flags = nullptr, *res_comm_off = nullptr, *res_comm_slice0 = nullptr;
     int32_t *cnt = nullptr, *perm = nullptr;
     void *omega = nullptr, *theta_n = nullptr, *acc = nullptr, *th[2] = {nullptr, nullptr};
     void *cs[2] = {nullptr, nullptr};
@@ -2220,6 +2502,68 @@ static cia_status tri_build_missing(cia_plan *p, PhaseState *s, const std::vecto
     return CIA_OK;
 }
 
+// Whether the plan's integration runs in one resident workgroup: a single
+// network of the phase model with the difference coupling (order <= 4), the
+// CIA method, every community staged whole, at most 128 slices and LDS for
+// all z values, slice partials and community sums.
+template <typename R, int P>
+static bool res_attr(size_t bytes) {
+    const hipError_t e = hipFuncSetAttribute((const void *)resident_integrate_kernel<R, P>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e == hipSuccess;
+}
+template <typename R>
+static bool res_attr_p(int P, size_t bytes) {
+    switch (P) {
+        case 1: return res_attr<R, 1>(bytes);
+        case 2: return res_attr<R, 2>(bytes);
+        case 3: return res_attr<R, 3>(bytes);
+        default: return res_attr<R, 4>(bytes);
+    }
+}
+
+static cia_status resident_setup(cia_plan *p, PhaseState *s, const cia_options *o) {
+    s->resident = false;
+    if (s->direct || s->complete_direct || s->tri || s->poly || s->gen || s->batch > 0 || s->has_wide) return CIA_OK;
+    if ((o->flags & CIA_FLAG_NO_RESIDENT) || s->P > RES_PMAX || s->h_slices.empty()) return CIA_OK;
+    // one CU's LDS serves every remainder gather of a stage: beyond about
+    // 1.3e5 entries the stage-by-stage launches over all CUs are faster
+    // (measured: 34K entries 1.6x faster resident, 280K equal, 2.5M 4x slower)
+    if (p->info.nnz_neg + p->info.nnz_pos > RES_MAX_REMAINDER) return CIA_OK;
+    const int64_t nsl = (int64_t)s->h_slices.size();
+    if (nsl > (int64_t)(s->f64 ? res_block<double>() / 64 * res_slices<double>()
+                               : res_block<float>() / 64 * res_slices<float>())) return CIA_OK;
+    for (const Slice &S : s->h_slices)
+        if (S.w[2] || S.w[3]) return CIA_OK;
+    const int32_t nc = s->h_ncomm;
+    const size_t bytes = s->f64 ? res_smem<double>(p->n, nsl, nc, s->P) : res_smem<float>(p->n, nsl, nc, s->P);
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess) {
+        (void)hipGetLastError();
+        lds_max = 64 * 1024;
+    }
+    if (bytes > std::min<size_t>(RES_LDS_BYTES, (size_t)lds_max)) return CIA_OK;
+    // a device that refuses the LDS size keeps the stage-by-stage path
+    if (!(s->f64 ? res_attr_p<double>(s->P, bytes) : res_attr_p<float>(s->P, bytes))) return CIA_OK;
+    std::vector<int32_t> scomm(nsl, -1), sflags(nsl, 0);
+    for (int32_t c = 0; c < nc; c++)
+        for (int32_t k = s->h_seg_off[c]; k < s->h_seg_off[c + 1]; k++) {
+            scomm[k] = c;
+            sflags[k] = s->h_staged[c] == SEG_STAGED ? UF_STAGED : 0;
+        }
+    std::vector<int32_t> cs0(s->h_seg_off.begin(), s->h_seg_off.begin() + nc + 1);
+    CIA_TRY(dupload(p, &s->res_slice_comm, scomm.data(), scomm.size()));
+    CIA_TRY(dupload(p, &s->res_slice_flags, sflags.data(), sflags.size()));
+    CIA_TRY(dupload(p, &s->res_comm_off, s->h_comm_off.data(), s->h_comm_off.size()));
+    CIA_TRY(dupload(p, &s->res_comm_slice0, cs0.data(), cs0.size()));
+    s->nslices = (int32_t)nsl;
+    s->res_smem = bytes;
+    s->resident = true;
+    p->info.resident = 1;
+    return CIA_OK;
+}
+
 cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, const cia_coupling *c,
                        const double *omega, const cia_options *o, const BatchSpec *bs, P1 *pre) {
     PhaseState *s = new (std::nothrow) PhaseState();
@@ -2681,6 +3025,7 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
             s->coef = d;
         }
     }
+    CIA_TRY(resident_setup(p, s, o));
     // device address of this GPU's scratch array for the allocation-free
     // entry point, resolved at set-up with the plan's device current
     double *scr = nullptr;
@@ -2995,6 +3340,53 @@ static cia_status integrate_impl(cia_plan *p, PhaseState *s, void *state, double
     // device trace of r(t): the plan's own buffer, or the caller-provided one
     // of the allocation-free entry point
     double *const rb = r_ext ? r_ext : s->r_dev;
+    if (s->resident && (p->stepper == CIA_RK4 || p->stepper == CIA_EULER)) {
+        ResArgs<R> ra{};
+        ra.slices = s->slices;
+        ra.negdata = s->negdata;
+        ra.posdata = s->posdata;
+        ra.slice_comm = s->res_slice_comm;
+        ra.slice_flags = s->res_slice_flags;
+        ra.comm_off = s->res_comm_off;
+        ra.comm_slice0 = s->res_comm_slice0;
+        ra.cnt = s->cnt;
+        ra.perm = s->perm;
+        ra.omega = static_cast<const R *>(s->omega);
+        ra.state_in = static_cast<const R *>(state);
+        ra.state_out = static_cast<R *>(state);
+        ra.r_out = want_r ? rb : nullptr;
+        ra.n = (int32_t)n;
+        ra.nslices = s->nslices;
+        ra.ncomm = s->h_ncomm;
+        ra.mode = p->stepper == CIA_RK4 ? M_RK4 : M_EULER;
+        ra.steps = steps;
+        ra.dt = (R)dt;
+        ra.Kn = (R)s->Kn;
+        ra.d0 = (R)s->d0;
+        ra.hzero = (R)s->hzero;
+        for (int k = 0; k <= PMAX; k++) {
+            ra.dsin[k] = (R)s->dsin[k];
+            ra.dcos[k] = (R)s->dcos[k];
+        }
+        CIA_TRY(timing_begin(p, st, KK_STAGE, (int)std::min<int64_t>(INT32_MAX, std::max<int64_t>(1, steps * (p->stepper == CIA_RK4 ? 4 : 1)))));
+        switch (s->P) {
+            case 1: hipLaunchKernelGGL((resident_integrate_kernel<R, 1>), dim3(1), dim3(res_block<R>()), s->res_smem, st, ra); break;
+            case 2: hipLaunchKernelGGL((resident_integrate_kernel<R, 2>), dim3(1), dim3(res_block<R>()), s->res_smem, st, ra); break;
+            case 3: hipLaunchKernelGGL((resident_integrate_kernel<R, 3>), dim3(1), dim3(res_block<R>()), s->res_smem, st, ra); break;
+            default: hipLaunchKernelGGL((resident_integrate_kernel<R, 4>), dim3(1), dim3(res_block<R>()), s->res_smem, st, ra); break;
+        }
+        CIA_HIP(hipGetLastError());
+        CIA_TRY(timing_end(p, st));
+        if (want_r) {
+            CIA_HIP(hipMemcpyAsync(r_trace, rb, sizeof(double) * (steps + 1), hipMemcpyDeviceToHost, st));
+            CIA_HIP(hipStreamSynchronize(st));
+            for (int64_t k = 0; k <= steps; k++)
+                if (!std::isfinite(r_trace[k]))
+                    return set_error(CIA_ENONFINITE, "state became non-finite (r(t_%lld) = %g)", (long long)k,
+                                     r_trace[k]);
+        }
+        return CIA_OK;
+    }
     const bool rk4 = p->stepper == CIA_RK4;
     const int64_t grid = (n + 255) / 256;
     int cur = 0;
