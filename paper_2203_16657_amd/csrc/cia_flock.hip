@@ -75,8 +75,13 @@ __device__ inline float silu_grad(float z) {
     return sg * (1.0f + z * (1.0f - sg));
 }
 
+// w = K (s2 + r2)^(-beta) as K 2^(-beta log2(s2 + r2)) on the hardware base-2
+// logarithm and exponential (v_log_f32, v_exp_f32, about one ulp each).  The
+// argument is clamped below at the smallest normal float: those instructions
+// do not take denormal inputs, and s2 + r2 is at least s2 for every pair.
 __device__ inline float cs_weight(float r2, float K, float s2, float beta) {
-    return K * exp2f(-beta * log2f(s2 + r2));
+    const float x = fmaxf(s2 + r2, 1.17549435e-38f);
+    return K * __builtin_amdgcn_exp2f(-beta * __builtin_amdgcn_logf(x));
 }
 
 __host__ __device__ inline uint64_t mix64(uint64_t x) {
