@@ -342,6 +342,7 @@ struct FlockArgs {
     int stage;           // RK4 stage 0..3
     int mode;            // 0 = RHS, 1 = RK4 stage, 2 = Euler step
     int Rp;
+    int select;          // chunks this launch takes: 0 all, 1 exact-path only, 2 expansion only
 };
 
 __device__ inline void flock_emit(const FlockArgs &a, int64_t i, const float k[6]) {
@@ -391,6 +392,10 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
         lam = a.comm_off[c + 1] - (int)c0;
         fb = a.fb[c] != 0;
     }
+    // the stage is split in two launches when a basis is in use: chunks on the
+    // exact path (fallback communities, rows of no community) in the lean
+    // exact-only instantiation, the others in the basis one
+    if ((a.select == 1 && !fb) || (a.select == 2 && fb)) return;   // before any barrier
     const bool staged = ch.staged != 0 && c >= 0;
     float *sY = lds;                       // [6][lam]
     float *sF = lds + ((6 * lam + 3) & ~3);  // [lam][Rp], 16-byte aligned
@@ -956,6 +961,7 @@ struct FlockState {
     FlockChunk *chunks = nullptr;
     int nchunks = 0;
     size_t lds_bytes = 0;
+    size_t lds_exact = 0;   // LDS of the exact-path launch (state planes only)
     // state and E1
     float *Y[3] = {nullptr, nullptr, nullptr};
     float *acc = nullptr;
@@ -1155,12 +1161,20 @@ cia_status run_observables(cia_plan *p, const float *Ys, bool judge, hipStream_t
     return CIA_OK;
 }
 
-cia_status launch_stage(cia_plan *p, const FlockArgs &a, hipStream_t s) {
+cia_status launch_stage(cia_plan *p, const FlockArgs &a0, hipStream_t s) {
     FlockState *f = p->flock;
     CIA_TRY(timing_begin(p, s, KK_STAGE));
     if (p->method == CIA_METHOD_DIRECT) {
-        flock_direct_kernel<<<grid_for(p->n, 4), 256, 0, s>>>(a);
+        flock_direct_kernel<<<grid_for(p->n, 4), 256, 0, s>>>(a0);
     } else if (f->nchunks > 0) {
+        FlockArgs a = a0;
+        if (f->basis != CIA_BASIS_EXACT) {
+            // exact-path chunks first, in the exact-only instantiation (fewer
+            // registers, only the state planes staged)
+            a.select = 1;
+            flock_stage_kernel<0><<<f->nchunks, FBLOCK, f->lds_exact, s>>>(a);
+            a.select = 2;
+        }
         const size_t lds = f->lds_bytes;
         switch (f->Rp) {
             case 16: flock_stage_kernel<16><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
@@ -1418,32 +1432,40 @@ cia_status flock_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     CIA_HIP(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
     const size_t cap = std::min(STAGE_LDS_CAP, (size_t)dev_lds);
     std::vector<FlockChunk> ch;
-    size_t lds = 0;
+    size_t lds = 0, lds_ex = 0;
     for (int32_t q = 0; q < p1.ncomm; q++) {
         const int32_t c0 = p1.comm_off[q], lam = p1.comm_off[q + 1] - c0;
-        const size_t need = ((((size_t)6 * lam + 3) & ~(size_t)3) +
-                             (size_t)lam * (f->basis == CIA_BASIS_EXACT ? 0 : f->Rp)) * sizeof(float);
+        const size_t planes = (((size_t)6 * lam + 3) & ~(size_t)3) * sizeof(float);
+        const size_t need = planes + (size_t)lam * (f->basis == CIA_BASIS_EXACT ? 0 : f->Rp) * sizeof(float);
         const int staged = need <= cap ? 1 : 0;
-        if (staged) lds = std::max(lds, need);
+        if (staged) {
+            lds = std::max(lds, need);
+            lds_ex = std::max(lds_ex, planes);
+        }
         for (int32_t r = 0; r < lam; r += CHUNK_ROWS) ch.push_back(FlockChunk{c0 + r, std::min(CHUNK_ROWS, lam - r), q, staged});
     }
     for (int64_t r = f->nassigned; r < n; r += CHUNK_ROWS)
         ch.push_back(FlockChunk{(int32_t)r, (int32_t)std::min<int64_t>(CHUNK_ROWS, n - r), -1, 0});
     f->nchunks = (int)ch.size();
     f->lds_bytes = lds;
+    f->lds_exact = lds_ex;
     if (!ch.empty()) CIA_TRY(dupload(p, &f->chunks, ch.data(), ch.size()));
-    if (lds > 64 * 1024) {
+    // the limit is raised to the staging cap (not to this plan's need), so
+    // plans of other sizes never lower it for one another
+    if (lds > 64 * 1024 || lds_ex > 64 * 1024) {
         hipError_t e = hipSuccess;
         switch (f->Rp) {
-            case 16: e = hipFuncSetAttribute((const void *)flock_stage_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
-            case 28: e = hipFuncSetAttribute((const void *)flock_stage_kernel<28>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
-            case 32: e = hipFuncSetAttribute((const void *)flock_stage_kernel<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
-            case 48: e = hipFuncSetAttribute((const void *)flock_stage_kernel<48>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
-            default: e = hipFuncSetAttribute((const void *)flock_stage_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+            case 16: e = hipFuncSetAttribute((const void *)flock_stage_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap); break;
+            case 28: e = hipFuncSetAttribute((const void *)flock_stage_kernel<28>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap); break;
+            case 32: e = hipFuncSetAttribute((const void *)flock_stage_kernel<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap); break;
+            case 48: e = hipFuncSetAttribute((const void *)flock_stage_kernel<48>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap); break;
+            default: break;
         }
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)flock_stage_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            return set_error(CIA_EHIP, "cannot raise the LDS limit of the flock stage kernel to %zu bytes", lds);
+            return set_error(CIA_EHIP, "cannot raise the LDS limit of the flock stage kernel to %zu bytes", cap);
         }
     }
     info.nunits = f->nchunks;
