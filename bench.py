@@ -701,12 +701,10 @@ def bench_structured(args, cia, W, torch, np):
         plan = make(n, kind, k, method)
         info = plan.info()
         th0 = rng.uniform(0, 2 * np.pi, n).astype(np.float32)
-        th = torch.as_tensor(th0, device="cuda")
-        plan.integrate(th, 0.01, 2)
-        plan.set_timing(1)
-        plan.timing(reset=True)
-        ms = timed(torch, lambda s: plan.integrate(th, 0.01, steps, stream=s))
-        t = plan.timing(reset=True)
+        # median of args.reps calls; HIP events around one launch in 17 of
+        # each kind (stage, scan), inside the timed region
+        ms, t, _, _ = time_integrate(plan, torch, th0, 0.01, steps, 2, with_r=False, timing_every=17,
+                                     reps=args.reps)
         stage_us = 1e3 * t.stage_ms / max(t.stage_launches, 1)
         res = {"n": n, "kind": kind, "k": k, "method": "cia" if method == 0 else "direct", "steps": steps,
                "ms_per_step": ms / steps, "value": n * 4 * steps / (ms / 1e3), "stage_us": round(stage_us, 2),

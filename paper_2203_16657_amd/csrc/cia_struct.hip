@@ -22,6 +22,7 @@
 //
 // The direct variants sum h over every coupled pair (O(N^2) for rank one,
 // O(N k) for the ring) and share the stage update.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -35,8 +36,9 @@ namespace {
 constexpr int SB = 256;            // threads per stage block
 constexpr int SNPT = 4;            // consecutive nodes per thread (the vector helpers take 4)
 constexpr int STILE = SB * SNPT;   // nodes per block
+static_assert(STILE == 1 << 10, "ring_windows shifts by 10 for / STILE");
 constexpr int SPMAX = 8;           // harmonics
-constexpr int SCAN_T = 256;        // threads of the scan launch
+constexpr int SCAN_CH = 256;       // most chunks of the tile-sum scan
 
 enum SKind { SK_RANK1 = 0, SK_RING = 1, SK_RANK1_DIRECT = 2, SK_RING_DIRECT = 3 };
 enum SMode { SM_PREP = 0, SM_RHS = 1, SM_RK4 = 2, SM_EULER = 3 };
@@ -81,6 +83,49 @@ __device__ __forceinline__ double wrap_phase<double>(double t) {
 }
 
 __device__ __forceinline__ double2 d2add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Wave-level sums and scans of doubles by DPP lane moves (ALU-side, no LDS
+// round trip); a double moves as its two 32-bit halves, and lanes without a
+// source, or in rows the row mask leaves out, read 0.  Every lane of the
+// wavefront must be active where these are called.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// Inclusive scan over the 64 lanes: shifts by 1, 2, 4 and 8 within each row
+// of 16 lanes, then the last lane of rows 0 and 2 added into rows 1 and 3,
+// then lane 31 into rows 2 and 3.  The order of the additions is fixed.
+__device__ __forceinline__ double wave_incl_scan(double x) {
+    x += dpp_d<0x111, 0xf>(x);   // row_shr:1
+    x += dpp_d<0x112, 0xf>(x);   // row_shr:2
+    x += dpp_d<0x114, 0xf>(x);   // row_shr:4
+    x += dpp_d<0x118, 0xf>(x);   // row_shr:8
+    x += dpp_d<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp_d<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+__device__ __forceinline__ double2 wave_incl_scan(double2 v) {
+    return make_double2(wave_incl_scan(v.x), wave_incl_scan(v.y));
+}
+// the value one lane down the wave (lane 0 reads 0): inclusive -> exclusive
+__device__ __forceinline__ double2 wave_shr1(double2 v) {
+    return make_double2(dpp_d<0x138, 0xf>(v.x), dpp_d<0x138, 0xf>(v.y));   // wave_shr:1
+}
+// lane 63's value, in every lane
+__device__ __forceinline__ double lane63(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// wave sum, identical in every lane
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+    const double2 s = wave_incl_scan(v);
+    return make_double2(lane63(s.x), lane63(s.y));
+}
 
 // Four consecutive entries from j0 (a multiple of 4, in a library-owned
 // allocation, so full groups are aligned vector accesses); entries at or
@@ -149,10 +194,7 @@ __device__ __forceinline__ void store4z(zc<R> *p, int64_t j0, int64_t n, const z
 // Block sum of one double2 per thread (fixed order), broadcast to all threads.
 template <int NT>
 __device__ __forceinline__ double2 block_sum(double2 v, double2 *sh) {
-    for (int o = 32; o > 0; o >>= 1) {
-        v.x += __shfl_xor(v.x, o);
-        v.y += __shfl_xor(v.y, o);
-    }
+    v = wave_sum(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) sh[wid] = v;
@@ -162,38 +204,77 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2 *sh) {
     return r;
 }
 
-// Exclusive scan of one double2 per thread in thread order (fixed order);
-// *total receives the block total.
-template <int NT>
-__device__ __forceinline__ double2 block_excl_scan(double2 v, double2 *sh, double2 *total) {
+// Batched block sums and scans, one barrier pair for all: sv[m] (m < MS)
+// become their block sums, xv[m] (m < MX) their exclusive scans in thread
+// order, with the block totals in xt[m].  The order of every sum is fixed.
+// sh holds NT / 64 * (MS + MX) double2.
+template <int NT, int MS, int MX>
+__device__ __forceinline__ void block_sums_scans(double2 (&sv)[MS], double2 (&xv)[MX], double2 (&xt)[MX],
+                                                 double2 *sh) {
+    constexpr int M = MS + MX;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    double2 inc = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        double2 u;
-        u.x = __shfl_up(inc.x, o);
-        u.y = __shfl_up(inc.y, o);
-        if (lane >= o) inc = d2add(inc, u);
+#pragma unroll
+    for (int m = 0; m < MS; m++) sv[m] = wave_sum(sv[m]);
+    double2 ex[MX], wt[MX];
+#pragma unroll
+    for (int m = 0; m < MX; m++) {
+        const double2 inc = wave_incl_scan(xv[m]);
+        ex[m] = wave_shr1(inc);
+        wt[m] = make_double2(lane63(inc.x), lane63(inc.y));
     }
-    double2 ex;
-    ex.x = __shfl_up(inc.x, 1);
-    ex.y = __shfl_up(inc.y, 1);
-    if (lane == 0) ex = make_double2(0.0, 0.0);
     __syncthreads();
-    if (lane == 63) sh[wid] = inc;
-    __syncthreads();
-    double2 off = make_double2(0.0, 0.0), tot = make_double2(0.0, 0.0);
-    for (int w = 0; w < NT / 64; w++) {
-        if (w < wid) off = d2add(off, sh[w]);
-        tot = d2add(tot, sh[w]);
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < MS; m++) sh[wid * M + m] = sv[m];
+#pragma unroll
+        for (int m = 0; m < MX; m++) sh[wid * M + MS + m] = wt[m];
     }
-    *total = tot;
-    return d2add(off, ex);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MS; m++) {
+        double2 r = sh[m];
+        for (int w = 1; w < NT / 64; w++) r = d2add(r, sh[w * M + m]);
+        sv[m] = r;
+    }
+#pragma unroll
+    for (int m = 0; m < MX; m++) {
+        double2 off = make_double2(0.0, 0.0), tot = make_double2(0.0, 0.0);
+        for (int w = 0; w < NT / 64; w++) {
+            const double2 q = sh[w * M + MS + m];
+            if (w < wid) off = d2add(off, q);
+            tot = d2add(tot, q);
+        }
+        xt[m] = tot;
+        xv[m] = d2add(off, ex[m]);
+    }
+}
+
+// Block sums of M double2 per thread in one barrier pair (fixed order);
+// sh holds NT / 64 * M double2.
+template <int NT, int M>
+__device__ __forceinline__ void block_sums(double2 (&v)[M], double2 *sh) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < M; m++) v[m] = wave_sum(v[m]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < M; m++) sh[wid * M + m] = v[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        double2 r = sh[m];
+        for (int w = 1; w < NT / 64; w++) r = d2add(r, sh[w * M + m]);
+        v[m] = r;
+    }
 }
 
 template <typename R>
 struct SArgs {
     int64_t n, kw;                      // nodes; ring half-width
     int32_t ntiles, mode, stage;
+    int32_t tcols;                      // ring: the window shift in tiles, at least 1
     R dt, Kn, d0w;                      // d0w: dcos[0] times the row weight (sum beta, or 2 kw + 1)
     R dsin[SPMAX + 1], dcos[SPMAX + 1];
     const R *omega, *alpha, *beta;      // [n]; alpha, beta for rank one only
@@ -208,78 +289,119 @@ struct SArgs {
 
 // Ring window sums for this thread's nodes j = a0 + SNPT t + e, harmonic by
 // harmonic, added into s as (dsin_k Im + dcos_k Re)(F_{j,k} conj(z_j^k)).
+// Every z the block needs (the start tile of each shifted window up to the
+// window start, and the two windows) is loaded at once; per harmonic, the
+// two partial-tile sums and the two window scans share one barrier pair.
 template <typename R, int P>
 __device__ __forceinline__ void ring_windows(const SArgs<R> &a, int64_t a0, const zc<R> (&zj)[SNPT], R (&s)[SNPT],
                                              double2 *sh) {
     const int t = threadIdx.x;
     const int64_t n = a.n, kw = a.kw;
     const double2 *off = a.tot + (P + 1);
-    zc<R> zjk[SNPT];
+    int64_t q[2], tl[2];
+    zc<R> zt[2][SNPT], zw[2][SNPT];
+    bool in_t[2][SNPT];
 #pragma unroll
-    for (int e = 0; e < SNPT; e++) zjk[e] = zj[e];
+    for (int r = 0; r < 2; r++) {
+        // 0 <= a0 < n and 0 <= kw < n / 2, so the window start st wraps at
+        // most once: q = floor(st / n) is -1 or 0 (r = 0), 0 or 1 (r = 1)
+        const int64_t st = r == 0 ? a0 - kw : a0 + kw + 1;
+        q[r] = st < 0 ? -1 : (st >= n ? 1 : 0);
+        const int64_t sp = st - q[r] * n;   // in [0, n)
+        tl[r] = sp >> 10;                   // sp / STILE
+#pragma unroll
+        for (int u = 0; u < SNPT; u++) {
+            const int64_t i = tl[r] * STILE + t + (int64_t)u * SB;
+            in_t[r][u] = i < sp;
+            zt[r][u] = i < sp ? a.z_in[i] : zc<R>{(R)0, (R)0};
+        }
+        const int64_t x0 = sp + (int64_t)SNPT * t;   // reduced mod n below
+#pragma unroll
+        for (int e = 0; e < SNPT; e++) {
+            int64_t x = x0 + e;
+            while (x >= n) x -= n;
+            zw[r][e] = a.z_in[x];
+        }
+    }
+#pragma unroll 1
     for (int k = 1; k <= P; k++) {
+        // per window: the start tile's sum of z^k up to the window start
+        // (block sum) and this thread's window sum (block scan); powers by
+        // the recurrence of zpow
+        double2 pt[2], ts[2], btot[2];
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            double2 v = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < SNPT; u++)
+                if (in_t[r][u]) {
+                    const zc<R> z = zpow(zt[r][u], k);
+                    v.x += (double)z.x;
+                    v.y += (double)z.y;
+                }
+#pragma unroll
+            for (int e = 0; e < SNPT; e++) {
+                const zc<R> z = zpow(zw[r][e], k);
+                w.x += (double)z.x;
+                w.y += (double)z.y;
+            }
+            pt[r] = v;
+            ts[r] = w;
+        }
+        block_sums_scans<SB, 2, 2>(pt, ts, btot, sh);
         const double2 Tot = off[(int64_t)a.ntiles * P + (k - 1)];
         double2 pc[2][SNPT];
 #pragma unroll
         for (int r = 0; r < 2; r++) {
-            const int64_t st = r == 0 ? a0 - kw : a0 + kw + 1;
-            int64_t q = st / n;
-            if (st - q * n < 0) q -= 1;
-            const int64_t sp = st - q * n;   // in [0, n)
-            const int64_t tl = sp / STILE;
-            // sum of z^k over the start tile up to sp (at most SNPT per thread,
-            // loads issued together)
-            double2 pt = make_double2(0.0, 0.0);
-            {
-                zc<R> zt[SNPT];
-#pragma unroll
-                for (int u = 0; u < SNPT; u++) {
-                    const int64_t i = tl * STILE + t + (int64_t)u * SB;
-                    zt[u] = i < sp ? a.z_in[i] : zc<R>{(R)0, (R)0};
-                }
-#pragma unroll
-                for (int u = 0; u < SNPT; u++) {
-                    if (tl * STILE + t + (int64_t)u * SB < sp) {
-                        const zc<R> z = zpow(zt[u], k);
-                        pt.x += (double)z.x;
-                        pt.y += (double)z.y;
-                    }
-                }
-            }
-            pt = block_sum<SB>(pt, sh);
-            const double2 o = off[tl * P + (k - 1)];
-            const double2 base = make_double2((double)q * Tot.x + o.x + pt.x, (double)q * Tot.y + o.y + pt.y);
-            // this thread's positions st + SNPT t + e, then a block scan
-            zc<R> v[SNPT];
-            double2 ts = make_double2(0.0, 0.0);
-            int64_t x0 = (st + (int64_t)SNPT * t) % n;   // one division per thread
-            if (x0 < 0) x0 += n;
-#pragma unroll
-            for (int e = 0; e < SNPT; e++) {
-                int64_t x = x0 + e;
-                while (x >= n) x -= n;
-                v[e] = zpow(a.z_in[x], k);
-                ts.x += (double)v[e].x;
-                ts.y += (double)v[e].y;
-            }
-            double2 btot;
-            double2 run = d2add(base, block_excl_scan<SB>(ts, sh, &btot));
+            const double2 o = off[tl[r] * P + (k - 1)];
+            const double2 base =
+                make_double2((double)q[r] * Tot.x + o.x + pt[r].x, (double)q[r] * Tot.y + o.y + pt[r].y);
+            double2 run = d2add(base, ts[r]);
 #pragma unroll
             for (int e = 0; e < SNPT; e++) {
                 pc[r][e] = run;
-                run.x += (double)v[e].x;
-                run.y += (double)v[e].y;
+                const zc<R> z = zpow(zw[r][e], k);
+                run.x += (double)z.x;
+                run.y += (double)z.y;
             }
         }
 #pragma unroll
         for (int e = 0; e < SNPT; e++) {
             const R fx = (R)(pc[1][e].x - pc[0][e].x), fy = (R)(pc[1][e].y - pc[0][e].y);
             // F conj(z_j^k)
-            const R wr = fx * zjk[e].x + fy * zjk[e].y, wi = fy * zjk[e].x - fx * zjk[e].y;
+            const zc<R> zjk = zpow(zj[e], k);
+            const R wr = fx * zjk.x + fy * zjk.y, wi = fy * zjk.x - fx * zjk.y;
             s[e] += a.dsin[k] * wi + a.dcos[k] * wr;
-            zjk[e] = zmul(zjk[e], zj[e]);
         }
     }
+}
+
+// Tile of block i for the ring.  Workgroups are dealt to the 8 XCDs in turn
+// (block i runs on XCD i mod 8, in increasing i), so XCD x is given a
+// contiguous run of an order that lists tile T = q D + c (D = tcols) column
+// by column: c outer, q inner (tcols = 1: the natural order, so each XCD
+// holds a contiguous run of tiles).  A block of tile T reads z from its own
+// tile and from T - D - 1, T - D, T + D and T + D + 1, all in columns
+// c - 1 .. c + 1, so the five readers of a tile run on one XCD within about
+// 2 N / (D STILE) blocks of each other and share its lines in that XCD's L2
+// (the plain block order puts them on different XCDs, each fetching the
+// tile on its own).
+__device__ __forceinline__ int64_t ring_tile(uint32_t i, uint32_t nb, uint32_t D) {
+    constexpr uint32_t X = 8;
+    const uint32_t x = i % X, j = i / X;
+    const uint32_t base = nb / X, extra = nb % X;
+    const uint32_t pos = x * base + (x < extra ? x : extra) + j;
+    const uint32_t Q = nb / D, rem = nb % D;
+    uint32_t c, q;
+    if (pos < rem * (Q + 1)) {
+        c = pos / (Q + 1);
+        q = pos - c * (Q + 1);
+    } else {
+        const uint32_t p2 = pos - rem * (Q + 1);
+        c = rem + p2 / Q;
+        q = p2 - (c - rem) * Q;
+    }
+    return (int64_t)q * D + c;
 }
 
 // h(theta_l - theta_j) from z_l and z_j (powers by recurrence)
@@ -300,12 +422,14 @@ __device__ __forceinline__ R h_pair(const SArgs<R> &a, zc<R> zl, zc<R> zj) {
 template <typename R, int P, int KIND>
 __global__ __launch_bounds__(SB) void struct_stage_kernel(SArgs<R> a) {
     constexpr bool RANK1 = KIND == SK_RANK1 || KIND == SK_RANK1_DIRECT;
-    __shared__ double2 sh[SB / 64];
+    __shared__ double2 sh[SB / 64 * (4 > P + 1 ? 4 : P + 1)];   // block_sums_scans<SB, 2, 2>, block_sums<SB, P + 1>
     __shared__ zc<R> zst[SB];
     __shared__ R bst[SB];
     const int t = threadIdx.x;
     const int64_t n = a.n;
-    const int64_t a0 = (int64_t)blockIdx.x * STILE;
+    const int64_t tile = KIND == SK_RING ? ring_tile(blockIdx.x, (uint32_t)a.ntiles, (uint32_t)a.tcols)
+                                         : (int64_t)blockIdx.x;
+    const int64_t a0 = tile * STILE;
     const int64_t j0 = a0 + (int64_t)SNPT * t;
     const int mode = a.mode;
 
@@ -444,74 +568,114 @@ __global__ __launch_bounds__(SB) void struct_stage_kernel(SArgs<R> a) {
     store4z(a.z_out, j0, n, zn);
     // tile sums: slot k-1 of w z^k (k = 1..P; the E1 variants), slot P of z
     if constexpr (KIND == SK_RANK1 || KIND == SK_RING) {
+        double2 v[P + 1];
         zc<R> zk[SNPT];
 #pragma unroll
         for (int e = 0; e < SNPT; e++) zk[e] = zn[e];
+#pragma unroll
         for (int k = 1; k <= P; k++) {
-            double2 v = make_double2(0.0, 0.0);
+            v[k - 1] = make_double2(0.0, 0.0);
 #pragma unroll
             for (int e = 0; e < SNPT; e++) {
-                v.x += (double)(wt[e] * zk[e].x);
-                v.y += (double)(wt[e] * zk[e].y);
+                v[k - 1].x += (double)(wt[e] * zk[e].x);
+                v[k - 1].y += (double)(wt[e] * zk[e].y);
             }
-            v = block_sum<SB>(v, sh);
-            if (t == 0) a.part[(size_t)blockIdx.x * (P + 1) + (k - 1)] = v;
             if (k < P) {
 #pragma unroll
                 for (int e = 0; e < SNPT; e++) zk[e] = zmul(zk[e], zn[e]);
             }
         }
-    }
-    double2 v = make_double2(0.0, 0.0);
+        v[P] = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int e = 0; e < SNPT; e++) {
-        v.x += (double)zn[e].x;
-        v.y += (double)zn[e].y;
+        for (int e = 0; e < SNPT; e++) {
+            v[P].x += (double)zn[e].x;
+            v[P].y += (double)zn[e].y;
+        }
+        block_sums<SB, P + 1>(v, sh);
+        if (t == 0) {
+#pragma unroll
+            for (int m = 0; m <= P; m++) a.part[(size_t)tile * (P + 1) + m] = v[m];
+        }
+    } else {
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int e = 0; e < SNPT; e++) {
+            v.x += (double)zn[e].x;
+            v.y += (double)zn[e].y;
+        }
+        v = block_sum<SB>(v, sh);
+        if (t == 0) a.part[(size_t)tile * (P + 1) + P] = v;
     }
-    v = block_sum<SB>(v, sh);
-    if (t == 0) a.part[(size_t)blockIdx.x * (P + 1) + P] = v;
 }
 
 // Totals of the tile sums (every slot) and, for the ring, exclusive tile
-// offsets of slots 0..P-1; r_out (optional) = |total of slot P| / n.  One
-// block; a batch of SCAN_T * SCAN_R tiles gives every thread SCAN_R
-// consecutive tiles, all loaded at once (the loads are in flight together),
-// summed in order, then one block scan of the thread sums; the order is fixed.
-constexpr int SCAN_R = 16;
-__global__ __launch_bounds__(SCAN_T) void struct_scan_kernel(const double2 *part, int32_t ntiles, int P, int ring,
-                                                             double invN, double2 *tot, double *r_out) {
-    __shared__ double2 sh[SCAN_T / 64];
-    const int t = threadIdx.x;
-    double2 *off = tot + (P + 1);
+// offsets of slots 0..P-1, in two launches spread over the CUs (a single
+// block cannot pull the tile sums of a large network fast enough).  The
+// tiles form nch <= SCAN_CH chunks of ct consecutive tiles; one 64-lane
+// block per chunk.  The order of every sum is fixed.
+
+// Launch 1: chunk sums csum[c][sl] of every slot (lane-strided over the
+// chunk's tiles, then a wave sum).
+template <int P>
+__global__ __launch_bounds__(64) void struct_chunk_kernel(const double2 *part, int32_t ntiles, int32_t ct,
+                                                          double2 *csum) {
+    const int l = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * ct, t1 = t0 + ct < ntiles ? t0 + ct : ntiles;
+    double2 v[P + 1];
+#pragma unroll
+    for (int sl = 0; sl <= P; sl++) v[sl] = make_double2(0.0, 0.0);
+    for (int64_t T = t0 + l; T < t1; T += 64)
+#pragma unroll
+        for (int sl = 0; sl <= P; sl++) v[sl] = d2add(v[sl], part[T * (P + 1) + sl]);
+#pragma unroll
     for (int sl = 0; sl <= P; sl++) {
-        const bool scan = ring && sl < P;
-        double2 carry = make_double2(0.0, 0.0);
-        for (int64_t b0 = 0; b0 < ntiles; b0 += (int64_t)SCAN_T * SCAN_R) {
-            const int64_t i0 = b0 + (int64_t)t * SCAN_R;
-            double2 v[SCAN_R];
+        v[sl] = wave_sum(v[sl]);
+        if (l == 0) csum[(int64_t)blockIdx.x * (P + 1) + sl] = v[sl];
+    }
+}
+
+// Launch 2: for the ring, block c adds the chunk sums before it (its chunk
+// offset) and writes the exclusive offsets of its tiles (wave scans of 64
+// tiles at a time); the last chunk's block also writes the totals (tot, the
+// ring's final offset slot) and r_out = |total of slot P| / n.  Without the
+// ring one block does only the last part.
+template <int P>
+__global__ __launch_bounds__(64) void struct_offsets_kernel(const double2 *part, const double2 *csum, int32_t ntiles,
+                                                            int32_t ct, int32_t nch, int ring, double invN,
+                                                            double2 *tot, double *r_out) {
+    const int l = threadIdx.x;
+    const int c = ring ? (int)blockIdx.x : nch - 1;
+    double2 o[P + 1];
 #pragma unroll
-            for (int r = 0; r < SCAN_R; r++)
-                v[r] = i0 + r < ntiles ? part[(i0 + r) * (P + 1) + sl] : make_double2(0.0, 0.0);
-            double2 ts = v[0];
+    for (int sl = 0; sl <= P; sl++) o[sl] = make_double2(0.0, 0.0);
+    for (int c2 = l; c2 < c; c2 += 64)
 #pragma unroll
-            for (int r = 1; r < SCAN_R; r++) ts = d2add(ts, v[r]);
-            if (!scan) {
-                carry = d2add(carry, block_sum<SCAN_T>(ts, sh));
-            } else {
-                double2 bt;
-                double2 run = d2add(carry, block_excl_scan<SCAN_T>(ts, sh, &bt));
+        for (int sl = 0; sl <= P; sl++) o[sl] = d2add(o[sl], csum[(int64_t)c2 * (P + 1) + sl]);
 #pragma unroll
-                for (int r = 0; r < SCAN_R; r++) {
-                    if (i0 + r < ntiles) off[(i0 + r) * P + sl] = run;
-                    run = d2add(run, v[r]);
-                }
-                carry = d2add(carry, bt);
+    for (int sl = 0; sl <= P; sl++) o[sl] = wave_sum(o[sl]);
+    double2 *off = tot + (P + 1);
+    if (ring) {
+        const int64_t t0 = (int64_t)c * ct, t1 = t0 + ct < ntiles ? t0 + ct : ntiles;
+        double2 run[P];
+#pragma unroll
+        for (int sl = 0; sl < P; sl++) run[sl] = o[sl];
+        for (int64_t b = t0; b < t1; b += 64) {
+            const int64_t T = b + l;
+#pragma unroll
+            for (int sl = 0; sl < P; sl++) {
+                const double2 inc = wave_incl_scan(T < t1 ? part[T * (P + 1) + sl] : make_double2(0.0, 0.0));
+                if (T < t1) off[T * P + sl] = d2add(run[sl], wave_shr1(inc));
+                run[sl] = d2add(run[sl], make_double2(lane63(inc.x), lane63(inc.y)));
             }
         }
-        if (t == 0) {
-            tot[sl] = carry;
-            if (scan) off[(int64_t)ntiles * P + sl] = carry;
-            if (sl == P && r_out) r_out[0] = sqrt(carry.x * carry.x + carry.y * carry.y) * invN;
+    }
+    if (c == nch - 1 && l == 0) {
+#pragma unroll
+        for (int sl = 0; sl <= P; sl++) {
+            const double2 T = d2add(o[sl], csum[(int64_t)c * (P + 1) + sl]);
+            tot[sl] = T;
+            if (ring && sl < P) off[(int64_t)ntiles * P + sl] = T;
+            if (sl == P && r_out) r_out[0] = sqrt(T.x * T.x + T.y * T.y) * invN;
         }
     }
 }
@@ -530,10 +694,12 @@ struct StructState {
     double dsin[SPMAX + 1] = {0}, dcos[SPMAX + 1] = {0};
     int64_t kw = 0;
     int32_t ntiles = 0;
+    int32_t ct = 0, nch = 0;            // tiles per scan chunk, chunks (<= SCAN_CH)
     void *omega = nullptr, *alpha = nullptr, *beta = nullptr;
     void *theta_n = nullptr, *acc = nullptr, *z[2] = {nullptr, nullptr};
     double2 *part[2] = {nullptr, nullptr};
     double2 *tot = nullptr;
+    double2 *csum = nullptr;            // [nch][P+1] chunk sums
     double *r_dev = nullptr;
     int64_t r_cap = 0;
 };
@@ -635,6 +801,9 @@ cia_status struct_build(cia_plan *p, const cia_graph *g, const int32_t *labels, 
         CIA_HIP(hipMemset(s->part[b], 0, sizeof(double2) * (size_t)ntiles * (s->P + 1)));
     }
     CIA_TRY(dalloc(p, &s->tot, (size_t)(s->P + 1) + (size_t)(ntiles + 1) * s->P));
+    s->ct = (int32_t)((ntiles + SCAN_CH - 1) / SCAN_CH);
+    s->nch = (int32_t)((ntiles + s->ct - 1) / s->ct);
+    CIA_TRY(dalloc(p, &s->csum, (size_t)s->nch * (s->P + 1)));
 
     cia_plan_info &inf = p->info;
     inf.n = n;
@@ -688,10 +857,26 @@ static cia_status launch_stage(cia_plan *p, const StructState *s, const SArgs<R>
 }
 
 // totals / offsets of the tile sums in part[b]; r_out optional
+template <int P>
+static void launch_scan_p(const StructState *s, int b, double invN, double *r_out, hipStream_t st) {
+    const int ring = s->kind == SK_RING ? 1 : 0;
+    hipLaunchKernelGGL(struct_chunk_kernel<P>, dim3(s->nch), dim3(64), 0, st, s->part[b], s->ntiles, s->ct, s->csum);
+    hipLaunchKernelGGL(struct_offsets_kernel<P>, dim3(ring ? s->nch : 1), dim3(64), 0, st, s->part[b], s->csum,
+                       s->ntiles, s->ct, s->nch, ring, invN, s->tot, r_out);
+}
 static cia_status launch_scan(cia_plan *p, const StructState *s, int b, double *r_out, hipStream_t st) {
     CIA_TRY(timing_begin(p, st, KK_AUX));
-    hipLaunchKernelGGL(struct_scan_kernel, dim3(1), dim3(SCAN_T), 0, st, s->part[b], s->ntiles, s->P,
-                       s->kind == SK_RING ? 1 : 0, 1.0 / (double)p->n, s->tot, r_out);
+    const double invN = 1.0 / (double)p->n;
+    switch (s->P) {
+        case 1: launch_scan_p<1>(s, b, invN, r_out, st); break;
+        case 2: launch_scan_p<2>(s, b, invN, r_out, st); break;
+        case 3: launch_scan_p<3>(s, b, invN, r_out, st); break;
+        case 4: launch_scan_p<4>(s, b, invN, r_out, st); break;
+        case 5: launch_scan_p<5>(s, b, invN, r_out, st); break;
+        case 6: launch_scan_p<6>(s, b, invN, r_out, st); break;
+        case 7: launch_scan_p<7>(s, b, invN, r_out, st); break;
+        default: launch_scan_p<8>(s, b, invN, r_out, st); break;
+    }
     CIA_HIP(hipGetLastError());
     return timing_end(p, st);
 }
@@ -703,6 +888,10 @@ static SArgs<R> base_args(cia_plan *p, const StructState *s) {
     a.n = p->n;
     a.kw = s->kw;
     a.ntiles = s->ntiles;
+    // column order when the window shift is large against one XCD's share of
+    // the tiles; otherwise tcols = 1, each XCD a contiguous run of tiles
+    const int64_t D = std::max<int64_t>(1, s->kw / STILE);
+    a.tcols = 4 * (D + 1) <= s->ntiles / 8 ? 1 : (int32_t)D;
     a.Kn = (R)s->Kn;
     a.d0w = (R)s->d0w;
     for (int k = 0; k <= SPMAX; k++) {
