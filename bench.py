@@ -37,7 +37,7 @@ def profiled_traffic(workload):
     kernel sources are the ones profiled."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "phase_stage_kernel_kuramoto_n1e6.md")
-    srcs = [os.path.join(ROOT, "paper_2203_16657_amd", "csrc", f) for f in ("cia_phase.hip", "plan.h", "fastmath.h")]
+    srcs = [os.path.join(ROOT, "paper_2203_16657_amd", "csrc", f) for f in ("cia_phase.hip", "plan.h", "fastmath.h", "wave.h")]
     try:
         text = open(prof).read()
         h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()

@@ -43,6 +43,7 @@
 
 #include "fastmath.h"
 #include "plan.h"
+#include "wave.h"
 
 namespace cia {
 
@@ -116,6 +117,16 @@ __device__ __forceinline__ void tsum_pair(float &s, float &c, float s2, float c2
     float e = (s - (t - bp)) + (s2 - bp);
     s = t;
     c = c + c2 + e;
+}
+// TwoSum-compensated wavefront sum of (s, c) pairs over the DPP lane moves
+// of wave_incl_scan (a lane without a source adds (0, 0), which changes
+// nothing); lane 63's pair, the total, ends in every lane.
+__device__ __forceinline__ void wave_tsum(float &s, float &c) {
+#define CIA_STEP(C, M) tsum_pair(s, c, dpp_f<C, M>(s), dpp_f<C, M>(c));
+    CIA_WAVE_SCAN_STEPS(CIA_STEP)
+#undef CIA_STEP
+    s = lane63(s);
+    c = lane63(c);
 }
 
 template <typename R>
@@ -210,7 +221,7 @@ __device__ __forceinline__ void acc_z(cx<R> (&T)[P], cx<R> z, R sign) {
 // z of the staged community at a byte offset (local index * sizeof(z)):
 // staged local indices are stored pre-scaled, so the address needs no shift
 // r(t) = |(1/N) sum z| from the unit partials: one wavefront, lane-strided
-// FP64 sums then an xor-butterfly, so the order is fixed.  Used by the
+// FP64 sums then a DPP wave sum, so the order is fixed.  Used by the
 // stage kernel (folded into the next launch) and by order_reduce_kernel.
 __device__ __forceinline__ void reduce_r_wave(const double2 *part, int n, double invN, double *out) {
     const int lane = threadIdx.x & 63;
@@ -221,10 +232,8 @@ __device__ __forceinline__ void reduce_r_wave(const double2 *part, int n, double
         x += v.x;
         y += v.y;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        x += __shfl_xor(x, o);
-        y += __shfl_xor(y, o);
-    }
+    x = wave_sum(x);
+    y = wave_sum(y);
     if (lane == 0) *out = sqrt(x * x + y * y) * invN;
 }
 
@@ -502,10 +511,8 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                     sx += q.x;
                     sy += q.y;
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    sx += __shfl_xor(sx, o);
-                    sy += __shfl_xor(sy, o);
-                }
+                sx = wave_sum(sx);
+                sy = wave_sum(sy);
                 if (lane == 0) qsh[k] = make_double2(sx, sy);
             }
         }
@@ -796,10 +803,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
 #pragma unroll
             for (int k = 0; k < 2 * P; k++) {
                 float s = ps[k], cc = pc[k];
-                for (int o = 32; o > 0; o >>= 1) {
-                    float s2 = __shfl_xor(s, o), c2 = __shfl_xor(cc, o);
-                    tsum_pair(s, cc, s2, c2);
-                }
+                wave_tsum(s, cc);
                 if (lane == 0) {
                     red_s[wid][k] = s;
                     red_c[wid][k] = cc;
@@ -808,17 +812,14 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
         } else {
 #pragma unroll
             for (int k = 0; k < 2 * P; k++) {
-                double s = pd[k];
-                for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+                const double s = wave_sum(pd[k]);
                 if (lane == 0) red_d[wid][k] = s;
             }
         }
     }
     if (a.want_r) {
-        for (int o = 32; o > 0; o >>= 1) {
-            rx += __shfl_xor(rx, o);
-            ry += __shfl_xor(ry, o);
-        }
+        rx = wave_sum(rx);
+        ry = wave_sum(ry);
         if (lane == 0) red_r[wid] = make_double2(rx, ry);
     }
     __syncthreads();
@@ -991,11 +992,7 @@ __global__ __launch_bounds__(res_block<R>()) void resident_integrate_kernel(ResA
                 pk[P] = make_double2((double)z.x, (double)z.y);
             }
 #pragma unroll
-            for (int k = 0; k <= P; k++)
-                for (int o = 32; o > 0; o >>= 1) {
-                    pk[k].x += __shfl_xor(pk[k].x, o);
-                    pk[k].y += __shfl_xor(pk[k].y, o);
-                }
+            for (int k = 0; k <= P; k++) pk[k] = wave_sum(pk[k]);
             if (lane == 0)
 #pragma unroll
                 for (int k = 0; k <= P; k++) part[(size_t)sl * (P + 1) + k] = pk[k];
@@ -1239,10 +1236,8 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
                     sx += q.x;
                     sy += q.y;
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    sx += __shfl_xor(sx, o);
-                    sy += __shfl_xor(sy, o);
-                }
+                sx = wave_sum(sx);
+                sy = wave_sum(sy);
                 if (lane == 0) {
                     qsh[0][k] = sx;
                     if (D == 2) qsh[D - 1][k] = sy;
@@ -1533,8 +1528,7 @@ __global__ __launch_bounds__(BLOCK) void poly_stage_kernel(PhaseArgs<R> a) {
     for (int d = 0; d < D; d++)
 #pragma unroll
         for (int k = 0; k < P; k++) {
-            double v = pd[d][k];
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            const double v = wave_sum(pd[d][k]);
             if (lane == 0) red[wid][d][k] = v;
         }
     __syncthreads();
@@ -1719,10 +1713,8 @@ __global__ __launch_bounds__(256) void tri_missing_kernel(const TriUnit *units, 
                 acc.y += p.y;
             }
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            acc.x += __shfl_xor(acc.x, o);
-            acc.y += __shfl_xor(acc.y, o);
-        }
+        acc.x = wave_sum(acc.x);
+        acc.y = wave_sum(acc.y);
         if (lane == 0) M[i] = acc;
     }
 }
@@ -1763,10 +1755,8 @@ __global__ __launch_bounds__(256) void triadic_present_kernel(const TriBlock *bl
                 E.y += p.y;
                 S = cx<R>{(R)0, (R)0};
             });
-        for (int o = 32; o > 0; o >>= 1) {
-            E.x += __shfl_xor(E.x, o);
-            E.y += __shfl_xor(E.y, o);
-        }
+        E.x = wave_sum(E.x);
+        E.y = wave_sum(E.y);
         if (lane == 0) out[i] = E;
     }
 }

@@ -28,6 +28,7 @@
 
 #include "fastmath.h"
 #include "plan.h"
+#include "wave.h"
 
 namespace cia {
 
@@ -83,49 +84,6 @@ __device__ __forceinline__ double wrap_phase<double>(double t) {
 }
 
 __device__ __forceinline__ double2 d2add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-
-// Wave-level sums and scans of doubles by DPP lane moves (ALU-side, no LDS
-// round trip); a double moves as its two 32-bit halves, and lanes without a
-// source, or in rows the row mask leaves out, read 0.  Every lane of the
-// wavefront must be active where these are called.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_d(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROW_MASK, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-// Inclusive scan over the 64 lanes: shifts by 1, 2, 4 and 8 within each row
-// of 16 lanes, then the last lane of rows 0 and 2 added into rows 1 and 3,
-// then lane 31 into rows 2 and 3.  The order of the additions is fixed.
-__device__ __forceinline__ double wave_incl_scan(double x) {
-    x += dpp_d<0x111, 0xf>(x);   // row_shr:1
-    x += dpp_d<0x112, 0xf>(x);   // row_shr:2
-    x += dpp_d<0x114, 0xf>(x);   // row_shr:4
-    x += dpp_d<0x118, 0xf>(x);   // row_shr:8
-    x += dpp_d<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-    x += dpp_d<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
-    return x;
-}
-__device__ __forceinline__ double2 wave_incl_scan(double2 v) {
-    return make_double2(wave_incl_scan(v.x), wave_incl_scan(v.y));
-}
-// the value one lane down the wave (lane 0 reads 0): inclusive -> exclusive
-__device__ __forceinline__ double2 wave_shr1(double2 v) {
-    return make_double2(dpp_d<0x138, 0xf>(v.x), dpp_d<0x138, 0xf>(v.y));   // wave_shr:1
-}
-// lane 63's value, in every lane
-__device__ __forceinline__ double lane63(double x) {
-    const long long b = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-// wave sum, identical in every lane
-__device__ __forceinline__ double2 wave_sum(double2 v) {
-    const double2 s = wave_incl_scan(v);
-    return make_double2(lane63(s.x), lane63(s.y));
-}
 
 // Four consecutive entries from j0 (a multiple of 4, in a library-owned
 // allocation, so full groups are aligned vector accesses); entries at or
