@@ -26,8 +26,12 @@
 //    step and switches failing communities to the exact fallback.
 //  * exact: every community uses the fallback: the all-pairs sum over the
 //    community minus S-neg, with the exact weight.
+#include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <type_traits>
 
 #include "fastmath.h"
 #include "plan.h"
@@ -40,6 +44,7 @@ constexpr int HID = 64;            // hidden width of the learned basis
 constexpr int TPR = 4;             // threads per row in the stage kernel
 constexpr int CHUNK_ROWS = 256;    // rows per chunk of the stage kernel
 constexpr int FBLOCK = CHUNK_ROWS * TPR;
+constexpr int EXACT_RT = 2;        // lanes per row of flock_exact_kernel
 constexpr int JUDGE_SAMPLES = 16;  // sampled members per community and step
 constexpr int TRAIN_PAIRS = 4096;  // pairs per optimiser step
 constexpr int TILE_PTS = 64;       // points per MFMA tile (32 pairs in training)
@@ -51,6 +56,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 struct FlockChunk {
     int32_t row0, rows, comm, staged;
+    int32_t sbase;   // flock_exact_kernel: first S-neg slice of the chunk, -1 if none
 };
 
 // --------------------------------------------------------------------------
@@ -342,7 +348,17 @@ struct FlockArgs {
     int stage;           // RK4 stage 0..3
     int mode;            // 0 = RHS, 1 = RK4 stage, 2 = Euler step
     int Rp;
-    int select;          // chunks this launch takes: 0 all, 1 exact-path only, 2 expansion only
+    int exact_lds;       // flock_exact_kernel: dynamic LDS bytes of the launch
+    // flock_exact_kernel: S-neg of staged chunks as slices of 64 / EXACT_RT
+    // rows (one wavefront), entry k of every row of a slice stored together
+    // (community-local indices; past a row's length, 0)
+    const uint16_t *sneg;
+    const int64_t *sneg_off;   // per slice: first entry
+    const int32_t *sneg_w;     // per slice: entries per row (the longest row's)
+    const uint8_t *srow;       // per row of a sliced chunk: the chunk row its thread slot takes
+                               // (rows by decreasing S-neg length, so a slice's rows are alike)
+    int plain;           // s2 >= the smallest normal float and s2^(-beta) finite: no clamp, and the
+                         // self pair adds exactly 0 (flock_exact_kernel)
 };
 
 __device__ inline void flock_emit(const FlockArgs &a, int64_t i, const float k[6]) {
@@ -372,11 +388,14 @@ __device__ inline void flock_emit(const FlockArgs &a, int64_t i, const float k[6
     }
 }
 
-// Four lanes per row (each takes every fourth partner, then the row's sums
-// are combined across the group); the block covers up to 256 rows of one
-// community (or of the unassigned tail).  Staged chunks copy the community's state planes
-// and features into LDS first.  RP > 0 fixes the feature stride at compile
-// time (own features held in registers); RP == 0 reads it from the arguments.
+// Chunks of the communities on a basis (the expansion of the weight, E1 and
+// E2 of App. A.6): four lanes per row (each takes every fourth partner, then
+// the row's sums are combined across the group); the block covers up to 256
+// rows of one community.  Staged chunks copy the community's state planes and
+// features into LDS first.  RP > 0 fixes the feature stride at compile time
+// (own features held in registers); RP == 0 reads it from the arguments.
+// Chunks on the exact path (fallback communities, rows of no community) are
+// flock_exact_kernel's.
 template <int RP>
 __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
     extern __shared__ float lds[];
@@ -392,10 +411,7 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
         lam = a.comm_off[c + 1] - (int)c0;
         fb = a.fb[c] != 0;
     }
-    // the stage is split in two launches when a basis is in use: chunks on the
-    // exact path (fallback communities, rows of no community) in the lean
-    // exact-only instantiation, the others in the basis one
-    if ((a.select == 1 && !fb) || (a.select == 2 && fb)) return;   // before any barrier
+    if (fb) return;   // an exact-path chunk; before any barrier
     const bool staged = ch.staged != 0 && c >= 0;
     float *sY = lds;                       // [6][lam]
     float *sF = lds + ((6 * lam + 3) & ~3);  // [lam][Rp], 16-byte aligned
@@ -460,68 +476,45 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
         }
     };
     float acc[3] = {0.f, 0.f, 0.f};
-    if (c >= 0) {
-        const int64_t e0 = a.negptr[i], e1 = a.negptr[i + 1];
-        if (!fb) {
-            // E1 broadcast: sum_r sgn_r f_r(s_i) (V_cr - v_i P_cr), by the
-            // first lane of the row's group
-            const float *fi = staged ? sF + (i - c0) * Rp : a.F + i * Rp;
-            const float4 *Qc = reinterpret_cast<const float4 *>(a.Q) + (int64_t)c * Rp;
-            float g[RP > 0 ? RP : 1];
-            float sP = 0.f, sV0 = 0.f, sV1 = 0.f, sV2 = 0.f;
-            for (int r = 0; r < Rp; r++) {
-                const float gr = a.sgn[r] * fi[r];
-                if (RP > 0) g[RP > 0 ? r : 0] = gr;
-                if (sub == 0) {
-                    const float4 q = Qc[r];
-                    sP += gr * q.x;
-                    sV0 += gr * q.y;
-                    sV1 += gr * q.z;
-                    sV2 += gr * q.w;
-                }
-            }
-            acc[0] = sV0 - vi[0] * sP;
-            acc[1] = sV1 - vi[1] * sP;
-            acc[2] = sV2 - vi[2] * sP;
-            // E2, S-neg: subtract the expanded weight of the missing intra pairs
-            for (int64_t e = e0 + sub; e < e1; e += TPR) {
-                const int jl = a.neg[e];
-                const float *fj = staged ? sF + (int64_t)jl * Rp : a.F + (c0 + jl) * Rp;
-                float wt = 0.f;
-                if (RP > 0) {
+    const int64_t e0 = a.negptr[i], e1 = a.negptr[i + 1];
+    // E1 broadcast: sum_r sgn_r f_r(s_i) (V_cr - v_i P_cr), by the
+    // first lane of the row's group
+    const float *fi = staged ? sF + (i - c0) * Rp : a.F + i * Rp;
+    const float4 *Qc = reinterpret_cast<const float4 *>(a.Q) + (int64_t)c * Rp;
+    float g[RP > 0 ? RP : 1];
+    float sP = 0.f, sV0 = 0.f, sV1 = 0.f, sV2 = 0.f;
+    for (int r = 0; r < Rp; r++) {
+        const float gr = a.sgn[r] * fi[r];
+        if (RP > 0) g[RP > 0 ? r : 0] = gr;
+        if (sub == 0) {
+            const float4 q = Qc[r];
+            sP += gr * q.x;
+            sV0 += gr * q.y;
+            sV1 += gr * q.z;
+            sV2 += gr * q.w;
+        }
+    }
+    acc[0] = sV0 - vi[0] * sP;
+    acc[1] = sV1 - vi[1] * sP;
+    acc[2] = sV2 - vi[2] * sP;
+    // E2, S-neg: subtract the expanded weight of the missing intra pairs
+    for (int64_t e = e0 + sub; e < e1; e += TPR) {
+        const int jl = a.neg[e];
+        const float *fj = staged ? sF + (int64_t)jl * Rp : a.F + (c0 + jl) * Rp;
+        float wt = 0.f;
+        if (RP > 0) {
 #pragma unroll
-                    for (int r = 0; r < (RP > 0 ? RP : 1); r += 4) {
-                        const float4 f4 = *reinterpret_cast<const float4 *>(fj + r);
-                        wt += g[r] * f4.x + g[r + 1] * f4.y + g[r + 2] * f4.z + g[r + 3] * f4.w;
-                    }
-                } else {
-                    for (int r = 0; r < Rp; r++) wt += a.sgn[r] * fi[r] * fj[r];
-                }
-                float xj[3], vj[3];
-                member(jl, xj, vj);
-#pragma unroll
-                for (int d = 0; d < 3; d++) acc[d] -= wt * (vj[d] - vi[d]);
+            for (int r = 0; r < (RP > 0 ? RP : 1); r += 4) {
+                const float4 f4 = *reinterpret_cast<const float4 *>(fj + r);
+                wt += g[r] * f4.x + g[r + 1] * f4.y + g[r + 2] * f4.z + g[r + 3] * f4.w;
             }
         } else {
-            // exact fallback: all pairs of the community minus S-neg
-            for (int jl = sub; jl < lam; jl += TPR) {
-                if (c0 + jl == i) continue;
-                float xj[3], vj[3];
-                member(jl, xj, vj);
-                const float d0 = xj[0] - xi[0], d1 = xj[1] - xi[1], d2 = xj[2] - xi[2];
-                const float w = cs_weight(d0 * d0 + d1 * d1 + d2 * d2, a.K, a.s2, a.beta);
-#pragma unroll
-                for (int d = 0; d < 3; d++) acc[d] += w * (vj[d] - vi[d]);
-            }
-            for (int64_t e = e0 + sub; e < e1; e += TPR) {
-                float xj[3], vj[3];
-                member(a.neg[e], xj, vj);
-                const float d0 = xj[0] - xi[0], d1 = xj[1] - xi[1], d2 = xj[2] - xi[2];
-                const float w = cs_weight(d0 * d0 + d1 * d1 + d2 * d2, a.K, a.s2, a.beta);
-#pragma unroll
-                for (int d = 0; d < 3; d++) acc[d] -= w * (vj[d] - vi[d]);
-            }
+            for (int r = 0; r < Rp; r++) wt += a.sgn[r] * fi[r] * fj[r];
         }
+        float xj[3], vj[3];
+        member(jl, xj, vj);
+#pragma unroll
+        for (int d = 0; d < 3; d++) acc[d] -= wt * (vj[d] - vi[d]);
     }
     // E2, S-pos: exact weight on the pairs leaving the community
     for (int64_t e = a.posptr[i] + sub, e1 = a.posptr[i + 1]; e < e1; e += TPR) {
@@ -537,6 +530,197 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
         for (int o = 1; o < TPR; o <<= 1) acc[d] += __shfl_xor(acc[d], o);
     if (sub == 0) {
         const float k[6] = {vi[0], vi[1], vi[2], acc[0] * a.invN, acc[1] * a.invN, acc[2] * a.invN};
+        flock_emit(a, i, k);
+    }
+}
+
+// Exact community path: the community sums of App. A.6 eq. (Cucker_Smale)
+// taken pair by pair, with RT lanes per row.  The dense sum runs over every
+// member of the row's community four members at a time, each plane read as a
+// 16-byte LDS broadcast (every lane of a row group takes the same members);
+// where s2 is a normal float and s2^(-beta) finite it sums w v_j and w and
+// subtracts v_i times the weight sum once (the self pair then adds exactly
+// 0), otherwise the self pair is masked and the clamp of cs_weight applies.
+// The S-neg pairs are then subtracted: a staged chunk's rows run in order of
+// decreasing S-neg length, and the S-neg of the 64 / RT rows of a wavefront
+// is a slice whose k-th entries lie together (one coalesced load of 16-bit
+// member indices per step, members gathered from LDS).  Last the S-pos pairs
+// are added.  Rows of no community take only their S-pos pairs.  Weights
+// are taken without K, which multiplies the row's total.  Chunks of
+// communities on a basis are left to flock_stage_kernel.
+template <int RT>
+__global__ __launch_bounds__(CHUNK_ROWS * RT) void flock_exact_kernel(FlockArgs a) {
+    extern __shared__ float lds[];
+    const FlockChunk ch = a.chunks[blockIdx.x];
+    const int64_t n = a.n;
+    const int c = ch.comm;
+    int64_t c0 = 0;
+    int lam = 0;
+    bool fb = true;
+    if (c >= 0) {
+        c0 = a.comm_off[c];
+        lam = a.comm_off[c + 1] - (int)c0;
+        fb = a.fb[c] != 0;
+    }
+    if (!fb) return;   // before any barrier
+    const int lamp = (lam + 3) & ~3;   // plane stride, a multiple of 4 floats
+    const bool staged = c >= 0 && (int64_t)6 * lamp * (int64_t)sizeof(float) <= (int64_t)a.exact_lds;
+    float *sY = lds;                   // [6][lamp], pad entries 0
+    if (staged) {
+        constexpr int US = 8;          // loads in flight per thread before the LDS writes
+        const int ny = 6 * lamp;
+        for (int q0 = threadIdx.x; q0 < ny; q0 += CHUNK_ROWS * RT * US) {
+            float v[US];
+#pragma unroll
+            for (int u = 0; u < US; u++) {
+                const int q = q0 + u * CHUNK_ROWS * RT;
+                const int d = q / lamp, j = q - d * lamp;
+                v[u] = q < ny && j < lam ? a.Ys[d * n + c0 + j] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < US; u++)
+                if (q0 + u * CHUNK_ROWS * RT < ny) sY[q0 + u * CHUNK_ROWS * RT] = v[u];
+        }
+    }
+    __syncthreads();
+    const int rloc = (int)threadIdx.x / RT, sub = (int)threadIdx.x % RT;
+    if (rloc >= ch.rows) return;   // no barrier below
+    const bool sliced = staged && ch.sbase >= 0;
+    const int64_t i = ch.row0 + (sliced ? (int)a.srow[ch.row0 + rloc] : rloc);
+    float xi[3], vi[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        xi[d] = a.Ys[d * n + i];
+        vi[d] = a.Ys[(3 + d) * n + i];
+    }
+    const float s2 = a.s2, nbeta = -a.beta;
+    // (s2 + r2)^(-beta) on the hardware base-2 log and exp (as cs_weight)
+    auto wt = [&](float d0, float d1, float d2) {
+        const float x = fmaxf(s2 + (d0 * d0 + d1 * d1 + d2 * d2), 1.17549435e-38f);
+        return __builtin_amdgcn_exp2f(nbeta * __builtin_amdgcn_logf(x));
+    };
+    // the same where s2 is a normal float (s2 + r2 >= s2: no clamp)
+    auto wt_plain = [&](float d0, float d1, float d2) {
+        const float x = fmaf(d2, d2, fmaf(d1, d1, fmaf(d0, d0, s2)));
+        return __builtin_amdgcn_exp2f(nbeta * __builtin_amdgcn_logf(x));
+    };
+    float acc[3] = {0.f, 0.f, 0.f};
+    if (c >= 0) {
+        const int il = (int)(i - c0);
+        if (staged) {
+            // whole groups of four members as 16-byte LDS broadcasts
+            const float4 *P0 = reinterpret_cast<const float4 *>(sY);
+            const int g4 = lamp >> 2, gfull = lam >> 2;
+            // plain: sum w v_j and w, and take v_i times the weight sum once
+            float aw[4] = {0.f, 0.f, 0.f, 0.f};
+            auto groups = [&](auto plain) {
+#pragma unroll 2
+                for (int g = sub; g < gfull; g += RT) {
+                    float4 X[3], V[3];
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        X[d] = P0[d * g4 + g];
+                        V[d] = P0[(3 + d) * g4 + g];
+                    }
+                    const float xs[3][4] = {{X[0].x, X[0].y, X[0].z, X[0].w},
+                                            {X[1].x, X[1].y, X[1].z, X[1].w},
+                                            {X[2].x, X[2].y, X[2].z, X[2].w}};
+                    const float vs[3][4] = {{V[0].x, V[0].y, V[0].z, V[0].w},
+                                            {V[1].x, V[1].y, V[1].z, V[1].w},
+                                            {V[2].x, V[2].y, V[2].z, V[2].w}};
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        if constexpr (decltype(plain)::value) {
+                            // the self pair adds w(0) (v_i - v_i), finite w(0)
+                            const float w = wt_plain(xs[0][u] - xi[0], xs[1][u] - xi[1], xs[2][u] - xi[2]);
+#pragma unroll
+                            for (int d = 0; d < 3; d++) aw[d] = fmaf(w, vs[d][u], aw[d]);
+                            aw[3] += w;
+                        } else {
+                            float w = wt(xs[0][u] - xi[0], xs[1][u] - xi[1], xs[2][u] - xi[2]);
+                            w = 4 * g + u == il ? 0.f : w;
+#pragma unroll
+                            for (int d = 0; d < 3; d++) acc[d] += w * (vs[d][u] - vi[d]);
+                        }
+                    }
+                }
+            };
+            if (a.plain) {
+                groups(std::integral_constant<bool, true>());
+#pragma unroll
+                for (int d = 0; d < 3; d++) acc[d] = fmaf(-vi[d], aw[3], aw[d]);
+            } else {
+                groups(std::integral_constant<bool, false>());
+            }
+            // the last lam mod 4 members
+            for (int j = 4 * gfull + sub; j < lam; j += RT) {
+                if (j == il) continue;
+                const float w = wt(sY[j] - xi[0], sY[lamp + j] - xi[1], sY[2 * lamp + j] - xi[2]);
+#pragma unroll
+                for (int d = 0; d < 3; d++) acc[d] += w * (sY[(3 + d) * lamp + j] - vi[d]);
+            }
+        } else {
+            for (int j = sub; j < lam; j += RT) {
+                if (j == il) continue;
+                const int64_t q = c0 + j;
+                const float w = wt(a.Ys[q] - xi[0], a.Ys[n + q] - xi[1], a.Ys[2 * n + q] - xi[2]);
+#pragma unroll
+                for (int d = 0; d < 3; d++) acc[d] += w * (a.Ys[(3 + d) * n + q] - vi[d]);
+            }
+        }
+        // S-neg: the missing intra pairs (never the self pair)
+        if (sliced) {
+            // this row's slice: one coalesced load of entry k for the
+            // wavefront's rows, members gathered from LDS
+            constexpr int SR = 64 / RT;
+            const int sl = ch.sbase + rloc / SR, rs = rloc % SR;
+            const uint16_t *sp = a.sneg + a.sneg_off[sl];
+            const int sw = a.sneg_w[sl];
+            const int len = (int)(a.negptr[i + 1] - a.negptr[i]);
+            auto sneg = [&](auto plain) {
+#pragma unroll 4
+                for (int k = sub; k < sw; k += RT) {
+                    const int jl = sp[(int64_t)k * SR + rs];
+                    const float d0 = sY[jl] - xi[0], d1 = sY[lamp + jl] - xi[1], d2 = sY[2 * lamp + jl] - xi[2];
+                    float w = decltype(plain)::value ? wt_plain(d0, d1, d2) : wt(d0, d1, d2);
+                    w = k < len ? w : 0.f;
+#pragma unroll
+                    for (int d = 0; d < 3; d++) acc[d] -= w * (sY[(3 + d) * lamp + jl] - vi[d]);
+                }
+            };
+            if (a.plain)
+                sneg(std::integral_constant<bool, true>());
+            else
+                sneg(std::integral_constant<bool, false>());
+        } else {
+            for (int64_t e = a.negptr[i] + sub, e1 = a.negptr[i + 1]; e < e1; e += RT) {
+                const int jl = a.neg[e];
+                float xj[3], vj[3];
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    xj[d] = staged ? sY[d * lamp + jl] : a.Ys[d * n + c0 + jl];
+                    vj[d] = staged ? sY[(3 + d) * lamp + jl] : a.Ys[(3 + d) * n + c0 + jl];
+                }
+                const float w = wt(xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]);
+#pragma unroll
+                for (int d = 0; d < 3; d++) acc[d] -= w * (vj[d] - vi[d]);
+            }
+        }
+    }
+    // S-pos: the pairs leaving the community
+    for (int64_t e = a.posptr[i] + sub, e1 = a.posptr[i + 1]; e < e1; e += RT) {
+        const int64_t j = a.pos[e];
+        const float w = wt(a.Ys[j] - xi[0], a.Ys[n + j] - xi[1], a.Ys[2 * n + j] - xi[2]);
+#pragma unroll
+        for (int d = 0; d < 3; d++) acc[d] += w * (a.Ys[(3 + d) * n + j] - vi[d]);
+    }
+    // the row's partial sums, combined in a fixed order across its group
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+        for (int o = 1; o < RT; o <<= 1) acc[d] += __shfl_xor(acc[d], o);
+    if (sub == 0) {
+        const float kn = a.K * a.invN;
+        const float k[6] = {vi[0], vi[1], vi[2], acc[0] * kn, acc[1] * kn, acc[2] * kn};
         flock_emit(a, i, k);
     }
 }
@@ -960,6 +1144,10 @@ struct FlockState {
     int32_t *neg = nullptr, *pos = nullptr, *acol = nullptr;
     FlockChunk *chunks = nullptr;
     int nchunks = 0;
+    uint16_t *sneg = nullptr;           // flock_exact_kernel's sliced S-neg
+    uint8_t *srow = nullptr;
+    int64_t *sneg_off = nullptr;
+    int32_t *sneg_w = nullptr;
     size_t lds_bytes = 0;
     size_t lds_exact = 0;   // LDS of the exact-path launch (state planes only)
     // state and E1
@@ -1066,6 +1254,10 @@ FlockArgs base_args(cia_plan *p) {
     a.comm_off = f->comm_off;
     a.negptr = f->negptr;
     a.neg = f->neg;
+    a.sneg = f->sneg;
+    a.sneg_off = f->sneg_off;
+    a.sneg_w = f->sneg_w;
+    a.srow = f->srow;
     a.posptr = f->posptr;
     a.pos = f->pos;
     a.arp = f->arp;
@@ -1168,12 +1360,18 @@ cia_status launch_stage(cia_plan *p, const FlockArgs &a0, hipStream_t s) {
         flock_direct_kernel<<<grid_for(p->n, 4), 256, 0, s>>>(a0);
     } else if (f->nchunks > 0) {
         FlockArgs a = a0;
-        if (f->basis != CIA_BASIS_EXACT) {
-            // exact-path chunks first, in the exact-only instantiation (fewer
-            // registers, only the state planes staged)
-            a.select = 1;
-            flock_stage_kernel<0><<<f->nchunks, FBLOCK, f->lds_exact, s>>>(a);
-            a.select = 2;
+        // exact-path chunks (communities on the exact fallback, rows of no
+        // community) in their own kernel; then, with a basis, the others
+        a.exact_lds = (int)f->lds_exact;
+        {
+            const double w0 = std::pow((double)f->s2, -(double)f->beta);   // the largest weight
+            a.plain = f->s2 >= FLT_MIN && std::isfinite(w0) && w0 < 1e38 ? 1 : 0;
+        }
+        flock_exact_kernel<EXACT_RT><<<f->nchunks, CHUNK_ROWS * EXACT_RT, f->lds_exact, s>>>(a);
+        if (f->basis == CIA_BASIS_EXACT) {
+            CIA_HIP(hipGetLastError());
+            CIA_TRY(timing_end(p, s));
+            return CIA_OK;
         }
         const size_t lds = f->lds_bytes;
         switch (f->Rp) {
@@ -1433,19 +1631,59 @@ cia_status flock_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     const size_t cap = std::min(STAGE_LDS_CAP, (size_t)dev_lds);
     std::vector<FlockChunk> ch;
     size_t lds = 0, lds_ex = 0;
+    constexpr int32_t SR = 64 / EXACT_RT;   // rows of an S-neg slice (one wavefront)
+    static_assert(CHUNK_ROWS <= 256, "chunk rows are numbered by uint8_t");
+    std::vector<uint16_t> sneg;
+    std::vector<int64_t> sneg_off;
+    std::vector<int32_t> sneg_w;
+    std::vector<uint8_t> srow(n, 0);
     for (int32_t q = 0; q < p1.ncomm; q++) {
         const int32_t c0 = p1.comm_off[q], lam = p1.comm_off[q + 1] - c0;
         const size_t planes = (((size_t)6 * lam + 3) & ~(size_t)3) * sizeof(float);
+        const size_t planes_e = (size_t)6 * (((size_t)lam + 3) & ~(size_t)3) * sizeof(float);   // exact kernel
         const size_t need = planes + (size_t)lam * (f->basis == CIA_BASIS_EXACT ? 0 : f->Rp) * sizeof(float);
         const int staged = need <= cap ? 1 : 0;
-        if (staged) {
-            lds = std::max(lds, need);
-            lds_ex = std::max(lds_ex, planes);
+        if (staged) lds = std::max(lds, need);
+        const bool staged_e = planes_e <= cap;   // flock_exact_kernel stages the planes
+        if (staged_e) lds_ex = std::max(lds_ex, planes_e);
+        for (int32_t r = 0; r < lam; r += CHUNK_ROWS) {
+            const int32_t rows = std::min(CHUNK_ROWS, lam - r);
+            int32_t sbase = -1;
+            if (staged_e) {
+                // the chunk's rows by decreasing S-neg length (stable), then
+                // S-neg slices of SR of them: entry k of the slice's rows together
+                const int64_t rw0 = (int64_t)c0 + r;
+                auto len = [&](int32_t t) { return p1.negptr[rw0 + t + 1] - p1.negptr[rw0 + t]; };
+                std::vector<int32_t> ord(rows);
+                std::iota(ord.begin(), ord.end(), 0);
+                std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return len(x) > len(y); });
+                for (int32_t t = 0; t < rows; t++) srow[rw0 + t] = (uint8_t)ord[t];
+                sbase = (int32_t)sneg_w.size();
+                for (int32_t s0 = 0; s0 < rows; s0 += SR) {
+                    const int32_t rs = std::min(SR, rows - s0);
+                    int64_t w = 0;
+                    for (int32_t u = 0; u < rs; u++) w = std::max(w, len(ord[s0 + u]));
+                    sneg_off.push_back((int64_t)sneg.size());
+                    sneg_w.push_back((int32_t)w);
+                    for (int64_t k = 0; k < w; k++)
+                        for (int32_t u = 0; u < SR; u++) {
+                            const bool in = u < rs && k < len(ord[s0 + u]);
+                            sneg.push_back(in ? (uint16_t)p1.neg_local[p1.negptr[rw0 + ord[s0 + u]] + k] : (uint16_t)0);
+                        }
+                }
+            }
+            ch.push_back(FlockChunk{c0 + r, rows, q, staged, sbase});
         }
-        for (int32_t r = 0; r < lam; r += CHUNK_ROWS) ch.push_back(FlockChunk{c0 + r, std::min(CHUNK_ROWS, lam - r), q, staged});
     }
     for (int64_t r = f->nassigned; r < n; r += CHUNK_ROWS)
-        ch.push_back(FlockChunk{(int32_t)r, (int32_t)std::min<int64_t>(CHUNK_ROWS, n - r), -1, 0});
+        ch.push_back(FlockChunk{(int32_t)r, (int32_t)std::min<int64_t>(CHUNK_ROWS, n - r), -1, 0, -1});
+    if (!sneg_w.empty()) {
+        if (sneg.empty()) sneg.push_back(0);   // every slice of width 0
+        CIA_TRY(dupload(p, &f->sneg, sneg.data(), sneg.size()));
+        CIA_TRY(dupload(p, &f->sneg_off, sneg_off.data(), sneg_off.size()));
+        CIA_TRY(dupload(p, &f->sneg_w, sneg_w.data(), sneg_w.size()));
+        CIA_TRY(dupload(p, &f->srow, srow.data(), srow.size()));
+    }
     f->nchunks = (int)ch.size();
     f->lds_bytes = lds;
     f->lds_exact = lds_ex;
@@ -1463,6 +1701,9 @@ cia_status flock_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         }
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void *)flock_stage_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)flock_exact_kernel<EXACT_RT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)cap);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return set_error(CIA_EHIP, "cannot raise the LDS limit of the flock stage kernel to %zu bytes", cap);
