@@ -80,6 +80,29 @@ def test_flock_exact_rhs(env, method):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("sigma,beta", [(1.0, 0.25), (1e-30, 0.25), (1e-20, 0.5), (0.01, 10.0)])
+def test_flock_exact_kernel_paths(env, sigma, beta):
+    """The exact-path kernel's cases: a community above the LDS staging cap
+    (4500 members, read from global memory with per-row S-neg lists) beside
+    staged ones whose sizes leave 1 to 3 members after the groups of four,
+    rows of no community.  s2 = 1 takes the unclamped weight-sum loop; an s2
+    that is 0 in FP32 (sigma = 1e-30), a denormal s2 (1e-40) and an
+    s2^(-beta) beyond the FP32 range (1e-4 to the power -10) take the clamped
+    loop with the self pair masked."""
+    cia, torch = env
+    g, x, v = small_flock(49, n=5131, sizes=[4500, 333, 250, 7], p_in=[0.8, 0.7, 0.9, 1.0], inter_deg=2.0,
+                          unassigned=41)
+    st = state_tensor(torch, x, v)
+    s64 = st.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(3).choice(g.n, 1500, replace=False)
+    _, vd = oracle.cs_rhs(g.n, g.row_ptr, g.col, 1.7, sigma, beta, s64[:3], s64[3:], rows=rows)
+    plan = cia.Plan.flock(g.n, g.row_ptr, g.col, g.labels, K=1.7, sigma=sigma, beta=beta)
+    got = run_rhs(torch, plan, st)
+    err = coupling_err(got[3:, rows], vd)
+    say("exact kernel paths sigma", sigma, "beta", beta, "ncomm", plan.info().ncomm, "rel_inf", err)
+    assert plan.info().ncomm == 4 and err < 1e-5
+
+
 def test_flock_edge_cases(env):
     cia, torch = env
     # one community of a single node, one dissolved by the cost rule (p_in tiny),
