@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--triadic-n", type=int, default=6000, help="triadic: network size (sizes U[200, 2000])")
     ap.add_argument("--train-iters", type=int, default=3000, help="flock: optimiser steps of the basis")
     ap.add_argument("--ensemble-nmax", type=float, default=2e5, help="ensemble: largest instance size")
-    ap.add_argument("--ensemble-oracle-share", type=float, default=0.08,
+    ap.add_argument("--ensemble-oracle-share", type=float, default=0.25,
                     help="ensemble: share of every instance's rows the CPU oracle evaluates")
     ap.add_argument("--no-sequential", action="store_true",
                     help="ensemble: skip the 256 single-network plans")
