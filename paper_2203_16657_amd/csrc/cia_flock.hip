@@ -35,6 +35,7 @@
 
 #include "fastmath.h"
 #include "plan.h"
+#include "wave.h"
 
 namespace cia {
 
@@ -763,96 +764,98 @@ struct JudgeArgs {
     const int64_t *negptr;
     const int32_t *neg;
     const float *F, *sgn, *Q, *Y;
-    int32_t *fb;
+    float2 *es;          // [ncomm][JUDGE_SAMPLES]: (error, scale) of every sample
     int64_t n;
-    float K, s2, beta, tol;
+    float K, s2, beta;
     int Rp;
     uint64_t seed;
 };
 
-// One block per community, one wavefront per sample.  For a sampled member i
-// the community part of its sum is computed twice: exactly (all pairs minus
+// One 64-lane block per (community, sample).  For the sampled member i the
+// community part of its sum is computed twice: exactly (all pairs minus
 // S-neg, exact weight) and as the method does (E1 broadcast minus S-neg with
-// the expanded weight).  The community falls back when
-//   max_i |approx_i - exact_i|_inf > tol * max_i |exact_i|_inf
-// or when any of it is not finite.
-__global__ __launch_bounds__(256) void flock_judge_kernel(JudgeArgs a) {
-    __shared__ float s_err[4], s_scale[4];
-    const int c = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// the expanded weight); the block writes max_d |approx - exact| (NaN kept)
+// and max_d |exact|.  flock_judge_decide then takes every community's
+// maximum over its samples.
+__global__ __launch_bounds__(64) void flock_judge_kernel(JudgeArgs a) {
+    extern __shared__ float gsh[];   // [Rp]: sgn_r f_r(s_i)
+    const int c = blockIdx.x / JUDGE_SAMPLES, smp = blockIdx.x % JUDGE_SAMPLES, lane = threadIdx.x;
     const int64_t n = a.n;
     const int64_t c0 = a.comm_off[c];
     const int lam = a.comm_off[c + 1] - (int)c0;
     const int Rp = a.Rp;
-    if (lam <= 0) {  // whole block leaves together
-        if (threadIdx.x == 0) a.fb[c] = 0;
+    if (lam <= 0) {  // the whole block leaves together
+        if (lane == 0) a.es[blockIdx.x] = make_float2(0.f, 0.f);
         return;
     }
-    float werr = 0.f, wscale = 0.f;
-    for (int smp = w; smp < JUDGE_SAMPLES; smp += 4) {
-        const int64_t i = c0 + (int64_t)(mix64(a.seed ^ ((uint64_t)c << 20) ^ (uint64_t)smp) % (uint64_t)lam);
-        float xi[3], vi[3];
-        for (int d = 0; d < 3; d++) {
-            xi[d] = a.Y[d * n + i];
-            vi[d] = a.Y[(3 + d) * n + i];
-        }
-        const float *fi = a.F + i * Rp;
-        float ex[3] = {0.f, 0.f, 0.f}, ap[3] = {0.f, 0.f, 0.f};
-        for (int64_t j = c0 + lane; j < c0 + lam; j += 64) {
-            if (j == i) continue;
-            const float d0 = a.Y[j] - xi[0], d1 = a.Y[n + j] - xi[1], d2 = a.Y[2 * n + j] - xi[2];
-            const float wx = cs_weight(d0 * d0 + d1 * d1 + d2 * d2, a.K, a.s2, a.beta);
-            for (int d = 0; d < 3; d++) ex[d] += wx * (a.Y[(3 + d) * n + j] - vi[d]);
-        }
-        for (int64_t e = a.negptr[i] + lane; e < a.negptr[i + 1]; e += 64) {
-            const int64_t j = c0 + a.neg[e];
-            const float d0 = a.Y[j] - xi[0], d1 = a.Y[n + j] - xi[1], d2 = a.Y[2 * n + j] - xi[2];
-            const float wx = cs_weight(d0 * d0 + d1 * d1 + d2 * d2, a.K, a.s2, a.beta);
-            const float *fj = a.F + j * Rp;
-            float wt = 0.f;
-            for (int r = 0; r < Rp; r++) wt += a.sgn[r] * fi[r] * fj[r];
-            for (int d = 0; d < 3; d++) {
-                const float dv = a.Y[(3 + d) * n + j] - vi[d];
-                ex[d] -= wx * dv;
-                ap[d] -= wt * dv;
-            }
-        }
-        for (int d = 0; d < 3; d++)
-            for (int off = 32; off > 0; off >>= 1) {
-                ex[d] += __shfl_xor(ex[d], off);
-                ap[d] += __shfl_xor(ap[d], off);
-            }
-        // E1 broadcast (every lane computes it; identical results)
-        float sP = 0.f, sV[3] = {0.f, 0.f, 0.f};
-        for (int r = 0; r < Rp; r++) {
-            const float g = a.sgn[r] * fi[r];
-            const float *q = a.Q + ((int64_t)c * Rp + r) * 4;
-            sP += g * q[0];
-            for (int d = 0; d < 3; d++) sV[d] += g * q[1 + d];
-        }
-        float e_ = 0.f, s_ = 0.f;
-        for (int d = 0; d < 3; d++) {
-            const float apd = ap[d] + sV[d] - vi[d] * sP;
-            const float diff = fabsf(apd - ex[d]);
-            e_ = (diff > e_ || diff != diff) ? diff : e_;  // NaN propagates
-            s_ = fmaxf(s_, fabsf(ex[d]));
-        }
-        werr = (e_ > werr || e_ != e_) ? e_ : werr;
-        wscale = fmaxf(wscale, s_);
+    const int64_t i = c0 + (int64_t)(mix64(a.seed ^ ((uint64_t)c << 20) ^ (uint64_t)smp) % (uint64_t)lam);
+    float xi[3], vi[3];
+    for (int d = 0; d < 3; d++) {
+        xi[d] = a.Y[d * n + i];
+        vi[d] = a.Y[(3 + d) * n + i];
     }
-    if (lane == 0) {
-        s_err[w] = werr;
-        s_scale[w] = wscale;
-    }
+    for (int r = lane; r < Rp; r += 64) gsh[r] = a.sgn[r] * a.F[i * Rp + r];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float e_ = 0.f, s_ = 0.f;
-        for (int q = 0; q < 4; q++) {
-            e_ = (s_err[q] > e_ || s_err[q] != s_err[q]) ? s_err[q] : e_;
-            s_ = fmaxf(s_, s_scale[q]);
-        }
-        const bool ok = (e_ <= a.tol * s_) && isfinite(e_) && isfinite(s_);
-        a.fb[c] = ok ? 0 : 1;
+    float ex[3] = {0.f, 0.f, 0.f}, ap[3] = {0.f, 0.f, 0.f};
+    for (int64_t j = c0 + lane; j < c0 + lam; j += 64) {
+        if (j == i) continue;
+        const float d0 = a.Y[j] - xi[0], d1 = a.Y[n + j] - xi[1], d2 = a.Y[2 * n + j] - xi[2];
+        const float wx = cs_weight(d0 * d0 + d1 * d1 + d2 * d2, a.K, a.s2, a.beta);
+        for (int d = 0; d < 3; d++) ex[d] += wx * (a.Y[(3 + d) * n + j] - vi[d]);
     }
+    const float4 *g4 = reinterpret_cast<const float4 *>(gsh);
+    for (int64_t e = a.negptr[i] + lane; e < a.negptr[i + 1]; e += 64) {
+        const int64_t j = c0 + a.neg[e];
+        const float d0 = a.Y[j] - xi[0], d1 = a.Y[n + j] - xi[1], d2 = a.Y[2 * n + j] - xi[2];
+        const float wx = cs_weight(d0 * d0 + d1 * d1 + d2 * d2, a.K, a.s2, a.beta);
+        const float4 *fj = reinterpret_cast<const float4 *>(a.F + j * Rp);   // Rp is a multiple of 4
+        float wt = 0.f;
+        for (int r = 0; r < Rp / 4; r++) {
+            const float4 f = fj[r], g = g4[r];
+            wt += g.x * f.x + g.y * f.y + g.z * f.z + g.w * f.w;
+        }
+        for (int d = 0; d < 3; d++) {
+            const float dv = a.Y[(3 + d) * n + j] - vi[d];
+            ex[d] -= wx * dv;
+            ap[d] -= wt * dv;
+        }
+    }
+    // E1 broadcast, lane-strided over the features
+    float sP = 0.f, sV[3] = {0.f, 0.f, 0.f};
+    for (int r = lane; r < Rp; r += 64) {
+        const float g = gsh[r];
+        const float4 q = reinterpret_cast<const float4 *>(a.Q)[(int64_t)c * Rp + r];
+        sP += g * q.x;
+        sV[0] += g * q.y;
+        sV[1] += g * q.z;
+        sV[2] += g * q.w;
+    }
+    sP = wave_sum(sP);
+    float e_ = 0.f, s_ = 0.f;
+    for (int d = 0; d < 3; d++) {
+        const float exd = wave_sum(ex[d]);
+        const float apd = wave_sum(ap[d]) + wave_sum(sV[d]) - vi[d] * sP;
+        const float diff = fabsf(apd - exd);
+        e_ = (diff > e_ || diff != diff) ? diff : e_;  // NaN propagates
+        s_ = fmaxf(s_, fabsf(exd));
+    }
+    if (lane == 0) a.es[blockIdx.x] = make_float2(e_, s_);
+}
+
+// A community falls back to the exact path when
+//   max_i |approx_i - exact_i|_inf > tol * max_i |exact_i|_inf
+// over its sampled members, or when any of it is not finite.
+__global__ void flock_judge_decide(const float2 *__restrict__ es, int ncomm, float tol, int32_t *__restrict__ fb) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncomm) return;
+    float e_ = 0.f, s_ = 0.f;
+    for (int q = 0; q < JUDGE_SAMPLES; q++) {
+        const float2 v = es[(int64_t)c * JUDGE_SAMPLES + q];
+        e_ = (v.x > e_ || v.x != v.x) ? v.x : e_;
+        s_ = fmaxf(s_, v.y);
+    }
+    const bool ok = (e_ <= tol * s_) && isfinite(e_) && isfinite(s_);
+    fb[c] = ok ? 0 : 1;
 }
 
 // --------------------------------------------------------------------------
@@ -1155,6 +1158,7 @@ struct FlockState {
     float *acc = nullptr;
     float *F = nullptr, *sgn = nullptr, *Q = nullptr;
     int32_t *fb = nullptr;
+    float2 *judge_es = nullptr;         // [ncomm][JUDGE_SAMPLES] per-sample judge results
     int4 *alpha = nullptr;
     int nh = 0;
     // learned basis
@@ -1338,15 +1342,16 @@ cia_status run_observables(cia_plan *p, const float *Ys, bool judge, hipStream_t
         j.sgn = f->sgn;
         j.Q = f->Q;
         j.Y = Ys;
-        j.fb = f->fb;
+        j.es = f->judge_es;
         j.n = p->n;
         j.K = f->K;
         j.s2 = f->s2;
         j.beta = f->beta;
-        j.tol = f->judge_tol;
         j.Rp = f->Rp;
         j.seed = mix64(f->judge_seed++);
-        flock_judge_kernel<<<f->ncomm, 256, 0, s>>>(j);
+        flock_judge_kernel<<<f->ncomm * JUDGE_SAMPLES, 64, (size_t)f->Rp * sizeof(float), s>>>(j);
+        CIA_HIP(hipGetLastError());
+        flock_judge_decide<<<grid_for(f->ncomm, 256), 256, 0, s>>>(f->judge_es, f->ncomm, f->judge_tol, f->fb);
         CIA_HIP(hipGetLastError());
     }
     CIA_TRY(timing_end(p, s));
@@ -1620,6 +1625,7 @@ cia_status flock_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         CIA_TRY(dalloc(p, &f->Q, (size_t)std::max(1, f->ncomm) * f->Rp * 4));
     }
     CIA_TRY(dalloc(p, &f->fb, (size_t)std::max(1, f->ncomm)));
+    if (f->judge) CIA_TRY(dalloc(p, &f->judge_es, (size_t)std::max(1, f->ncomm) * JUDGE_SAMPLES));
     if (f->ncomm > 0) {
         flock_fill_i32<<<grid_for(f->ncomm, 256), 256>>>(f->fb, f->ncomm, f->basis == CIA_BASIS_EXACT ? 1 : 0);
         CIA_HIP(hipGetLastError());
