@@ -50,6 +50,7 @@ constexpr int JUDGE_SAMPLES = 16;  // sampled members per community and step
 constexpr int TRAIN_PAIRS = 4096;  // pairs per optimiser step
 constexpr int TILE_PTS = 64;       // points per MFMA tile (32 pairs in training)
 constexpr int HS = 68;             // padded LDS row of bf16 tiles (K = 64)
+constexpr int MLP_GRID = 1024;     // most blocks of mlp_features_kernel
 constexpr size_t STAGE_LDS_CAP = 96 * 1024;
 
 typedef short s4v __attribute__((ext_vector_type(4)));
@@ -199,8 +200,9 @@ struct MlpArgs {
     int R;
 };
 
-// Learned features of 64 points per block: layer 1 on the VALU, layers 2 and 3
-// as 16x16x16 bf16 MFMA tiles (wave w owns points 16w..16w+15).
+// Learned features, 64 points per tile: layer 1 on the VALU, layers 2 and 3
+// as 16x16x16 bf16 MFMA tiles (wave w owns points 16w..16w+15).  A block
+// stages the weights once and takes every gridDim.x-th tile.
 __global__ __launch_bounds__(256) void mlp_features_kernel(const float *__restrict__ X, int64_t n, MlpArgs m,
                                                            float *__restrict__ F) {
     __shared__ uint16_t sW2[HID * HS], sW3[HID * HS], sH1[TILE_PTS * HS], sH2[TILE_PTS * HS];
@@ -216,56 +218,60 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const float *__restri
         sb2[t] = m.params[po.b2 + t];
     }
     if (t < R) sb3[t] = m.params[po.b3 + t];
-    const int64_t p0 = (int64_t)blockIdx.x * TILE_PTS;
-    if (m.comm_of) {
-        const int64_t p = p0 + (t >> 2);
-        int need = 0;
-        if (p < n) {
-            const int c = m.comm_of[p];
-            need = c >= 0 && !(m.fb && m.fb[c]);
+    const int64_t ntiles = (n + TILE_PTS - 1) / TILE_PTS;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t p0 = tile * TILE_PTS;
+        if (m.comm_of) {
+            const int64_t p = p0 + (t >> 2);
+            int need = 0;
+            if (p < n) {
+                const int c = m.comm_of[p];
+                need = c >= 0 && !(m.fb && m.fb[c]);
+            }
+            if (!__syncthreads_or(need)) continue;  // the whole block skips the tile
         }
-        if (!__syncthreads_or(need)) return;  // the whole block leaves together
-    }
-    {
-        // layer 1: thread t -> point t/4, hidden units 16*(t%4) .. +15
-        const int pl = t >> 2, g = (t & 3) * 16;
-        const int64_t p = p0 + pl;
-        float u0 = 0.f, u1 = 0.f, u2 = 0.f;
-        if (p < n) {
-            u0 = X[p] * m.scale[0] + m.shift[0];
-            u1 = X[n + p] * m.scale[1] + m.shift[1];
-            u2 = X[2 * n + p] * m.scale[2] + m.shift[2];
+        {
+            // layer 1: thread t -> point t/4, hidden units 16*(t%4) .. +15
+            const int pl = t >> 2, g = (t & 3) * 16;
+            const int64_t p = p0 + pl;
+            float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+            if (p < n) {
+                u0 = X[p] * m.scale[0] + m.shift[0];
+                u1 = X[n + p] * m.scale[1] + m.shift[1];
+                u2 = X[2 * n + p] * m.scale[2] + m.shift[2];
+            }
+            __syncthreads();  // weights in LDS; the previous tile's layer 2 is done with sH1
+            for (int o = g; o < g + 16; o++) {
+                float z = sb1[o] + sW1[o * 3] * u0 + sW1[o * 3 + 1] * u1 + sW1[o * 3 + 2] * u2;
+                sH1[pl * HS + o] = to_bf16(silu_f(z));
+            }
         }
-        __syncthreads();  // weights in LDS
-        for (int o = g; o < g + 16; o++) {
-            float z = sb1[o] + sW1[o * 3] * u0 + sW1[o * 3 + 1] * u1 + sW1[o * 3 + 2] * u2;
-            sH1[pl * HS + o] = to_bf16(silu_f(z));
-        }
-    }
-    __syncthreads();
-    // layer 2: H2 = silu(H1 W2^T + b2)
-    const int mrow = 16 * w;
-    for (int nt = 0; nt < HID / 16; nt++) {
-        f4v acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma16(sH1 + mrow * HS, HS, 1, sW2 + nt * 16 * HS, HS, 1, HID, acc);
-        const int col = nt * 16 + (lane & 15);
+        __syncthreads();
+        // layer 2: H2 = silu(H1 W2^T + b2)
+        const int mrow = 16 * w;
+        for (int nt = 0; nt < HID / 16; nt++) {
+            f4v acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mma16(sH1 + mrow * HS, HS, 1, sW2 + nt * 16 * HS, HS, 1, HID, acc);
+            const int col = nt * 16 + (lane & 15);
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int row = mrow + (lane >> 4) * 4 + q;
-            sH2[row * HS + col] = to_bf16(silu_f(acc[q] + sb2[col]));
+            for (int q = 0; q < 4; q++) {
+                const int row = mrow + (lane >> 4) * 4 + q;
+                sH2[row * HS + col] = to_bf16(silu_f(acc[q] + sb2[col]));
+            }
         }
-    }
-    __syncthreads();
-    // layer 3: F = H2 W3^T + b3
-    for (int nt = 0; nt < R / 16; nt++) {
-        f4v acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma16(sH2 + mrow * HS, HS, 1, sW3 + nt * 16 * HS, HS, 1, HID, acc);
-        const int col = nt * 16 + (lane & 15);
+        __syncthreads();
+        // layer 3: F = H2 W3^T + b3
+        for (int nt = 0; nt < R / 16; nt++) {
+            f4v acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mma16(sH2 + mrow * HS, HS, 1, sW3 + nt * 16 * HS, HS, 1, HID, acc);
+            const int col = nt * 16 + (lane & 15);
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int64_t p = p0 + mrow + (lane >> 4) * 4 + q;
-            if (p < n) F[p * R + col] = acc[q] + sb3[col];
+            for (int q = 0; q < 4; q++) {
+                const int64_t p = p0 + mrow + (lane >> 4) * 4 + q;
+                if (p < n) F[p * R + col] = acc[q] + sb3[col];
+            }
         }
+        __syncthreads();  // layer 3 is done with sH2 before the next tile's layer 2
     }
 }
 
@@ -273,19 +279,20 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const float *__restri
 // E1: per-community sums P_cr = sum f_r, V_cr = sum f_r v (FP64 accumulation)
 // --------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void flock_e1_kernel(const float *__restrict__ F, const float *__restrict__ Y,
+constexpr int E1_BLOCK = 1024;   // threads of flock_e1_kernel (G of them per item)
+__global__ __launch_bounds__(E1_BLOCK) void flock_e1_kernel(const float *__restrict__ F, const float *__restrict__ Y,
                                                        int64_t n, const int32_t *__restrict__ comm_off, int Rp,
                                                        const int32_t *__restrict__ fb, float *__restrict__ Q) {
-    __shared__ double part[256];
+    __shared__ double part[E1_BLOCK];
     const int c = blockIdx.x, t = threadIdx.x;
     if (fb && fb[c]) return;  // exact fallback: no observables needed (whole block)
     const int c0 = comm_off[c], c1 = comm_off[c + 1];
     const int items = Rp * 4;
     // G threads share an item and take every G-th row; four independent
     // accumulators keep several loads in flight
-    const int G = items >= 256 ? 1 : 256 / items;
-    for (int base = 0; base < items; base += 256 / G) {
-        const int item = base + t % (256 / G), ph = t / (256 / G);
+    const int G = items >= E1_BLOCK ? 1 : E1_BLOCK / items;
+    for (int base = 0; base < items; base += E1_BLOCK / G) {
+        const int item = base + t % (E1_BLOCK / G), ph = t / (E1_BLOCK / G);
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         if (item < items && ph < G) {
             const int r = item >> 2, q = item & 3;
@@ -312,7 +319,7 @@ __global__ __launch_bounds__(256) void flock_e1_kernel(const float *__restrict__
         __syncthreads();
         if (ph == 0 && item < items) {
             double v = part[t];
-            for (int g = 1; g < G; g++) v += part[t + g * (256 / G)];
+            for (int g = 1; g < G; g++) v += part[t + g * (E1_BLOCK / G)];
             Q[((int64_t)c * Rp + (item >> 2)) * 4 + (item & 3)] = (float)v;
         }
         __syncthreads();
@@ -1316,7 +1323,9 @@ cia_status run_features(cia_plan *p, const float *X, int64_t n, float *F, hipStr
         MlpArgs m = mlp_args(f);
         m.comm_of = comm_of;
         m.fb = fb;
-        mlp_features_kernel<<<grid_for(n, TILE_PTS), 256, 0, s>>>(X, n, m, F);
+        // about four blocks per CU, each staging the weights once
+        const int64_t ntiles = (n + TILE_PTS - 1) / TILE_PTS;
+        mlp_features_kernel<<<(int)std::min<int64_t>(ntiles, MLP_GRID), 256, 0, s>>>(X, n, m, F);
     }
     CIA_HIP(hipGetLastError());
     return CIA_OK;
@@ -1331,7 +1340,7 @@ cia_status run_observables(cia_plan *p, const float *Ys, bool judge, hipStream_t
     // other stages skip communities held on the exact fallback
     const int32_t *skip = (judge && f->judge) ? nullptr : f->fb;
     CIA_TRY(run_features(p, Ys, p->n, f->F, s, f->comm_of, skip));
-    flock_e1_kernel<<<f->ncomm, 256, 0, s>>>(f->F, Ys, p->n, f->comm_off, f->Rp, skip, f->Q);
+    flock_e1_kernel<<<f->ncomm, E1_BLOCK, 0, s>>>(f->F, Ys, p->n, f->comm_off, f->Rp, skip, f->Q);
     CIA_HIP(hipGetLastError());
     if (judge && f->judge) {
         JudgeArgs j{};
