@@ -42,10 +42,11 @@ namespace cia {
 namespace {
 
 constexpr int HID = 64;            // hidden width of the learned basis
-constexpr int TPR = 4;             // threads per row in the stage kernel
+constexpr int TPR = 2;             // threads per row in the stage kernel
 constexpr int CHUNK_ROWS = 256;    // rows per chunk of the stage kernel
 constexpr int FBLOCK = CHUNK_ROWS * TPR;
 constexpr int EXACT_RT = 2;        // lanes per row of flock_exact_kernel
+static_assert(TPR == EXACT_RT, "both stage kernels read the same S-neg slices");
 constexpr int JUDGE_SAMPLES = 16;  // sampled members per community and step
 constexpr int TRAIN_PAIRS = 4096;  // pairs per optimiser step
 constexpr int TILE_PTS = 64;       // points per MFMA tile (32 pairs in training)
@@ -397,13 +398,14 @@ __device__ inline void flock_emit(const FlockArgs &a, int64_t i, const float k[6
 }
 
 // Chunks of the communities on a basis (the expansion of the weight, E1 and
-// E2 of App. A.6): four lanes per row (each takes every fourth partner, then
-// the row's sums are combined across the group); the block covers up to 256
+// E2 of App. A.6): two lanes per row (each takes every other partner, then
+// the row's sums are combined across the pair); the block covers up to 256
 // rows of one community.  Staged chunks copy the community's state planes and
-// features into LDS first.  RP > 0 fixes the feature stride at compile time
-// (own features held in registers); RP == 0 reads it from the arguments.
-// Chunks on the exact path (fallback communities, rows of no community) are
-// flock_exact_kernel's.
+// features into LDS first.  The S-neg pairs come from the slices of
+// flock_exact_kernel where the chunk has them (rows in the slices' order).
+// RP > 0 fixes the feature stride at compile time (own features held in
+// registers); RP == 0 reads it from the arguments.  Chunks on the exact path
+// (fallback communities, rows of no community) are flock_exact_kernel's.
 template <int RP>
 __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
     extern __shared__ float lds[];
@@ -459,8 +461,9 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
     // wavefront); whole groups past the chunk leave together
     const int rloc = (int)threadIdx.x / TPR, sub = (int)threadIdx.x % TPR;
     if (rloc >= ch.rows) return;  // no barrier below
-
-    const int64_t i = ch.row0 + rloc;
+    // chunks with S-neg slices take their rows in the slices' order
+    const bool sliced = ch.sbase >= 0;
+    const int64_t i = ch.row0 + (sliced ? (int)a.srow[ch.row0 + rloc] : rloc);
     float xi[3], vi[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
@@ -506,8 +509,7 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
     acc[1] = sV1 - vi[1] * sP;
     acc[2] = sV2 - vi[2] * sP;
     // E2, S-neg: subtract the expanded weight of the missing intra pairs
-    for (int64_t e = e0 + sub; e < e1; e += TPR) {
-        const int jl = a.neg[e];
+    auto sneg_pair = [&](int jl, bool in) {
         const float *fj = staged ? sF + (int64_t)jl * Rp : a.F + (c0 + jl) * Rp;
         float wt = 0.f;
         if (RP > 0) {
@@ -519,10 +521,21 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
         } else {
             for (int r = 0; r < Rp; r++) wt += a.sgn[r] * fi[r] * fj[r];
         }
+        wt = in ? wt : 0.f;
         float xj[3], vj[3];
         member(jl, xj, vj);
 #pragma unroll
         for (int d = 0; d < 3; d++) acc[d] -= wt * (vj[d] - vi[d]);
+    };
+    if (sliced) {
+        // the wavefront's slice: entry k of its rows in one coalesced load
+        constexpr int SR = 64 / TPR;
+        const int sl = ch.sbase + rloc / SR, rs = rloc % SR;
+        const uint16_t *sp = a.sneg + a.sneg_off[sl];
+        const int sw = a.sneg_w[sl], len = (int)(e1 - e0);
+        for (int k = sub; k < sw; k += TPR) sneg_pair(sp[(int64_t)k * SR + rs], k < len);
+    } else {
+        for (int64_t e = e0 + sub; e < e1; e += TPR) sneg_pair(a.neg[e], true);
     }
     // E2, S-pos: exact weight on the pairs leaving the community
     for (int64_t e = a.posptr[i] + sub, e1 = a.posptr[i + 1]; e < e1; e += TPR) {
@@ -1393,7 +1406,7 @@ cia_status launch_stage(cia_plan *p, const FlockArgs &a0, hipStream_t s) {
             case 28: flock_stage_kernel<28><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
             case 32: flock_stage_kernel<32><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
             case 48: flock_stage_kernel<48><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
-            // 64 cached features would spill registers at 1024 threads per block
+            // 64 features cached in registers would cost too many of them
             default: flock_stage_kernel<0><<<f->nchunks, FBLOCK, lds, s>>>(a); break;
         }
     }
