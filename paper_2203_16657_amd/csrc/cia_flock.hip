@@ -56,6 +56,7 @@ constexpr size_t STAGE_LDS_CAP = 96 * 1024;
 
 typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 struct FlockChunk {
     int32_t row0, rows, comm, staged;
@@ -100,22 +101,35 @@ __host__ __device__ inline uint64_t mix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
-// One 16x16 tile C += A * B^T over K (multiple of 16) with bf16 MFMA and
+// One 16x16 tile C += A * B^T over K (a multiple of 16) with bf16 MFMA and
 // FP32 accumulation.  Element (m, k) of A is A[m*am + k*ak] and element
 // (n, k) of B is B[n*bn + k*bk] (tile origins already applied), so any
-// operand orientation in LDS is read in place.  Lane l supplies row m = l%16
-// and k = 4*(l/16)..+3 of each 16-wide k block; the result element t of
-// lane l is C[4*(l/16) + t][l%16].
+// operand orientation in LDS is read in place.  Each 32-wide k block is one
+// gfx950 16x16x32 step (lane l supplies row m = l%16 and k = 8*(l/16)..+7 of
+// the block), a last 16-wide block one 16x16x16 step (k = 4*(l/16)..+3); the
+// result element t of lane l is C[4*(l/16) + t][l%16].
 __device__ inline f4v mma16(const uint16_t *A, int am, int ak, const uint16_t *B, int bn, int bk, int K,
                             f4v acc) {
     const int lane = threadIdx.x & 63;
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    const int r = lane & 15;
+    int k0 = 0;
+    for (; k0 + 32 <= K; k0 += 32) {
+        const int kq = k0 + (lane >> 4) * 8;
+        bf8v a, b;
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            a[t] = __builtin_bit_cast(__bf16, A[r * am + (kq + t) * ak]);
+            b[t] = __builtin_bit_cast(__bf16, B[r * bn + (kq + t) * bk]);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    if (k0 < K) {
+        const int kq = k0 + (lane >> 4) * 4;
         s4v a, b;
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-            a[t] = (short)A[r * am + (k0 + kq + t) * ak];
-            b[t] = (short)B[r * bn + (k0 + kq + t) * bk];
+            a[t] = (short)A[r * am + (kq + t) * ak];
+            b[t] = (short)B[r * bn + (kq + t) * bk];
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
     }
