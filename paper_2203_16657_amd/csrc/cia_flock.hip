@@ -781,8 +781,7 @@ __global__ __launch_bounds__(256) void flock_direct_kernel(FlockArgs a) {
         for (int d = 0; d < 3; d++) acc[d] += w * (a.Ys[(3 + d) * n + j] - vi[d]);
     }
 #pragma unroll
-    for (int d = 0; d < 3; d++)
-        for (int off = 32; off > 0; off >>= 1) acc[d] += __shfl_xor(acc[d], off);
+    for (int d = 0; d < 3; d++) acc[d] = wave_sum(acc[d]);
     if (lane == 0) {
         const float k[6] = {vi[0], vi[1], vi[2], acc[0] * a.invN, acc[1] * a.invN, acc[2] * a.invN};
         flock_emit(a, i, k);
