@@ -570,18 +570,20 @@ __global__ __launch_bounds__(FBLOCK) void flock_stage_kernel(FlockArgs a) {
 }
 
 // Exact community path: the community sums of App. A.6 eq. (Cucker_Smale)
-// taken pair by pair, with RT lanes per row.  The dense sum runs over every
-// member of the row's community four members at a time, each plane read as a
-// 16-byte LDS broadcast (every lane of a row group takes the same members);
+// taken pair by pair, with RT lanes per row.  The community's state is staged
+// in LDS as three pair planes {s_x, s_y}, {s_z, v_x}, {v_y, v_z}.  The dense
+// sum runs over every member of the row's community four members at a time,
+// two 16-byte LDS broadcasts per pair plane (every lane of a row group takes
+// the same members);
 // where s2 is a normal float and s2^(-beta) finite it sums w v_j and w and
 // subtracts v_i times the weight sum once (the self pair then adds exactly
 // 0), otherwise the self pair is masked and the clamp of cs_weight applies.
 // The S-neg pairs are then subtracted: a staged chunk's rows run in order of
 // decreasing S-neg length, and the S-neg of the 64 / RT rows of a wavefront
 // is a slice whose k-th entries lie together (one coalesced load of 16-bit
-// member indices per step, members gathered from LDS).  Last the S-pos pairs
-// are added.  Rows of no community take only their S-pos pairs.  Weights
-// are taken without K, which multiplies the row's total.  Chunks of
+// member indices per step, each member three 8-byte LDS gathers).  Last the
+// S-pos pairs are added.  Rows of no community take only their S-pos pairs.
+// Weights are taken without K, which multiplies the row's total.  Chunks of
 // communities on a basis are left to flock_stage_kernel.
 template <int RT>
 __global__ __launch_bounds__(CHUNK_ROWS * RT) void flock_exact_kernel(FlockArgs a) {
@@ -600,7 +602,10 @@ __global__ __launch_bounds__(CHUNK_ROWS * RT) void flock_exact_kernel(FlockArgs 
     if (!fb) return;   // before any barrier
     const int lamp = (lam + 3) & ~3;   // plane stride, a multiple of 4 floats
     const bool staged = c >= 0 && (int64_t)6 * lamp * (int64_t)sizeof(float) <= (int64_t)a.exact_lds;
-    float *sY = lds;                   // [6][lamp], pad entries 0
+    // the state as three pair planes [3][lamp] of {s_x, s_y}, {s_z, v_x},
+    // {v_y, v_z} (state dimension d is component d mod 2 of plane d / 2),
+    // pad entries 0
+    float *sY = lds;
     if (staged) {
         constexpr int US = 8;          // loads in flight per thread before the LDS writes
         const int ny = 6 * lamp;
@@ -613,10 +618,14 @@ __global__ __launch_bounds__(CHUNK_ROWS * RT) void flock_exact_kernel(FlockArgs 
                 v[u] = q < ny && j < lam ? a.Ys[d * n + c0 + j] : 0.f;
             }
 #pragma unroll
-            for (int u = 0; u < US; u++)
-                if (q0 + u * CHUNK_ROWS * RT < ny) sY[q0 + u * CHUNK_ROWS * RT] = v[u];
+            for (int u = 0; u < US; u++) {
+                const int q = q0 + u * CHUNK_ROWS * RT;
+                const int d = q / lamp, j = q - d * lamp;
+                if (q < ny) sY[(d >> 1) * 2 * lamp + 2 * j + (d & 1)] = v[u];
+            }
         }
     }
+    const float2 *PP = reinterpret_cast<const float2 *>(sY);   // PP[p * lamp + j]
     __syncthreads();
     const int rloc = (int)threadIdx.x / RT, sub = (int)threadIdx.x % RT;
     if (rloc >= ch.rows) return;   // no barrier below
@@ -643,26 +652,28 @@ __global__ __launch_bounds__(CHUNK_ROWS * RT) void flock_exact_kernel(FlockArgs 
     if (c >= 0) {
         const int il = (int)(i - c0);
         if (staged) {
-            // whole groups of four members as 16-byte LDS broadcasts
-            const float4 *P0 = reinterpret_cast<const float4 *>(sY);
-            const int g4 = lamp >> 2, gfull = lam >> 2;
+            // whole groups of four members, two 16-byte LDS broadcasts per
+            // pair plane
+            const float4 *P4 = reinterpret_cast<const float4 *>(sY);   // P4[p * lamp / 2 + 2 g + h]
+            const int h4 = lamp >> 1, gfull = lam >> 2;
             // plain: sum w v_j and w, and take v_i times the weight sum once
             float aw[4] = {0.f, 0.f, 0.f, 0.f};
             auto groups = [&](auto plain) {
 #pragma unroll 2
                 for (int g = sub; g < gfull; g += RT) {
-                    float4 X[3], V[3];
+                    float4 Q[3][2];
 #pragma unroll
-                    for (int d = 0; d < 3; d++) {
-                        X[d] = P0[d * g4 + g];
-                        V[d] = P0[(3 + d) * g4 + g];
+                    for (int p = 0; p < 3; p++) {
+                        Q[p][0] = P4[p * h4 + 2 * g];
+                        Q[p][1] = P4[p * h4 + 2 * g + 1];
                     }
-                    const float xs[3][4] = {{X[0].x, X[0].y, X[0].z, X[0].w},
-                                            {X[1].x, X[1].y, X[1].z, X[1].w},
-                                            {X[2].x, X[2].y, X[2].z, X[2].w}};
-                    const float vs[3][4] = {{V[0].x, V[0].y, V[0].z, V[0].w},
-                                            {V[1].x, V[1].y, V[1].z, V[1].w},
-                                            {V[2].x, V[2].y, V[2].z, V[2].w}};
+                    // member u: dimension 2p + e is component 2 (u & 1) + e of Q[p][u >> 1]
+                    const float xs[3][4] = {{Q[0][0].x, Q[0][0].z, Q[0][1].x, Q[0][1].z},
+                                            {Q[0][0].y, Q[0][0].w, Q[0][1].y, Q[0][1].w},
+                                            {Q[1][0].x, Q[1][0].z, Q[1][1].x, Q[1][1].z}};
+                    const float vs[3][4] = {{Q[1][0].y, Q[1][0].w, Q[1][1].y, Q[1][1].w},
+                                            {Q[2][0].x, Q[2][0].z, Q[2][1].x, Q[2][1].z},
+                                            {Q[2][0].y, Q[2][0].w, Q[2][1].y, Q[2][1].w}};
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
                         if constexpr (decltype(plain)::value) {
@@ -690,9 +701,11 @@ __global__ __launch_bounds__(CHUNK_ROWS * RT) void flock_exact_kernel(FlockArgs 
             // the last lam mod 4 members
             for (int j = 4 * gfull + sub; j < lam; j += RT) {
                 if (j == il) continue;
-                const float w = wt(sY[j] - xi[0], sY[lamp + j] - xi[1], sY[2 * lamp + j] - xi[2]);
-#pragma unroll
-                for (int d = 0; d < 3; d++) acc[d] += w * (sY[(3 + d) * lamp + j] - vi[d]);
+                const float2 A = PP[j], B = PP[lamp + j], C = PP[2 * lamp + j];
+                const float w = wt(A.x - xi[0], A.y - xi[1], B.x - xi[2]);
+                acc[0] += w * (B.y - vi[0]);
+                acc[1] += w * (C.x - vi[1]);
+                acc[2] += w * (C.y - vi[2]);
             }
         } else {
             for (int j = sub; j < lam; j += RT) {
@@ -716,11 +729,13 @@ __global__ __launch_bounds__(CHUNK_ROWS * RT) void flock_exact_kernel(FlockArgs 
 #pragma unroll 4
                 for (int k = sub; k < sw; k += RT) {
                     const int jl = sp[(int64_t)k * SR + rs];
-                    const float d0 = sY[jl] - xi[0], d1 = sY[lamp + jl] - xi[1], d2 = sY[2 * lamp + jl] - xi[2];
+                    const float2 A = PP[jl], B = PP[lamp + jl], C = PP[2 * lamp + jl];
+                    const float d0 = A.x - xi[0], d1 = A.y - xi[1], d2 = B.x - xi[2];
                     float w = decltype(plain)::value ? wt_plain(d0, d1, d2) : wt(d0, d1, d2);
                     w = k < len ? w : 0.f;
-#pragma unroll
-                    for (int d = 0; d < 3; d++) acc[d] -= w * (sY[(3 + d) * lamp + jl] - vi[d]);
+                    acc[0] -= w * (B.y - vi[0]);
+                    acc[1] -= w * (C.x - vi[1]);
+                    acc[2] -= w * (C.y - vi[2]);
                 }
             };
             if (a.plain)
@@ -728,13 +743,15 @@ __global__ __launch_bounds__(CHUNK_ROWS * RT) void flock_exact_kernel(FlockArgs 
             else
                 sneg(std::integral_constant<bool, false>());
         } else {
+            // a community above the staging cap (no slices): members from
+            // global memory
             for (int64_t e = a.negptr[i] + sub, e1 = a.negptr[i + 1]; e < e1; e += RT) {
                 const int jl = a.neg[e];
                 float xj[3], vj[3];
 #pragma unroll
                 for (int d = 0; d < 3; d++) {
-                    xj[d] = staged ? sY[d * lamp + jl] : a.Ys[d * n + c0 + jl];
-                    vj[d] = staged ? sY[(3 + d) * lamp + jl] : a.Ys[(3 + d) * n + c0 + jl];
+                    xj[d] = a.Ys[d * n + c0 + jl];
+                    vj[d] = a.Ys[(3 + d) * n + c0 + jl];
                 }
                 const float w = wt(xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]);
 #pragma unroll
