@@ -453,7 +453,8 @@ typedef struct cia_plan_info {
                                  chunk, and the sums written), 0 if there is none */
     int32_t resident;         /* 1: cia_integrate runs the whole call in one resident
                                  workgroup (small single networks, see cia_integrate) */
-    int32_t reserved;
+    int32_t merged_slices;    /* FP32 phase plans with p = 1: 64-row slices whose +1 entries
+                                 are stored as one partner-sorted list of the slice */
 } cia_plan_info;
 
 cia_status cia_plan_get_info(const cia_plan *p, cia_plan_info *info);

@@ -68,7 +68,7 @@ class cia_plan_info(_c.Structure):
                 ("method", _c.c_int32), ("precision", _c.c_int32), ("model", _c.c_int32),
                 ("p", _c.c_int32), ("bytes_per_rhs", _c.c_double), ("bytes_per_stage", _c.c_double),
                 ("nnz_extra", _c.c_int64), ("judge_fallbacks", _c.c_int32), ("tiled_comms", _c.c_int32),
-                ("bytes_aux", _c.c_double), ("resident", _c.c_int32), ("reserved", _c.c_int32)]
+                ("bytes_aux", _c.c_double), ("resident", _c.c_int32), ("merged_slices", _c.c_int32)]
 
 
 class cia_tune_report(_c.Structure):

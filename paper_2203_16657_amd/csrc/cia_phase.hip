@@ -68,8 +68,16 @@ struct alignas(16) Slice {
     uint32_t beg[4];      // first 16-byte chunk of each stream's block
     int32_t w[4];         // chunks per lane of each stream
     int32_t tw;           // tiled communities: first entry of this slice's per-tile S-neg widths
-    int32_t pad1;         // keeps the descriptor at 48 bytes
+    int32_t sflags;       // SF_* (keeps the descriptor at 48 bytes)
 };
+
+// slice flag bits
+// SF_MERGED: the S-pos entries of the slice's rows form one stream sorted by
+// partner, each 32-bit entry the partner's position | (lane of the row << 26);
+// entry e sits in word (e % 256) / 64 of chunk e / 256 of lane e % 64, so the
+// 64 lanes of one gather read 64 consecutive partners.  Padding: the word n.
+constexpr int SF_MERGED = 1;
+constexpr int MERGE_ROW_SHIFT = 26;
 
 // A work unit (one block): a run of slices of one community or of the rows
 // outside every community, with everything needed to start in one load.
@@ -360,6 +368,67 @@ __device__ __forceinline__ void gather_staged_rows(cx<R> (&T)[P], const uint4 *_
         gather_rows<R, P, UG, false>(T, pos + (size_t)UG * SLICE, wp - UG, cs, th, pad, (R)1, padp);
 }
 
+// S-pos of a slice stored merged (SF_MERGED): the wavefront walks the
+// partner-sorted stream of all its rows, so the 64 lanes of one gather read
+// neighbouring partners and share cache lines, and each lane adds its z into
+// the sum of the entry's row in LDS (acc: [64] x sums then [64] y sums) as a
+// 64-bit fixed-point integer in units of 2^-40.  Integer sums do not depend on
+// the order of the additions, so the result is deterministic; |cos|, |sin| <= 1
+// keeps a row of up to 2^23 entries from overflowing.  Lane l then adds row l's
+// sum to T.  Every lane of the wavefront takes part (uniform w).
+template <int U>
+__device__ __forceinline__ void merged_pos_sum(cx<float> &T, const uint4 *__restrict__ col, int w,
+                                               const float *__restrict__ th, uint32_t pad,
+                                               unsigned long long *acc) {
+    const int lane = threadIdx.x & 63;
+    constexpr uint32_t MASK = (1u << MERGE_ROW_SHIFT) - 1;
+    __hip_atomic_store(acc + lane, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_store(acc + 64 + lane, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __builtin_amdgcn_wave_barrier();
+    const uint4 padv = make_uint4(pad, pad, pad, pad);
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) v[u] = u < w ? ld_stream(col + (size_t)u * SLICE) : padv;
+    for (int k = 0; k < w; k += U) {
+        uint4 vn[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) vn[u] = k + U + u < w ? ld_stream(col + (size_t)(k + U + u) * SLICE) : padv;
+        float t[U][4];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            t[u][0] = th[v[u].x & MASK];
+            t[u][1] = th[v[u].y & MASK];
+            t[u][2] = th[v[u].z & MASK];
+            t[u][3] = th[v[u].w & MASK];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint32_t q4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                float sn, c0;
+                dsincos(t[u][q], &sn, &c0);
+                if (q4[q] != pad) {
+                    const int row = (int)(q4[q] >> MERGE_ROW_SHIFT);
+                    const long long fx = (long long)__builtin_rintf(c0 * 0x1p40f);
+                    const long long fy = (long long)__builtin_rintf(sn * 0x1p40f);
+                    __hip_atomic_fetch_add(acc + row, (unsigned long long)fx, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    __hip_atomic_fetch_add(acc + 64 + row, (unsigned long long)fy, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = vn[u];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const long long sx = (long long)__hip_atomic_load(acc + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const long long sy = (long long)__hip_atomic_load(acc + 64 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    T.x += (float)sx * 0x1p-40f;
+    T.y += (float)sy * 0x1p-40f;
+}
+
 // S-neg chunks of one lane gathered from the staged z in LDS: 8 uint16 byte
 // offsets per chunk, UL chunks per batch (a tile of a tiled community).
 template <typename R, int P, int UL>
@@ -460,9 +529,11 @@ __device__ __forceinline__ const double *gen_d(const R *g) {
 // communities is compiled in (F32 plans that have such communities).
 // TRI: the triadic term of the higher-order model (P = 2 observables give
 // S1 = sum z and S2 = sum z^2 per community).
-template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE, bool TRI, bool GEN = false>
+// MERGE: FP32 plans with P = 1 whose S-pos has slices stored merged.
+template <typename R, int P, int BLOCK, bool DIRECT, bool WIDE, bool TRI, bool GEN = false, bool MERGE = false>
 __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     constexpr int NW = BLOCK / 64;
+    constexpr bool MG = MERGE && sizeof(R) == 4 && P == 1 && !DIRECT && !TRI && !GEN;
     constexpr int UL = P >= 4 ? 2 : 8 / P;  // chunks per batch, LDS-gathered rows
     constexpr int UG = P >= 2 ? 1 : 2;      // chunks per batch, global-gathered rows (two in flight)
     extern __shared__ __align__(16) unsigned char smem[];
@@ -471,6 +542,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     __shared__ float red_s[NW][2 * P], red_c[NW][2 * P];
     __shared__ double red_d[NW][2 * P];
     __shared__ double2 red_r[NW];
+    __shared__ unsigned long long macc[MG ? NW : 1][128];   // merged S-pos row sums, per wavefront
 
     const Unit Un = a.units[blockIdx.x];
     const int tid = threadIdx.x;
@@ -622,10 +694,12 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
         cx<R> T[P];
 #pragma unroll
         for (int k = 0; k < P; k++) T[k].x = T[k].y = (R)0;
+        const bool merged = MG && (S.sflags & SF_MERGED) != 0;
+        const int wpos = merged ? 0 : S.w[1];
         if (gather) {
             if (!DIRECT && staged) {
                 gather_staged_rows<R, P, UL, UG>(T, a.negdata + S.beg[0] + lane, S.w[0], a.posdata + S.beg[1] + lane,
-                                                 S.w[1], zsh, a.cs_in, a.th_in, a.pad_pos, padl, padp);
+                                                 wpos, zsh, a.cs_in, a.th_in, a.pad_pos, padl, padp);
             } else {
                 if (WIDE && tiled) {
                     // S-neg summed tile by tile above (static indexing keeps Tn in registers)
@@ -636,7 +710,11 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
                             for (int k = 0; k < P; k++) T[k].x += Tn[j][k].x, T[k].y += Tn[j][k].y;
                 } else if (!DIRECT)
                     gather_rows<R, P, UG, false>(T, a.negdata + S.beg[0] + lane, S.w[0], a.cs_in, a.th_in, a.pad_pos, (R)-1, padp);
-                gather_rows<R, P, UG, DIRECT>(T, a.posdata + S.beg[1] + lane, S.w[1], a.cs_in, a.th_in, a.pad_pos, (R)1, padp);
+                gather_rows<R, P, UG, DIRECT>(T, a.posdata + S.beg[1] + lane, wpos, a.cs_in, a.th_in, a.pad_pos, (R)1, padp);
+            }
+            if constexpr (MG) {
+                if (merged)
+                    merged_pos_sum<UG>(T[0], a.posdata + S.beg[1] + lane, S.w[1], a.th_in, a.pad_pos, macc[wid]);
             }
         }
         cx<R> Mt = {(R)0, (R)0}, Xt = {(R)0, (R)0};   // missing intra / cross hyperedge pair sums
@@ -1923,6 +2001,7 @@ struct PhaseState {
     bool f64 = false, direct = false, complete_direct = false;
     int block = 256;
     bool has_wide = false;   // F32 plan with a community beyond the LDS cap (FP64 observables or tiled)
+    bool merged = false;     // some S-pos slices stored merged (SF_MERGED)
     bool tri = false;        // triadic model
     bool poly = false;       // polynomial difference coupling
     void *gen = nullptr;     // general coupling coefficients on the device (R), or NULL
@@ -2044,7 +2123,7 @@ static inline void tile_shape(int64_t lam, int64_t tile_cap, int64_t &nt, int64_
 
 static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, int32_t ncomm,
                              const std::vector<char> &seg_staged, const StreamIn (&S)[4], uint32_t zscale,
-                             Sell &out, int64_t tile_cap = 0) {
+                             Sell &out, int64_t tile_cap = 0, bool merge_pos = false) {
     const int32_t nseg = ncomm + 1;
     std::vector<int64_t> sb(nseg + 1);
     for (int32_t c = 0; c <= ncomm; c++) sb[c] = c < ncomm ? comm_off[c] : (ncomm ? comm_off[ncomm] : 0);
@@ -2100,6 +2179,34 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
             std::sort(v, v + m);
         }
     }
+    // S-pos slices stored merged (SF_MERGED, FP32 plans with P = 1): those
+    // whose partners are dense enough that 64 consecutive ones of the sorted
+    // stream lie within a few cache lines (on average at most MERGE_SPAN nodes
+    // apart), and long enough that the padding to 256 entries is small
+    constexpr int64_t MERGE_MIN = 256, MERGE_SPAN = 8;
+    std::vector<int64_t> sl_first(nseg + 1, 0);
+    for (int32_t c = 0; c < nseg; c++) sl_first[c + 1] = sl_first[c] + (sb[c + 1] - sb[c] + SLICE - 1) / SLICE;
+    std::vector<int64_t> mcount;   // merged S-pos entries per slice, 0 = one row per lane
+    if (merge_pos && S[1].ptr && n < ((int64_t)1 << MERGE_ROW_SHIFT)) {
+        mcount.assign(sl_first[nseg], 0);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t k = 0; k < sl_first[nseg]; k++) {
+            const int32_t c = (int32_t)(std::upper_bound(sl_first.begin(), sl_first.end(), k) - sl_first.begin()) - 1;
+            const int64_t r = sb[c] + (k - sl_first[c]) * SLICE, rows = std::min<int64_t>(SLICE, sb[c + 1] - r);
+            int64_t tot = 0;
+            int32_t lo = INT32_MAX, hi = -1;
+            for (int64_t l = 0; l < rows; l++) {
+                const int64_t o = oldpos[r + l];
+                for (int64_t e = (*S[1].ptr)[o]; e < (*S[1].ptr)[o + 1]; e++) {
+                    const int32_t pn = out.newpos[S[1].val[e]];
+                    lo = std::min(lo, pn);
+                    hi = std::max(hi, pn);
+                }
+                tot += len(1, o);
+            }
+            if (tot >= MERGE_MIN && (int64_t)hi - lo + 1 <= MERGE_SPAN * tot) mcount[k] = tot;
+        }
+    }
     // slices and their widths
     out.slices.clear();
     out.tile_w.clear();
@@ -2128,6 +2235,10 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
                         out.tile_w.push_back((int32_t)wt);
                         w += wt;
                     }
+                } else if (q == 1 && !mcount.empty() && mcount[out.slices.size()] > 0) {
+                    // merged: 256 entries per chunk row (4 per lane)
+                    w = (mcount[out.slices.size()] + 4 * SLICE - 1) / (4 * SLICE);
+                    Sl.sflags |= SF_MERGED;
                 } else {
                     for (int l = 0; l < Sl.rows; l++) w = std::max(w, chunks(q, c, oldpos[r + l]));
                 }
@@ -2177,6 +2288,26 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
                         }
                     }
                     base += wt;
+                }
+                continue;
+            }
+            if (q == 1 && (Sl.sflags & SF_MERGED)) {
+                // every row's partners, sorted by (new position, lane)
+                std::vector<uint64_t> ent;
+                ent.reserve((size_t)Sl.w[q] * 4 * SLICE);
+                for (int l = 0; l < Sl.rows; l++) {
+                    const int64_t o = oldpos[Sl.row0 + l];
+                    for (int64_t e = (*S[q].ptr)[o]; e < (*S[q].ptr)[o + 1]; e++)
+                        ent.push_back(((uint64_t)out.newpos[S[q].val[e]] << 6) | (uint64_t)l);
+                }
+                std::sort(ent.begin(), ent.end());
+                uint32_t *w32 = reinterpret_cast<uint32_t *>(out.data[q].data() + Sl.beg[q]);
+                for (int64_t e = 0; e < (int64_t)Sl.w[q] * 4 * SLICE; e++) {
+                    const int64_t chunk = e / (4 * SLICE), word = (e % (4 * SLICE)) / SLICE, l = e % SLICE;
+                    uint32_t v = (uint32_t)n;
+                    if (e < (int64_t)ent.size())
+                        v = (uint32_t)(ent[e] >> 6) | ((uint32_t)(ent[e] & 63) << MERGE_ROW_SHIFT);
+                    w32[(chunk * SLICE + l) * 4 + word] = v;
                 }
                 continue;
             }
@@ -2516,7 +2647,7 @@ static bool res_attr_p(int P, size_t bytes) {
 static cia_status resident_setup(cia_plan *p, PhaseState *s, const cia_options *o) {
     s->resident = false;
     if (s->direct || s->complete_direct || s->tri || s->poly || s->gen || s->batch > 0 || s->has_wide) return CIA_OK;
-    if ((o->flags & CIA_FLAG_NO_RESIDENT) || s->P > RES_PMAX || s->h_slices.empty()) return CIA_OK;
+    if ((o->flags & CIA_FLAG_NO_RESIDENT) || s->P > RES_PMAX || s->h_slices.empty() || s->merged) return CIA_OK;
     // one CU's LDS serves every remainder gather of a stage: beyond about
     // 1.3e5 entries the stage-by-stage launches over all CUs are faster
     // (measured: 34K entries 1.6x faster resident, 280K equal, 2.5M 4x slower)
@@ -2731,7 +2862,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
                 S[3].val = xval.data();
                 S[3].pair = true;
             }
-            CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, S, (uint32_t)zbytes, sell, cap));
+            const bool merge_pos = !f64 && !s->poly && !s->tri && !gen && s->P == 1;
+            CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, S, (uint32_t)zbytes, sell, cap, merge_pos));
             s->tile_cap = (int32_t)cap;
             if (s->d0 != 0.0) {
                 // |S+| - |S-| per row (all zero for a complete graph)
@@ -2814,6 +2946,8 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
         const int32_t nc = s->direct ? 0 : p1.ncomm;
         s->unit_work = o->unit_work > 0 ? o->unit_work : 32768;
         s->h_slices = sell.slices;
+        for (const Slice &Sl : sell.slices)
+            if (Sl.sflags & SF_MERGED) s->merged = true;
         s->h_flags = o->flags;
         s->h_staged = comm_staged;
         if (s->direct) {
@@ -2862,6 +2996,9 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
     for (int32_t cc = 0; cc < p1.ncomm; cc++)
         if (!s->direct && comm_staged[cc] == SEG_TILED) tiledc++;
     inf.tiled_comms = tiledc;
+    inf.merged_slices = 0;
+    for (const Slice &Sl : s->h_slices)
+        if (Sl.sflags & SF_MERGED) inf.merged_slices++;
     inf.method = o->method;
     inf.precision = o->precision;
     inf.model = s->tri ? CIA_MODEL_TRIADIC : (s->poly ? CIA_MODEL_POLY : CIA_MODEL_PHASE);
@@ -3106,6 +3243,18 @@ static void launch_stage_v(PhaseState *s, const PhaseArgs<R> &a, hipStream_t st)
             hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, false, false, true>), g, b, s->smem, st, a);
         return;
       }
+    }
+    if constexpr (sizeof(R) == 4 && P == 1) {
+        if (s->merged) {
+            // plans with merged S-pos slices (built for FP32, P = 1 only)
+            if (s->has_wide)
+                hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, true, false, false, true>), g, b, s->smem, st,
+                                   a);
+            else
+                hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, false, false, false, false, true>), g, b, s->smem,
+                                   st, a);
+            return;
+        }
     }
     if (s->direct)
         hipLaunchKernelGGL((phase_stage_kernel<R, P, BLOCK, true, false, false>), g, b, s->smem, st, a);

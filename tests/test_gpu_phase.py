@@ -172,6 +172,53 @@ def test_wide_community_fp64_observables(env):
     plan.close()
 
 
+@pytest.mark.parametrize("unit_work,block", [(64, 256), (0, 512)])
+def test_rhs_merged_pos_slices(env, unit_work, block):
+    """Dense links between communities (FP32, p = 1): slices whose +1 lists
+    are stored as one partner-sorted list and summed per row in fixed point,
+    beside slices that keep one row per lane (sparse rows); one RHS against
+    the oracle, the same bits on a second plan, and an RK4 trajectory."""
+    cia, torch = env
+    rng = np.random.default_rng(31)
+    sizes = [1800, 1200, 640, 333, 64, 7]
+    n = sum(sizes) + 129
+    labels = W.shuffled_labels(sizes, n, rng)
+    g = W.sbm(labels, len(sizes), 0.8, p_out=0.04, seed=31)
+    theta = rng.uniform(0.0, 2 * np.pi, n)
+    omega = rng.standard_normal(n)
+    kw = dict(unit_work=unit_work, block=block)
+    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, None, K=2.5, **kw)
+    info = plan.info()
+    th = torch.as_tensor(theta, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(th)
+    plan.rhs(th, out)
+    out2 = torch.empty_like(th)
+    plan2 = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, None, K=2.5, **kw)
+    plan2.rhs(th, out2)
+    torch.cuda.synchronize()
+    plan.close()
+    plan2.close()
+    got = out.cpu().numpy().astype(np.float64)
+    want = oracle.phase_rhs(g.n, g.row_ptr, g.col, None, 2.5, [0, 1], [0, 0], th.cpu().numpy().astype(np.float64))
+    err = rel_inf(got, want)
+    say("merged S-pos rhs: slices merged", info.merged_slices, "units", info.nunits, "rel_inf", err)
+    assert info.merged_slices > 0
+    assert err <= TOL32
+    assert torch.equal(out, out2)
+
+    steps = 100
+    want_th, want_r = oracle.phase_integrate(g.n, g.row_ptr, g.col, omega, 2.5, [0, 1], [0, 0], theta, 0.01, steps)
+    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, omega, K=2.5, **kw)
+    th = torch.as_tensor(theta, dtype=torch.float32, device="cuda")
+    r = np.zeros(steps + 1)
+    plan.integrate(th, 0.01, steps, r)
+    plan.close()
+    circ = np.abs(np.angle(np.exp(1j * (th.cpu().numpy().astype(np.float64) - want_th))))
+    say("merged S-pos trajectory: max |dr|", np.abs(r - want_r).max(), "max circ", circ.max())
+    assert np.abs(r - want_r).max() < 1e-4
+    assert circ.max() < 1e-3
+
+
 def test_deterministic_bits(env):
     cia, torch = env
     P = W.random_phase_problem(5000, 6, seed=9, p=2)

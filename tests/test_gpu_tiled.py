@@ -108,3 +108,17 @@ def test_tiled_autotune_keeps_results(env, prob):
     scale = np.abs(before).max()
     assert np.abs(after - before).max() <= 1e-5 * scale
     plan.close()
+
+
+def test_tiled_with_merged_pos_slices(env):
+    """A tiled community (9000 nodes, two tiles) whose rows also have dense
+    links out (p_out 0.01): the tile-by-tile S-neg sums and the merged,
+    partner-sorted S-pos sums of the same slices, against the oracle."""
+    cia, _ = env
+    g, _, theta = big_problem([9000, 700, 300], 0.6, seed=43, p_out=0.01)
+    got, th_used, info = rhs(env, g, theta)
+    want = oracle.phase_rhs(g.n, g.row_ptr, g.col, None, 3.0, [0, 1], [0, 0], th_used)
+    err = float(np.abs(got - want).max() / np.abs(want).max())
+    say("tiled + merged: tiled", info.tiled_comms, "merged slices", info.merged_slices, "rel_inf", err)
+    assert info.tiled_comms == 1 and info.merged_slices > 0
+    assert err <= 1e-5
