@@ -181,9 +181,9 @@ def main():
         log("autotune: unit_work %d block %d (%.2f us vs %.2f us default, %d candidates)" % (
             rep.unit_work, rep.block, rep.best_us, rep.default_us, rep.candidates))
     info = plan.info()
-    log("cia plan: units=%d ncomm=%d nnz_neg=%d nnz_pos=%d unassigned=%d bytes/stage=%.3e (%.1fs)" % (
-        info.nunits, info.ncomm, info.nnz_neg, info.nnz_pos, info.n_unassigned, info.bytes_per_stage,
-        time.time() - t0))
+    log("cia plan: units=%d ncomm=%d nnz_neg=%d nnz_pos=%d unassigned=%d merged_slices=%d bytes/stage=%.3e (%.1fs)" % (
+        info.nunits, info.ncomm, info.nnz_neg, info.nnz_pos, info.n_unassigned, info.merged_slices,
+        info.bytes_per_stage, time.time() - t0))
     ms, tim, r, calls = time_integrate(plan, torch, P.theta0, P.dt, args.steps, args.warmup, timing_every=every,
                                        reps=args.reps)
     n = g.n
@@ -462,9 +462,9 @@ def bench_ensemble(args, cia, W, torch, np):
     info = plan.info()
     off = plan.offsets
     ntot = int(off[-1])
-    log("ensemble plan: N %d nnz %d units %d nnz_neg %d nnz_pos %d bytes/stage %.3e (finish %.0f s, all %.0f s)" % (
-        ntot, info.nnz_graph, info.nunits, info.nnz_neg, info.nnz_pos, info.bytes_per_stage, time.time() - tb,
-        time.time() - t0))
+    log("ensemble plan: N %d nnz %d units %d nnz_neg %d nnz_pos %d merged_slices %d bytes/stage %.3e "
+        "(finish %.0f s, all %.0f s)" % (ntot, info.nnz_graph, info.nunits, info.nnz_neg, info.nnz_pos,
+                                         info.merged_slices, info.bytes_per_stage, time.time() - tb, time.time() - t0))
     th0 = np.concatenate(th_parts)
     del th_parts
     every = 0 if args.no_timing else max(1, args.timing_every)

@@ -2181,9 +2181,10 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
     }
     // S-pos slices stored merged (SF_MERGED, FP32 plans with P = 1): those
     // whose partners are dense enough that 64 consecutive ones of the sorted
-    // stream lie within a few cache lines (on average at most MERGE_SPAN nodes
-    // apart), and long enough that the padding to 256 entries is small
-    constexpr int64_t MERGE_MIN = 256, MERGE_SPAN = 8;
+    // stream share cache lines (on average at most MERGE_SPAN nodes apart:
+    // 64 4-byte theta values within 64 lines of 128 bytes, mostly far fewer),
+    // and long enough that the padding to 256 entries is small
+    constexpr int64_t MERGE_MIN = 256, MERGE_SPAN = 32;
     std::vector<int64_t> sl_first(nseg + 1, 0);
     for (int32_t c = 0; c < nseg; c++) sl_first[c + 1] = sl_first[c] + (sb[c + 1] - sb[c] + SLICE - 1) / SLICE;
     std::vector<int64_t> mcount;   // merged S-pos entries per slice, 0 = one row per lane
