@@ -2194,7 +2194,7 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
         for (int64_t k = 0; k < sl_first[nseg]; k++) {
             const int32_t c = (int32_t)(std::upper_bound(sl_first.begin(), sl_first.end(), k) - sl_first.begin()) - 1;
             const int64_t r = sb[c] + (k - sl_first[c]) * SLICE, rows = std::min<int64_t>(SLICE, sb[c + 1] - r);
-            int64_t tot = 0;
+            int64_t tot = 0, longest = 0;
             int32_t lo = INT32_MAX, hi = -1;
             for (int64_t l = 0; l < rows; l++) {
                 const int64_t o = oldpos[r + l];
@@ -2204,8 +2204,11 @@ static cia_status build_sell(int64_t n, const std::vector<int32_t> &comm_off, in
                     hi = std::max(hi, pn);
                 }
                 tot += len(1, o);
+                longest = std::max(longest, len(1, o));
             }
-            if (tot >= MERGE_MIN && (int64_t)hi - lo + 1 <= MERGE_SPAN * tot) mcount[k] = tot;
+            // a row's fixed-point sum holds at most 2^23 entries of magnitude <= 2^40
+            if (tot >= MERGE_MIN && longest < ((int64_t)1 << 23) && (int64_t)hi - lo + 1 <= MERGE_SPAN * tot)
+                mcount[k] = tot;
         }
     }
     // slices and their widths
@@ -2863,7 +2866,10 @@ cia_status phase_build(cia_plan *p, const cia_graph *g, const int32_t *labels, c
                 S[3].val = xval.data();
                 S[3].pair = true;
             }
-            const bool merge_pos = !f64 && !s->poly && !s->tri && !gen && s->P == 1;
+            // merged S-pos slices: FP32, p = 1, and not for single networks small
+            // enough for the resident integrator, whose kernel reads one row per lane
+            const bool merge_pos = !f64 && !s->poly && !s->tri && !gen && s->P == 1 &&
+                                   (pre || (o->flags & CIA_FLAG_NO_RESIDENT) || nnz_neg + nnz_pos > RES_MAX_REMAINDER);
             CIA_TRY(build_sell(n, p1.comm_off, p1.ncomm, comm_staged, S, (uint32_t)zbytes, sell, cap, merge_pos));
             s->tile_cap = (int32_t)cap;
             if (s->d0 != 0.0) {

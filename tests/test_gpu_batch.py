@@ -272,8 +272,9 @@ def test_ensemble_256_instances_full_size(env):
     info = plan.info()
     off = plan.offsets
     say("full-size ensemble: N", off[-1], "nnz", info.nnz_graph, "units", info.nunits, "nnz_neg", info.nnz_neg,
-        "nnz_pos", info.nnz_pos, "build %.0f s" % (time.time() - t0))
+        "nnz_pos", info.nnz_pos, "merged slices", info.merged_slices, "build %.0f s" % (time.time() - t0))
     assert len(off) == count + 1 and off[-1] > 5e6 and info.nnz_graph == nnz
+    assert info.merged_slices > 0   # the dense instances' S-pos takes the partner-sorted path
     th = torch.as_tensor(np.concatenate(th_parts), device="cuda")
     del th_parts
     out = torch.empty_like(th)
