@@ -31,19 +31,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(workload):
-    """HBM bytes per stage-kernel launch from the committed rocprofv3 counter
+def profiled_traffic(workload, summary="phase_stage_kernel_kuramoto_n1e6.md"):
+    """HBM bytes per stage-kernel launch from a committed rocprofv3 counter
     summary, valid only for the workload it was measured on and while the
     kernel sources are the ones profiled."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "phase_stage_kernel_kuramoto_n1e6.md")
+    prof = os.path.join(ROOT, "profiles", summary)
     srcs = [os.path.join(ROOT, "paper_2203_16657_amd", "csrc", f) for f in ("cia_phase.hip", "plan.h", "fastmath.h", "wave.h")]
     try:
         text = open(prof).read()
         h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
     except OSError:
         return None
-    keys = ("traffic_bytes", "source_sha", "workload")
+    keys = ("traffic_bytes_per_launch: ", "source_sha256: ", "workload: ")
     vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(keys))
     if vals.get("source_sha256", "").strip() != h or vals.get("workload", "").strip() != workload:
         return None
@@ -476,7 +476,10 @@ def bench_ensemble(args, cia, W, torch, np):
     if stage_avg_ms:
         achieved = info.bytes_per_stage / (stage_avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "phase_stage_kernel",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic("ensemble_256" if args.ensemble_nmax == 2e5 else "other",
+                                            "ensemble_batched_256.md"),
+                "kernel": "phase_stage_kernel",
                 "avg_launch_us": round(stage_avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": info.bytes_per_stage, "timed_launches": tim.stage_launches}
         log("ensemble stage kernel avg %.2f us, %.1f GB/s algorithmic (%.1f%% of 8 TB/s)" % (
