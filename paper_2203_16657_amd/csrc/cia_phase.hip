@@ -536,6 +536,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
     constexpr bool MG = MERGE && sizeof(R) == 4 && P == 1 && !DIRECT && !TRI && !GEN;
     constexpr int UL = P >= 4 ? 2 : 8 / P;  // chunks per batch, LDS-gathered rows
     constexpr int UG = P >= 2 ? 1 : 2;      // chunks per batch, global-gathered rows (two in flight)
+    constexpr int UM = 4;                   // chunks per batch of a merged S-pos slice (16 gathers per lane)
     extern __shared__ __align__(16) unsigned char smem[];
     cx<R> *zsh = reinterpret_cast<cx<R> *>(smem);   // [lds_cap + 1]
     __shared__ double2 qsh[P];
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(BLOCK) void phase_stage_kernel(PhaseArgs<R> a) {
             }
             if constexpr (MG) {
                 if (merged)
-                    merged_pos_sum<UG>(T[0], a.posdata + S.beg[1] + lane, S.w[1], a.th_in, a.pad_pos, macc[wid]);
+                    merged_pos_sum<UM>(T[0], a.posdata + S.beg[1] + lane, S.w[1], a.th_in, a.pad_pos, macc[wid]);
             }
         }
         cx<R> Mt = {(R)0, (R)0}, Xt = {(R)0, (R)0};   // missing intra / cross hyperedge pair sums
