@@ -219,6 +219,36 @@ def test_rhs_merged_pos_slices(env, unit_work, block):
     assert circ.max() < 1e-3
 
 
+@pytest.mark.parametrize("flags", [0x100, 0x400, 0x20])
+def test_rhs_merged_pos_slices_kernel_paths(env, flags):
+    """Merged S-pos slices beside the other kernel paths: FP64-wide
+    observables (the tiled/wide instantiation), no LDS staging (S-neg
+    gathered from global memory), and units re-cut by the autotuner."""
+    rng = np.random.default_rng(37)
+    sizes = [1500, 900, 410, 65]
+    n = sum(sizes) + 77
+    labels = W.shuffled_labels(sizes, n, rng)
+    g = W.sbm(labels, len(sizes), 0.75, p_out=0.05, seed=37)
+    theta = rng.uniform(0.0, 2 * np.pi, n)
+    cia, torch = env
+    plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, None, K=2.0, flags=flags)
+    try:
+        th = torch.as_tensor(theta, dtype=torch.float32, device="cuda")
+        out = torch.empty_like(th)
+        plan.rhs(th, out)
+        torch.cuda.synchronize()
+        info = plan.info()
+    finally:
+        plan.close()
+    got = out.cpu().numpy().astype(np.float64)
+    th_used = th.cpu().numpy().astype(np.float64)
+    want = oracle.phase_rhs(g.n, g.row_ptr, g.col, None, 2.0, [0, 1], [0, 0], th_used)
+    err = rel_inf(got, want)
+    say("merged S-pos, flags %#x: slices merged" % flags, info.merged_slices, "units", info.nunits, "rel_inf", err)
+    assert info.merged_slices > 0
+    assert err <= TOL32
+
+
 def test_deterministic_bits(env):
     cia, torch = env
     P = W.random_phase_problem(5000, 6, seed=9, p=2)
