@@ -249,6 +249,35 @@ def test_rhs_merged_pos_slices_kernel_paths(env, flags):
     assert err <= TOL32
 
 
+def test_merged_pos_slices_graph_replay_bitwise(env):
+    """A plan with merged S-pos slices integrated by replaying its captured
+    RK4 step graph gives the bits of plain launches, over three calls with
+    host work and synchronisation between them."""
+    cia, torch = env
+    rng = np.random.default_rng(41)
+    sizes = [1200, 700, 300]
+    n = sum(sizes) + 45
+    labels = W.shuffled_labels(sizes, n, rng)
+    g = W.sbm(labels, len(sizes), 0.8, p_out=0.05, seed=41)
+    omega = rng.standard_normal(n)
+    theta = rng.uniform(0.0, 2 * np.pi, n).astype(np.float32)
+    runs = []
+    for flags in (0, 0x8):
+        plan = cia.Plan.phase(g.n, g.row_ptr, g.col, g.labels, omega, K=2.0, flags=flags)
+        assert plan.info().merged_slices > 0
+        th = torch.as_tensor(theta, device="cuda")
+        got = []
+        for steps in (10, 15, 10):
+            r = np.zeros(steps + 1)
+            plan.integrate(th, 0.01, steps, r)
+            torch.cuda.synchronize()
+            got.append((th.cpu().numpy().copy(), r))
+        plan.close()
+        runs.append(got)
+    for (a, ra), (b, rb) in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b) and np.array_equal(ra, rb)
+
+
 def test_deterministic_bits(env):
     cia, torch = env
     P = W.random_phase_problem(5000, 6, seed=9, p=2)
